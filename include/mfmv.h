@@ -1,0 +1,167 @@
+/*
+ * mfmv.h - matrix-free finite-element matrix-multivector products on MI355X.
+ *
+ * C ABI of libmfmv.so.  The library evaluates Y = A X for the operator
+ *
+ *     A = mu K + M_{V + sigma}
+ *
+ * on a structured hexahedral mesh, where K is the stiffness matrix and M_kappa
+ * the kappa-weighted mass matrix of the paper's model problem (Sec. 2.1,
+ * eq. refprob and eq. integrals), discretised with tensor-product Lagrange
+ * elements of degree p on Gauss-Lobatto-Legendre nodes (eq. NTensor) and a
+ * q-point Gauss rule per direction (eq. quadTensor).  X and Y are multivectors
+ * of nvec columns.  The product is evaluated matrix-free by sum factorisation
+ * (Sec. 2.2.2, Alg. 1 and Alg. 2, eq. helmholtz), with cell extraction and
+ * assembly through the cell-to-node map (Sec. 3.2.3, eq. AU) fused into one
+ * GPU launch over (cell, vector-tile) pairs (Sec. 3.1.2, eq. basempigpu).
+ *
+ * Conventions shared by every entry point:
+ *  - Status: MF_OK (0) on success, a negative mf_status otherwise; after an
+ *    error mf_last_error() returns a message (thread-local, valid until the
+ *    next call on the same thread).
+ *  - Node numbering ("full numbering"): nodes of the box, x fastest:
+ *    node (gx, gy, gz) -> gx + Nx*(gy + Ny*gz), with N_d = n_d*p + 1, or
+ *    N_d = n_d*p on a periodic mesh (nodes identified modulo N_d).  Zero
+ *    Dirichlet nodes keep their numbers; they are constrained rows.
+ *  - Cells are numbered x fastest; inside a cell, nodes and quadrature points
+ *    are numbered with the first reference direction fastest (Sec. 3.2.3).
+ *  - Multivector layout: dof-major, the nvec values of one node contiguous
+ *    (the BCV layout of Sec. 3.2.1 with one batch of all columns):
+ *    entry (node i, column j) is at X[i*ldx + j], ldx >= nvec.
+ *  - Device pointers are hipMalloc'd memory of the device that was current
+ *    when the operator was created; that device must be current at the call.
+ *  - Streams are passed as `void*` holding a hipStream_t (NULL = the null
+ *    stream).  Device entry points are stream-ordered and asynchronous: they
+ *    enqueue work and return without synchronising, and allocate nothing.
+ */
+#ifndef MFMV_H
+#define MFMV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MF_OK = 0,
+    MF_ERR_ARG = -1,          /* null pointer, bad size, aliasing, bad mesh */
+    MF_ERR_UNSUPPORTED = -2,  /* degree / quadrature / precision not built */
+    MF_ERR_OOM = -3,          /* device or host allocation failed */
+    MF_ERR_HIP = -4           /* a HIP runtime call failed (message has hipGetErrorString) */
+} mf_status;
+
+typedef enum {
+    MF_BC_NONE = 0,           /* natural boundary: no constrained nodes */
+    MF_BC_DIRICHLET0 = 1,     /* zero Dirichlet on every boundary node */
+    MF_BC_PERIODIC = 2        /* periodic in all three directions */
+} mf_bc;
+
+typedef enum {
+    MF_FP64 = 0,              /* all arithmetic in FP64 */
+    MF_FP32_MFMA = 1,         /* contractions in FP32, FP64 assembly */
+    MF_BF16_MFMA = 2          /* contractions with BF16 operands, FP32 accumulation, FP64 assembly */
+} mf_precision;
+
+/* Structured hexahedral box mesh: n[d] cells per direction on [lo, hi], then
+ * the optional linear map x = lin * y (row-major 3x3) applied to every box
+ * point y.  All-zero `lin` means the identity.  With a map the cells are
+ * parallelepipeds and each cell Jacobian is a full 3x3 matrix; det(lin) must
+ * be positive. */
+typedef struct {
+    int32_t n[3];
+    double lo[3];
+    double hi[3];
+    int32_t bc;               /* mf_bc */
+    double lin[9];
+} mf_box_mesh;
+
+typedef struct mf_operator mf_operator;
+
+/* ---------------------------------------------------------------- host ---- */
+
+/* Number of nodes of the full numbering (constrained nodes included) of a
+ * degree-p mesh.  Errors: MF_ERR_ARG for a null pointer or invalid mesh,
+ * MF_ERR_UNSUPPORTED for p outside [1, 10]. */
+int mf_num_dofs(const mf_box_mesh* mesh, int p, int64_t* ndofs);
+
+/* Number of cells, n[0]*n[1]*n[2]. */
+int mf_num_cells(const mf_box_mesh* mesh, int64_t* ncells);
+
+/* Physical coordinates of the q^3 Gauss points of every cell (host memory,
+ * caller-owned, E*q^3*3 doubles, cell-major, first direction fastest, xyz
+ * innermost).  Used to tabulate V at the points the operator integrates with
+ * (eq. mjacobian: kappa is needed at every quadrature point of every cell). */
+int mf_quad_points(const mf_box_mesh* mesh, int q, double* xq);
+
+/* 1 for constrained (zero-Dirichlet) nodes, 0 otherwise; host, ndofs bytes. */
+int mf_constrained_mask(const mf_box_mesh* mesh, int p, uint8_t* mask);
+
+/* The 1D tables of the sum factorisation, unfolded (host, caller-owned):
+ *   xq[q], wq[q]   Gauss points and weights on [-1, 1];
+ *   xn[p+1]        GLL nodes;
+ *   N[q*(p+1)]     N1D(a, i) = L_i(xq_a), row-major (quadrature point major);
+ *   D[q*(p+1)]     D1D(a, i) = L_i'(xq_a);
+ *   Dt[q*q]        the collocation derivative at the Gauss points,
+ *                  Dt(a, b) = l_b'(xq_a) with l_b the Lagrange basis on the
+ *                  Gauss points, so that D1D = Dt * N1D (eq. DU).
+ * Any output pointer may be NULL.  Requires q >= p+1 (see mf_create_operator). */
+int mf_basis_1d(int p, int q, double* xq, double* wq, double* xn, double* N, double* D, double* Dt);
+
+/* -------------------------------------------------------------- device ---- */
+
+/* Build the operator A = mu K + M_{V+sigma} for degree p, q Gauss points.
+ *   Vq:    host array of E*q^3 values V(x_Q) at the points given by
+ *          mf_quad_points (same order); NULL means V = 0.
+ *   sigma: constant added to V (the shift of the solve "(A + sigma M) X = B").
+ * Precomputes on the host (Sec. 3.2, Alg. 4 data): the cell-to-node map with
+ * constrained nodes marked, the per-cell 3x3 factor mu det(J) J^-1 J^-T
+ * (eq. sjacobian), the per-point factor det(J) (V + sigma) (eq. mjacobian), and
+ * the weight-folded 1D matrices (Sec. 3.2.4); copies them to the current device
+ * once (synchronously).  The operator owns these device copies.
+ * Errors: MF_ERR_ARG (null pointer, invalid mesh, non-finite input),
+ * MF_ERR_UNSUPPORTED (p outside [1, 10]; q outside [p+1, p+3] - the
+ * collocation factorisation D1D = Dt N1D of eq. DU is exact only for q >= p+1),
+ * MF_ERR_OOM, MF_ERR_HIP. */
+int mf_create_operator(const mf_box_mesh* mesh, int p, int q, double mu, const double* Vq,
+                       double sigma, mf_operator** out);
+
+/* Release the operator's device memory.  NULL is ignored.  Work already
+ * enqueued that uses the operator must have completed. */
+void mf_destroy_operator(mf_operator* op);
+
+/* Sizes of an operator (any output pointer may be NULL). */
+int mf_operator_info(const mf_operator* op, int64_t* ndofs, int64_t* ncells, int* p, int* q);
+
+/* Y := A X (overwrite, never accumulate), eq. AU with one partition.
+ *   X: device, ndofs rows, row stride ldx >= nvec; constrained rows are
+ *      ignored (read as zero: the action of C, Sec. 3.2.2).
+ *   Y: device, ndofs rows, row stride ldy >= nvec; constrained rows are
+ *      written as zero (the action of C^T).  Y must not overlap X.
+ *   prec: MF_FP64 evaluates every step in FP64 (FP64 atomic assembly).
+ *         MF_FP32_MFMA / MF_BF16_MFMA: see mf_precision.
+ * Stream-ordered on `stream`; allocates nothing, does not synchronise.
+ * Errors: MF_ERR_ARG (null, nvec < 1, ld < nvec, overlap), MF_ERR_UNSUPPORTED
+ * (precision not available for this p, q), MF_ERR_HIP (launch failure). */
+int mf_apply(mf_operator* op, const double* X, double* Y, int nvec, int64_t ldx, int64_t ldy,
+             int prec, void* stream);
+
+/* Y += A X: the accumulating form of mf_apply (same arguments and errors).
+ * Constrained rows of Y are left unchanged.  mf_apply is mf_zero on Y followed
+ * by this call. */
+int mf_apply_add(mf_operator* op, const double* X, double* Y, int nvec, int64_t ldx, int64_t ldy,
+                 int prec, void* stream);
+
+/* Y[i*ld + j] := 0 for i < nrows, j < ncols (device, stream-ordered; a
+ * kernel, not a memset, so it can be captured in a graph).
+ * Errors: MF_ERR_ARG (NULL, nrows < 0, ncols < 1, ld < ncols), MF_ERR_HIP. */
+int mf_zero(double* Y, int64_t nrows, int ncols, int64_t ld, void* stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char* mf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFMV_H */

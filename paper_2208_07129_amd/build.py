@@ -1,0 +1,88 @@
+"""Build libmfmv.so in-tree with hipcc for gfx950.
+
+    python -m paper_2208_07129_amd.build [-j N]
+
+Objects go to ``_build/`` at the repository root; the shared library is
+written next to this file.  Every HIP source is compiled with the packed-FP32
+VALU forms switched off, and FP64 atomics compile to the hardware add.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+OUT = os.path.join(PKG, "libmfmv.so")
+BUILD = os.path.join(ROOT, "_build")
+ARCH = "gfx950"
+MAX_P = 10
+
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics",
+          f"-I{os.path.join(ROOT, 'include')}"]
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def jobs():
+    """(source, object, extra flags) for every translation unit."""
+    out = [
+        ("capi.cpp", "capi.o", []),
+        ("host_setup.cpp", "host_setup.o", []),
+        ("dispatch.hip", "dispatch.o", []),
+    ]
+    for p in range(1, MAX_P + 1):
+        out.append(("apply_f64.hip", f"apply_f64_p{p}.o", [f"-DMF_P={p}"]))
+    return out
+
+
+def _compile(cc, src, obj, extra):
+    cmd = [cc, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, obj)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build(nproc: int | None = None, verbose: bool = False) -> str:
+    cc = hipcc()
+    os.makedirs(BUILD, exist_ok=True)
+    nproc = nproc or min(8, os.cpu_count() or 4)
+    objs = []
+    with cf.ThreadPoolExecutor(max_workers=nproc) as ex:
+        futs = [ex.submit(_compile, cc, s, o, e) for s, o, e in jobs()]
+        for f in futs:
+            objs.append(f.result())
+            if verbose:
+                print("compiled", objs[-1], flush=True)
+    tmp = OUT + ".tmp"
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
+           *[os.path.join(BUILD, o) for o in objs]]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, OUT)
+    return OUT
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("-v", action="store_true")
+    a = ap.parse_args(argv)
+    print(build(a.j, a.v))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,320 @@
+// C ABI of libmfmv: argument checking, operator setup and kernel dispatch.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "mf_internal.h"
+
+namespace mf {
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int hip_fail(hipError_t err, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(err);
+  return MF_ERR_HIP;
+}
+
+static int check_degree(int p) {
+  if (p < 1 || p > kMaxP) return fail(MF_ERR_UNSUPPORTED, "p must be in [1, 10]");
+  return MF_OK;
+}
+
+static int check_pq(int p, int q) {
+  if (int s = check_degree(p)) return s;
+  if (q < p + 1 || q > p + kMaxQExtra)
+    return fail(MF_ERR_UNSUPPORTED,
+                "q must be in [p+1, p+3]: the collocation factorisation needs q >= p+1");
+  return MF_OK;
+}
+
+}  // namespace mf
+
+using namespace mf;
+
+extern "C" {
+
+const char* mf_last_error(void) { return g_last_error.c_str(); }
+
+int mf_num_cells(const mf_box_mesh* mesh, int64_t* ncells) {
+  if (int s = validate_mesh(mesh)) return s;
+  if (!ncells) return fail(MF_ERR_ARG, "ncells is NULL");
+  *ncells = (int64_t)mesh->n[0] * mesh->n[1] * mesh->n[2];
+  return MF_OK;
+}
+
+int mf_num_dofs(const mf_box_mesh* mesh, int p, int64_t* ndofs) {
+  if (int s = validate_mesh(mesh)) return s;
+  if (int s = check_degree(p)) return s;
+  if (!ndofs) return fail(MF_ERR_ARG, "ndofs is NULL");
+  *ndofs = nodes_per_dir(*mesh, p, 0) * nodes_per_dir(*mesh, p, 1) * nodes_per_dir(*mesh, p, 2);
+  return MF_OK;
+}
+
+int mf_constrained_mask(const mf_box_mesh* mesh, int p, uint8_t* mask) {
+  int64_t nd;
+  if (int s = mf_num_dofs(mesh, p, &nd)) return s;
+  if (!mask) return fail(MF_ERR_ARG, "mask is NULL");
+  const int64_t Nx = nodes_per_dir(*mesh, p, 0), Ny = nodes_per_dir(*mesh, p, 1),
+                Nz = nodes_per_dir(*mesh, p, 2);
+  const bool dir = mesh->bc == MF_BC_DIRICHLET0;
+  for (int64_t gz = 0; gz < Nz; ++gz)
+    for (int64_t gy = 0; gy < Ny; ++gy)
+      for (int64_t gx = 0; gx < Nx; ++gx) {
+        const bool b = gx == 0 || gx == Nx - 1 || gy == 0 || gy == Ny - 1 || gz == 0 || gz == Nz - 1;
+        mask[gx + Nx * (gy + Ny * gz)] = (dir && b) ? 1 : 0;
+      }
+  return MF_OK;
+}
+
+int mf_quad_points(const mf_box_mesh* mesh, int q, double* xq) {
+  if (int s = validate_mesh(mesh)) return s;
+  if (q < 1 || q > kMaxP + 1 + kMaxQExtra) return fail(MF_ERR_UNSUPPORTED, "q out of range");
+  if (!xq) return fail(MF_ERR_ARG, "xq is NULL");
+  Rule1D g = gauss_rule(q);
+  double L[9];
+  lin_matrix(*mesh, L);
+  double h[3];
+  for (int d = 0; d < 3; ++d) h[d] = (mesh->hi[d] - mesh->lo[d]) / mesh->n[d];
+  int64_t idx = 0;
+  for (int cz = 0; cz < mesh->n[2]; ++cz)
+    for (int cy = 0; cy < mesh->n[1]; ++cy)
+      for (int cx = 0; cx < mesh->n[0]; ++cx)
+        for (int a3 = 0; a3 < q; ++a3)
+          for (int a2 = 0; a2 < q; ++a2)
+            for (int a1 = 0; a1 < q; ++a1) {
+              const double y[3] = {mesh->lo[0] + h[0] * (cx + 0.5 * (g.x[a1] + 1.0)),
+                                   mesh->lo[1] + h[1] * (cy + 0.5 * (g.x[a2] + 1.0)),
+                                   mesh->lo[2] + h[2] * (cz + 0.5 * (g.x[a3] + 1.0))};
+              for (int r = 0; r < 3; ++r)
+                xq[idx * 3 + r] = L[3 * r] * y[0] + L[3 * r + 1] * y[1] + L[3 * r + 2] * y[2];
+              ++idx;
+            }
+  return MF_OK;
+}
+
+int mf_basis_1d(int p, int q, double* xq, double* wq, double* xn, double* N, double* D, double* Dt) {
+  if (int s = check_pq(p, q)) return s;
+  Tables1D t = make_tables(p, q);
+  auto put = [](double* dst, const std::vector<double>& v) {
+    if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(double));
+  };
+  put(xq, t.xq);
+  put(wq, t.wq);
+  put(xn, t.xn);
+  put(N, t.N);
+  put(D, t.D);
+  put(Dt, t.Dt);
+  return MF_OK;
+}
+
+int mf_create_operator(const mf_box_mesh* mesh, int p, int q, double mu, const double* Vq,
+                       double sigma, mf_operator** out) {
+  if (!out) return fail(MF_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (int s = validate_mesh(mesh)) return s;
+  if (int s = check_pq(p, q)) return s;
+  if (!std::isfinite(mu) || !std::isfinite(sigma)) return fail(MF_ERR_ARG, "mu and sigma must be finite");
+  if (!apply_f64_supported(p, q)) return fail(MF_ERR_UNSUPPORTED, "no kernel built for this (p, q)");
+
+  Operator* op = new (std::nothrow) Operator();
+  if (!op) return fail(MF_ERR_OOM, "host allocation failed");
+  op->p = p;
+  op->q = q;
+  op->np = p + 1;
+  op->nq = q;
+  op->mu = mu;
+  op->sigma = sigma;
+  op->t = make_tables(p, q);
+  const int np = op->np, nq = op->nq, np3 = np * np * np, nq3 = nq * nq * nq;
+  const int64_t Nx = nodes_per_dir(*mesh, p, 0), Ny = nodes_per_dir(*mesh, p, 1),
+                Nz = nodes_per_dir(*mesh, p, 2);
+  op->ndofs = Nx * Ny * Nz;
+  op->ncells = (int64_t)mesh->n[0] * mesh->n[1] * mesh->n[2];
+  if (op->ndofs >= (int64_t)1 << 31) {
+    delete op;
+    return fail(MF_ERR_UNSUPPORTED, "more than 2^31-1 nodes");
+  }
+  const int64_t E = op->ncells;
+
+  // Cell-to-node map (extraction Q of Sec. 3.2.3) with zero-Dirichlet nodes
+  // marked -1: reading them as zero and skipping them on assembly is the
+  // action of C and C^T for constraints with empty masters (Sec. 3.2.2).
+  std::vector<int32_t> map(E * np3);
+  std::vector<uint8_t> mask(op->ndofs);
+  mf_constrained_mask(mesh, p, mask.data());
+  const bool per = mesh->bc == MF_BC_PERIODIC;
+  for (int64_t e = 0; e < E; ++e) {
+    const int64_t cx = e % mesh->n[0], cy = (e / mesh->n[0]) % mesh->n[1],
+                  cz = e / ((int64_t)mesh->n[0] * mesh->n[1]);
+    for (int i3 = 0; i3 < np; ++i3)
+      for (int i2 = 0; i2 < np; ++i2)
+        for (int i1 = 0; i1 < np; ++i1) {
+          int64_t gx = cx * p + i1, gy = cy * p + i2, gz = cz * p + i3;
+          if (per) {
+            gx %= Nx;
+            gy %= Ny;
+            gz %= Nz;
+          }
+          const int64_t g = gx + Nx * (gy + Ny * gz);
+          map[e * np3 + i1 + np * (i2 + np * i3)] = mask[g] ? -1 : (int32_t)g;
+        }
+  }
+
+  // Geometry (eq. sjacobian / eq. mjacobian): the cell map is affine, so J is
+  // constant per cell: J = lin * diag(h/2).
+  double L[9];
+  lin_matrix(*mesh, L);
+  double h[3];
+  for (int d = 0; d < 3; ++d) h[d] = (mesh->hi[d] - mesh->lo[d]) / mesh->n[d];
+  double J[9], Ji[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) J[3 * r + c] = L[3 * r + c] * 0.5 * h[c];
+  const double detJ = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                      J[2] * (J[3] * J[7] - J[4] * J[6]);
+  Ji[0] = (J[4] * J[8] - J[5] * J[7]) / detJ;
+  Ji[1] = (J[2] * J[7] - J[1] * J[8]) / detJ;
+  Ji[2] = (J[1] * J[5] - J[2] * J[4]) / detJ;
+  Ji[3] = (J[5] * J[6] - J[3] * J[8]) / detJ;
+  Ji[4] = (J[0] * J[8] - J[2] * J[6]) / detJ;
+  Ji[5] = (J[2] * J[3] - J[0] * J[5]) / detJ;
+  Ji[6] = (J[3] * J[7] - J[4] * J[6]) / detJ;
+  Ji[7] = (J[1] * J[6] - J[0] * J[7]) / detJ;
+  Ji[8] = (J[0] * J[4] - J[1] * J[3]) / detJ;
+  double G[9];  // mu det J J^-1 J^-T
+  for (int s = 0; s < 3; ++s)
+    for (int d = 0; d < 3; ++d) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += Ji[3 * s + k] * Ji[3 * d + k];
+      G[3 * s + d] = mu * detJ * acc;
+    }
+  std::vector<double> geo(E * 6);
+  for (int64_t e = 0; e < E; ++e) {
+    double* g = &geo[e * 6];
+    g[0] = G[0];
+    g[1] = G[1];
+    g[2] = G[2];
+    g[3] = G[4];
+    g[4] = G[5];
+    g[5] = G[8];
+  }
+  std::vector<double> vq(E * nq3);
+  for (int64_t k = 0; k < E * nq3; ++k) {
+    const double v = Vq ? Vq[k] : 0.0;
+    if (!std::isfinite(v)) {
+      delete op;
+      return fail(MF_ERR_ARG, "Vq holds a non-finite value");
+    }
+    vq[k] = detJ * (v + sigma);
+  }
+
+  hipError_t err = hipGetDevice(&op->device);
+  if (err != hipSuccess) {
+    delete op;
+    return hip_fail(err, "hipGetDevice");
+  }
+  auto alloc_copy = [&](void** dst, const void* src, size_t bytes) -> int {
+    hipError_t e2 = hipMalloc(dst, bytes);
+    if (e2 != hipSuccess) {
+      *dst = nullptr;
+      return e2 == hipErrorOutOfMemory ? fail(MF_ERR_OOM, "hipMalloc failed") : hip_fail(e2, "hipMalloc");
+    }
+    e2 = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    if (e2 != hipSuccess) return hip_fail(e2, "hipMemcpy");
+    return MF_OK;
+  };
+  int s = alloc_copy((void**)&op->d_map, map.data(), map.size() * sizeof(int32_t));
+  if (!s) s = alloc_copy((void**)&op->d_geo, geo.data(), geo.size() * sizeof(double));
+  if (!s) s = alloc_copy((void**)&op->d_vq, vq.data(), vq.size() * sizeof(double));
+  if (s) {
+    mf_destroy_operator(reinterpret_cast<mf_operator*>(op));
+    return s;
+  }
+  *out = reinterpret_cast<mf_operator*>(op);
+  return MF_OK;
+}
+
+void mf_destroy_operator(mf_operator* handle) {
+  if (!handle) return;
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  if (op->d_map) (void)hipFree(op->d_map);
+  if (op->d_geo) (void)hipFree(op->d_geo);
+  if (op->d_vq) (void)hipFree(op->d_vq);
+  delete op;
+}
+
+int mf_operator_info(const mf_operator* handle, int64_t* ndofs, int64_t* ncells, int* p, int* q) {
+  if (!handle) return fail(MF_ERR_ARG, "operator is NULL");
+  const Operator* op = reinterpret_cast<const Operator*>(handle);
+  if (ndofs) *ndofs = op->ndofs;
+  if (ncells) *ncells = op->ncells;
+  if (p) *p = op->p;
+  if (q) *q = op->q;
+  return MF_OK;
+}
+
+static bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const char* ca = static_cast<const char*>(a);
+  const char* cb = static_cast<const char*>(b);
+  return ca < cb + bbytes && cb < ca + abytes;
+}
+
+static int apply_common(mf_operator* handle, const double* X, double* Y, int nvec, int64_t ldx,
+                        int64_t ldy, int prec, void* stream, bool zero_first) {
+  if (!handle) return fail(MF_ERR_ARG, "operator is NULL");
+  if (!X || !Y) return fail(MF_ERR_ARG, "X and Y must be non-NULL device pointers");
+  if (nvec < 1) return fail(MF_ERR_ARG, "nvec must be >= 1");
+  if (ldx < nvec || ldy < nvec) return fail(MF_ERR_ARG, "ldx and ldy must be >= nvec");
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  const size_t xb = ((op->ndofs - 1) * ldx + nvec) * sizeof(double);
+  const size_t yb = ((op->ndofs - 1) * ldy + nvec) * sizeof(double);
+  if (overlaps(X, xb, Y, yb)) return fail(MF_ERR_ARG, "X and Y overlap");
+  if (prec != MF_FP64) return fail(MF_ERR_UNSUPPORTED, "precision not available");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  ApplyLaunch a{};
+  a.map = op->d_map;
+  a.geo = op->d_geo;
+  a.vq = op->d_vq;
+  a.X = X;
+  a.Y = Y;
+  a.ldx = ldx;
+  a.ldy = ldy;
+  a.ncells = op->ncells;
+  a.nvec = nvec;
+  a.threads = 256;
+  a.vtile = choose_vtile_f64(op->np, op->nq, nvec);
+  if (zero_first) {
+    hipError_t err = launch_zero_rows(Y, op->ndofs, nvec, ldy, s);
+    if (err != hipSuccess) return hip_fail(err, "zero kernel launch");
+  }
+  hipError_t err = launch_apply_f64(*op, a, s);
+  if (err != hipSuccess) return hip_fail(err, "apply kernel launch");
+  return MF_OK;
+}
+
+int mf_apply(mf_operator* handle, const double* X, double* Y, int nvec, int64_t ldx, int64_t ldy,
+             int prec, void* stream) {
+  return apply_common(handle, X, Y, nvec, ldx, ldy, prec, stream, true);
+}
+
+int mf_apply_add(mf_operator* handle, const double* X, double* Y, int nvec, int64_t ldx,
+                 int64_t ldy, int prec, void* stream) {
+  return apply_common(handle, X, Y, nvec, ldx, ldy, prec, stream, false);
+}
+
+int mf_zero(double* Y, int64_t nrows, int ncols, int64_t ld, void* stream) {
+  if (!Y) return fail(MF_ERR_ARG, "Y is NULL");
+  if (nrows < 0 || ncols < 1 || ld < ncols) return fail(MF_ERR_ARG, "need nrows >= 0, 1 <= ncols <= ld");
+  if (nrows == 0) return MF_OK;
+  hipError_t err = launch_zero_rows(Y, nrows, ncols, ld, static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "zero kernel launch");
+  return MF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal declarations shared by the host setup, the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mfmv.h"
+
+namespace mf {
+
+constexpr int kMaxP = 10;
+constexpr int kMaxQExtra = 3;  // q in [p+1, p+3]
+
+// Error reporting: every entry point returns a status and stores a message.
+int fail(int status, const std::string& msg);
+int hip_fail(hipError_t err, const char* what);
+
+// ---------------------------------------------------------------- host setup
+struct Rule1D {
+  std::vector<double> x, w;
+};
+Rule1D gauss_rule(int n);
+std::vector<double> gll_points(int p);
+
+// Unfolded 1D tables (row-major, quadrature point major).
+struct Tables1D {
+  int np = 0, nq = 0;
+  std::vector<double> xq, wq, xn;
+  std::vector<double> N;   // nq x np
+  std::vector<double> D;   // nq x np
+  std::vector<double> Dt;  // nq x nq
+  std::vector<double> Nf;  // folded: N(a,i) sqrt(w_a)
+  std::vector<double> Dtf; // folded: Dt(a,b) sqrt(w_a / w_b)
+};
+Tables1D make_tables(int p, int q);
+
+int validate_mesh(const mf_box_mesh* m);
+int64_t nodes_per_dir(const mf_box_mesh& m, int p, int d);
+void lin_matrix(const mf_box_mesh& m, double L[9]);
+
+// --------------------------------------------------------------- operator
+struct Operator {
+  int device = 0;
+  int p = 0, q = 0, np = 0, nq = 0;
+  int64_t ncells = 0, ndofs = 0;
+  double mu = 0.0, sigma = 0.0;
+  // device arrays
+  int32_t* d_map = nullptr;   // E x np^3, -1 = constrained
+  double* d_geo = nullptr;    // E x 6: mu det J (J^-1 J^-T), (00,01,02,11,12,22)
+  double* d_vq = nullptr;     // E x nq^3: det J (V + sigma)
+  Tables1D t;
+};
+
+// ----------------------------------------------------------------- kernels
+struct ApplyLaunch {
+  const int32_t* map;
+  const double* geo;
+  const double* vq;
+  const double* X;
+  double* Y;
+  int64_t ldx, ldy;
+  int64_t ncells;
+  int nvec;
+  int vtile;    // vectors per workgroup tile
+  int threads;  // workgroup size
+};
+
+// FP64 fused apply; returns hipSuccess or the launch error.
+hipError_t launch_apply_f64(const Operator& op, const ApplyLaunch& a, hipStream_t s);
+// Zero rows [0, nrows) x columns [0, ncols) of a row-major array with stride ld.
+hipError_t launch_zero_rows(double* Y, int64_t nrows, int ncols, int64_t ld, hipStream_t s);
+bool apply_f64_supported(int p, int q);
+// Vectors per workgroup tile of the FP64 kernel (256 threads, LDS within 64 KiB).
+int choose_vtile_f64(int np, int nq, int nvec);
+
+}  // namespace mf

@@ -1,0 +1,200 @@
+"""ctypes binding of libmfmv.so (argument marshalling only).
+
+Every step of the product runs in the library's HIP kernels.  PyTorch is used
+for device memory and streams: tensors are passed by ``data_ptr()`` and the
+stream by ``torch.cuda.current_stream().cuda_stream``.  There is no fallback:
+if the library is missing, or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmfmv.so")
+
+MF_OK, MF_ERR_ARG, MF_ERR_UNSUPPORTED, MF_ERR_OOM, MF_ERR_HIP = 0, -1, -2, -3, -4
+MF_BC_NONE, MF_BC_DIRICHLET0, MF_BC_PERIODIC = 0, 1, 2
+MF_FP64, MF_FP32_MFMA, MF_BF16_MFMA = 0, 1, 2
+PRECISIONS = {"fp64": MF_FP64, "fp32": MF_FP32_MFMA, "bf16": MF_BF16_MFMA}
+
+# Every symbol declared in include/mfmv.h.
+EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask", "mf_basis_1d",
+           "mf_create_operator", "mf_destroy_operator", "mf_operator_info", "mf_apply",
+           "mf_apply_add", "mf_zero", "mf_last_error")
+
+
+class MfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libmfmv status {status}: {msg}")
+        self.status = status
+
+
+class MeshC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("bc", ctypes.c_int32), ("lin", ctypes.c_double * 9)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2208_07129_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        MP = ctypes.POINTER(MeshC)
+        sig = {
+            "mf_num_dofs": (I, [MP, I, ctypes.POINTER(I64)]),
+            "mf_num_cells": (I, [MP, ctypes.POINTER(I64)]),
+            "mf_quad_points": (I, [MP, I, P]),
+            "mf_constrained_mask": (I, [MP, I, P]),
+            "mf_basis_1d": (I, [I, I, P, P, P, P, P, P]),
+            "mf_create_operator": (I, [MP, I, I, D, P, D, ctypes.POINTER(P)]),
+            "mf_destroy_operator": (None, [P]),
+            "mf_operator_info": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(I64),
+                                     ctypes.POINTER(I), ctypes.POINTER(I)]),
+            "mf_apply": (I, [P, P, P, I, I64, I64, I, P]),
+            "mf_apply_add": (I, [P, P, P, I, I64, I64, I, P]),
+            "mf_zero": (I, [P, I64, I, I64, P]),
+            "mf_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != MF_OK:
+        raise MfError(status, lib().mf_last_error().decode())
+
+
+def mesh_c(mesh) -> MeshC:
+    """Convert a workloads.BoxMesh (or any object with n, lo, hi, bc, lin) to the C struct."""
+    m = MeshC()
+    for d in range(3):
+        m.n[d] = int(mesh.n[d])
+        m.lo[d] = float(mesh.lo[d])
+        m.hi[d] = float(mesh.hi[d])
+    m.bc = int(mesh.bc)
+    lin = getattr(mesh, "lin", None)
+    if lin is not None:
+        flat = np.asarray(lin, dtype=np.float64).reshape(9)
+        for k in range(9):
+            m.lin[k] = float(flat[k])
+    return m
+
+
+def num_dofs(mesh, p: int) -> int:
+    out = ctypes.c_int64()
+    _check(lib().mf_num_dofs(ctypes.byref(mesh_c(mesh)), p, ctypes.byref(out)))
+    return out.value
+
+
+def num_cells(mesh) -> int:
+    out = ctypes.c_int64()
+    _check(lib().mf_num_cells(ctypes.byref(mesh_c(mesh)), ctypes.byref(out)))
+    return out.value
+
+
+def quad_points(mesh, q: int) -> np.ndarray:
+    E = num_cells(mesh)
+    xq = np.empty((E, q ** 3, 3), dtype=np.float64)
+    _check(lib().mf_quad_points(ctypes.byref(mesh_c(mesh)), q, xq.ctypes.data))
+    return xq
+
+
+def constrained_mask(mesh, p: int) -> np.ndarray:
+    m = np.empty(num_dofs(mesh, p), dtype=np.uint8)
+    _check(lib().mf_constrained_mask(ctypes.byref(mesh_c(mesh)), p, m.ctypes.data))
+    return m.astype(bool)
+
+
+def basis_1d(p: int, q: int) -> dict:
+    np1 = p + 1
+    out = {"xq": np.empty(q), "wq": np.empty(q), "xn": np.empty(np1), "N": np.empty((q, np1)),
+           "D": np.empty((q, np1)), "Dt": np.empty((q, q))}
+    _check(lib().mf_basis_1d(p, q, *(out[k].ctypes.data for k in ("xq", "wq", "xn", "N", "D", "Dt"))))
+    return out
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+class Operator:
+    """A = mu K + M_{V+sigma} on the current HIP device (owns its device data)."""
+
+    def __init__(self, mesh, p: int, q: int, mu: float = 0.5, Vq: Optional[np.ndarray] = None,
+                 sigma: float = 0.0):
+        self._h = ctypes.c_void_p()
+        self.mesh, self.p, self.q, self.mu, self.sigma = mesh, p, q, mu, sigma
+        vptr = None
+        if Vq is not None:
+            self._vq = np.ascontiguousarray(Vq, dtype=np.float64).reshape(-1)
+            if self._vq.size != num_cells(mesh) * q ** 3:
+                raise ValueError("Vq must hold E*q^3 values")
+            vptr = self._vq.ctypes.data
+        _check(lib().mf_create_operator(ctypes.byref(mesh_c(mesh)), p, q, float(mu), vptr,
+                                        float(sigma), ctypes.byref(self._h)))
+        nd, nc = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().mf_operator_info(self._h, ctypes.byref(nd), ctypes.byref(nc), None, None))
+        self.ndofs, self.ncells = nd.value, nc.value
+
+    @classmethod
+    def from_workload(cls, w):
+        """Build the operator of a workloads.Workload, tabulating V at the library's points."""
+        Vq = w.V(quad_points(w.mesh, w.q)) if w.V is not None else None
+        return cls(w.mesh, w.p, w.q, w.mu, Vq, w.sigma)
+
+    def close(self):
+        if self._h:
+            lib().mf_destroy_operator(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_ptr(self, X_ptr: int, Y_ptr: int, nvec: int, ldx: int, ldy: int,
+                  prec: int = MF_FP64, stream=None):
+        _check(lib().mf_apply(self._h, X_ptr, Y_ptr, nvec, ldx, ldy, prec, _stream_ptr(stream)))
+
+    def apply_add_ptr(self, X_ptr: int, Y_ptr: int, nvec: int, ldx: int, ldy: int,
+                      prec: int = MF_FP64, stream=None):
+        _check(lib().mf_apply_add(self._h, X_ptr, Y_ptr, nvec, ldx, ldy, prec, _stream_ptr(stream)))
+
+    def apply(self, X, Y=None, precision: str = "fp64", stream=None, accumulate: bool = False):
+        """Y := A X for torch float64 device tensors of shape (ndofs, nvec) (row stride >= nvec)."""
+        import torch
+        if X.dtype != torch.float64 or not X.is_cuda:
+            raise TypeError("X must be a float64 device tensor")
+        if X.dim() != 2 or X.shape[0] != self.ndofs or X.stride(1) != 1:
+            raise ValueError("X must be (ndofs, nvec) with unit column stride")
+        nvec = X.shape[1]
+        if Y is None:
+            Y = torch.empty_like(X, memory_format=torch.contiguous_format)
+        if Y.dtype != torch.float64 or Y.shape != X.shape or Y.stride(1) != 1:
+            raise ValueError("Y must match X")
+        fn = self.apply_add_ptr if accumulate else self.apply_ptr
+        fn(X.data_ptr(), Y.data_ptr(), nvec, X.stride(0), Y.stride(0), PRECISIONS[precision], stream)
+        return Y
+
+
+def zero_ptr(Y_ptr: int, nrows: int, ncols: int, ld: int, stream=None):
+    _check(lib().mf_zero(Y_ptr, nrows, ncols, ld, _stream_ptr(stream)))
