@@ -30,7 +30,8 @@ METRIC = "A·X GDoF·vec/s, FP64 vs mixed precision at ≤1e-6 rel err; %rooflin
 UNIT = "GDoF·vec/s"
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (= FP64 matrix) peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_f64_traffic.json")
-KERNEL_SOURCES = ["paper_2208_07129_amd/csrc/apply_f64.hip", "paper_2208_07129_amd/csrc/sf_common.h"]
+KERNEL_SOURCES = ["paper_2208_07129_amd/csrc/apply_box.hip", "paper_2208_07129_amd/csrc/sf_common.h",
+                  "paper_2208_07129_amd/csrc/sf_tables.h"]
 
 
 def flops_per_cell_vector(p: int, q: int) -> int:
@@ -124,6 +125,9 @@ def main(argv=None):
     ap.add_argument("--nvec", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-cells", type=int, default=512)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of X into Y (known bytes), for scaling "
+                         "the FETCH_SIZE / WRITE_SIZE counters")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU's partition only; --gpus {a.gpus} is not supported "
@@ -146,32 +150,36 @@ def main(argv=None):
     free = int(op.ndofs - mfmv.constrained_mask(w.mesh, w.p).sum())
     stream = torch.cuda.current_stream()
     sptr = stream.cuda_stream
+    if a.calibrate_copy:
+        for _ in range(a.steps):
+            Y.copy_(X)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": X.numel() * 8,
+                          "calibrate_copy_bytes_written": Y.numel() * 8, "steps": a.steps}))
+        return 0
 
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        mfmv.zero_ptr(Y.data_ptr(), op.ndofs, nvec, nvec, sptr)
-        if ev is not None:
-            ev[1].record(stream)
-        op.apply_add_ptr(X.data_ptr(), Y.data_ptr(), nvec, nvec, nvec, prec, sptr)
-        if ev is not None:
-            ev[2].record(stream)
+    def step():
+        op.apply_ptr(X.data_ptr(), Y.data_ptr(), nvec, nvec, nvec, prec, sptr)
 
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # untimed pass with the library's per-launch events: zero-fill and fused-kernel times
+    op.timing(a.steps)
+    for _ in range(a.steps):
+        step()
+    n_ev, zero_sum, kern_sum = op.timing_read()
+    op.timing(0)
+    kern_ms, zero_ms = kern_sum / n_ev, zero_sum / n_ev
     torch.cuda.synchronize()
     start.record(stream)
-    for k in range(a.steps):
-        step(evs[k])
+    for _ in range(a.steps):
+        step()
     end.record(stream)
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(end)
     ms_per_step = total_ms / a.steps
-    kern_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    zero_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     value = free * nvec / (ms_per_step * 1e-3) / 1e9
 
     flops = flops_per_cell_vector(w.p, w.q) * op.ncells * nvec

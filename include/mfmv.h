@@ -157,6 +157,27 @@ int mf_apply_add(mf_operator* op, const double* X, double* Y, int nvec, int64_t 
  * Errors: MF_ERR_ARG (NULL, nrows < 0, ncols < 1, ld < ncols), MF_ERR_HIP. */
 int mf_zero(double* Y, int64_t nrows, int ncols, int64_t ld, void* stream);
 
+/* Launch selection (used by the tuner and by tests):
+ *   general != 0 forces the general-geometry kernel (full 3x3 factor, three
+ *                LDS buffers) even on axis-aligned cells; it cannot be undone
+ *                on this operator.
+ *   cfg          launch shape of the axis-aligned-cell kernel, 0..3, or -1 for
+ *                the built-in choice by column count.
+ * Errors: MF_ERR_ARG (NULL, cfg out of range), MF_ERR_UNSUPPORTED (shape does
+ * not fit the LDS for this p, q). */
+int mf_set_launch(mf_operator* op, int general, int cfg);
+
+/* Per-launch timing for diagnostics and benchmarks.  mf_timing(op, slots)
+ * (slots > 0) makes every following mf_apply / mf_apply_add on this operator
+ * record HIP events on its stream around the zero fill and around the fused
+ * kernel, in a ring of `slots` entries; slots = 0 turns it off.  Not for use
+ * under graph capture.  mf_timing_read waits for the recorded events and
+ * returns the number of applies recorded since the last read and the summed
+ * milliseconds of the zero fill and of the fused kernel; it then clears the
+ * ring.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+int mf_timing(mf_operator* op, int slots);
+int mf_timing_read(mf_operator* op, int* count, double* zero_ms, double* kernel_ms);
+
 /* Message of the last error on this thread ("" if none). */
 const char* mf_last_error(void);
 

@@ -44,6 +44,7 @@ def jobs():
     ]
     for p in range(1, MAX_P + 1):
         out.append(("apply_f64.hip", f"apply_f64_p{p}.o", [f"-DMF_P={p}"]))
+        out.append(("apply_box.hip", f"apply_box_p{p}.o", [f"-DMF_P={p}"]))
     return out
 
 

@@ -1,0 +1,315 @@
+// FP64 fused apply for axis-aligned (box) cells.
+//
+// On a box cell the Jacobian is diagonal, so the 3x3 factor of eq. sjacobian is
+// diagonal: G = diag(g0, g1, g2) per cell.  The gradient part of Alg. 2 then
+// splits by direction, sum_s Dt_s^T g_s Dt_s T, and the two derivative stages
+// of direction s collapse into one symmetric contraction with
+// Lf = Dtf^T Dtf (weight-folded).  Per cell e and column:
+//   T   = (N x N x N) U_e                          (Alg. 1, eq. tc1-tc3)
+//   T  <- det J (V + sigma) o T + sum_s g_s Lf_s T  (eq. helmholtz, eq. mjacobian)
+//   V_e = (N x N x N)^T T;  Y += Q_e^T V_e         (Sec. 3.2.3)
+// Only two cell buffers live in LDS (the general kernel needs three), which
+// doubles the number of cell-columns resident per CU.
+//
+// Work item = (cell, tile of B columns); cells are taken in the order given by
+// `order` (XCD-blocked, Morton inside a block) so that cells sharing nodes run
+// close in time on the same XCD.  Inside a phase each thread owns R pencils
+// and issues all their LDS reads before computing (latency hiding).  Nodes
+// interior to the cell have exactly one contributor and are written with
+// plain stores; nodes on cell faces, edges and corners use FP64 atomics.
+#include "mf_internal.h"
+#include "sf_common.h"
+#include "sf_tables.h"
+
+#ifndef MF_P
+#error "compile with -DMF_P=<degree>"
+#endif
+
+namespace mf {
+namespace {
+
+// One phase: every (vector, pencil) task w in [0, TASKS), R rounds per thread.
+// load(w, in) fills the inputs, comp(w, in, out) computes, store(w, out) writes.
+template <int TASKS, int NT, int NIN, int NOUT, class Load, class Comp, class Store>
+__device__ __forceinline__ void phase(int tid, Load load, Comp comp, Store store) {
+  constexpr int R = (TASKS + NT - 1) / NT;
+  constexpr bool EXACT = TASKS % NT == 0;
+  double in[R][NIN];
+  double out[R][NOUT];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int w = tid + k * NT;
+    if (EXACT || k < R - 1 || w < TASKS) load(w, in[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) comp(tid + k * NT, in[k], out[k]);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int w = tid + k * NT;
+    if (EXACT || k < R - 1 || w < TASKS) store(w, out[k]);
+  }
+}
+
+template <int NP, int NQ, int B, int NT, bool ACCUM>
+__global__ void __launch_bounds__(NT)
+apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ order,
+                 const double* __restrict__ geo, const double* __restrict__ vq,
+                 const double* __restrict__ X, double* __restrict__ Y, int64_t ldx, int64_t ldy,
+                 int nvec, int ntiles, int64_t nitems, int64_t chunk) {
+  constexpr int NP2 = NP * NP, NP3 = NP * NP * NP, NQ2 = NQ * NQ, NQ3 = NQ * NQ * NQ;
+  using Nf = MatN<NP, NQ>;
+  using Lf = MatL<NP, NQ>;
+  extern __shared__ double lds[];
+  const int64_t item = xcd_item(blockIdx.x, chunk);
+  if (item >= nitems) return;
+  const int64_t e = order[item / ntiles];
+  const int v0 = (int)(item % ntiles) * B;
+
+  double* bA = lds;
+  double* bB = bA + NQ3 * B;
+  double* svq = bB + NQ3 * B;
+  int* smap = reinterpret_cast<int*>(svq + NQ3);
+  const int tid = threadIdx.x;
+
+  for (int i = tid; i < NP3; i += NT) smap[i] = cmap[e * NP3 + i];
+  for (int i = tid; i < NQ3; i += NT) svq[i] = vq[e * NQ3 + i];
+  const double g0 = geo[e * 6 + 0], g1 = geo[e * 6 + 3], g2 = geo[e * 6 + 5];
+  __syncthreads();
+
+  // P1: extraction fused with N along direction 0: (NP,NP,NP) -> A (NQ,NP,NP).
+  phase<NP2 * B, NT, NP, NQ>(
+      tid,
+      [&](int w, double (&r)[NP]) {
+        const int b = w % B, pen = w / B, v = v0 + b;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          const int node = smap[pen * NP + i];
+          r[i] = (node >= 0 && v < nvec) ? X[(int64_t)node * ldx + v] : 0.0;
+        }
+      },
+      [&](int, double (&r)[NP], double (&o)[NQ]) { matvec<Nf, NQ, NP, false, NP>(r, o); },
+      [&](int w, double (&o)[NQ]) {
+        const int b = w % B, pen = w / B;
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) bA[(pen * NQ + a) * B + b] = o[a];
+      });
+  __syncthreads();
+
+  // P2, P3: N along directions 1 and 2 -> T in A (NQ,NQ,NQ).
+  {
+    using PI = Pencils<1, NQ, NP, NP>;
+    using PO = Pencils<1, NQ, NQ, NP>;
+    phase<PI::COUNT * B, NT, NP, NQ>(
+        tid,
+        [&](int w, double (&r)[NP]) {
+          const int b = w % B, base = PI::base(w / B);
+#pragma unroll
+          for (int i = 0; i < NP; ++i) r[i] = bA[(base + i * PI::STRIDE) * B + b];
+        },
+        [&](int, double (&r)[NP], double (&o)[NQ]) { matvec<Nf, NQ, NP, false, NP>(r, o); },
+        [&](int w, double (&o)[NQ]) {
+          const int b = w % B, base = PO::base(w / B);
+#pragma unroll
+          for (int a = 0; a < NQ; ++a) bB[(base + a * PO::STRIDE) * B + b] = o[a];
+        });
+  }
+  __syncthreads();
+  {
+    using PI = Pencils<2, NQ, NQ, NP>;
+    phase<PI::COUNT * B, NT, NP, NQ>(
+        tid,
+        [&](int w, double (&r)[NP]) {
+          const int b = w % B, pen = w / B;
+#pragma unroll
+          for (int i = 0; i < NP; ++i) r[i] = bB[(pen + i * NQ2) * B + b];
+        },
+        [&](int, double (&r)[NP], double (&o)[NQ]) { matvec<Nf, NQ, NP, false, NP>(r, o); },
+        [&](int w, double (&o)[NQ]) {
+          const int b = w % B, pen = w / B;
+#pragma unroll
+          for (int a = 0; a < NQ; ++a) bA[(pen + a * NQ2) * B + b] = o[a];
+        });
+  }
+  __syncthreads();
+
+  // P4: B = g0 Lf_0 T (direction-0 pencils).
+  phase<NQ2 * B, NT, NQ, NQ>(
+      tid,
+      [&](int w, double (&t)[NQ]) {
+        const int b = w % B, pen = w / B;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) t[k] = bA[(pen * NQ + k) * B + b];
+      },
+      [&](int, double (&t)[NQ], double (&o)[NQ]) {
+        matvec<Lf, NQ, NQ, false, NQ>(t, o);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) o[k] *= g0;
+      },
+      [&](int w, double (&o)[NQ]) {
+        const int b = w % B, pen = w / B;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) bB[(pen * NQ + k) * B + b] = o[k];
+      });
+  __syncthreads();
+
+  // P5: B += g1 Lf_1 T (direction-1 pencils).
+  phase<NQ2 * B, NT, 2 * NQ, NQ>(
+      tid,
+      [&](int w, double (&t)[2 * NQ]) {
+        const int b = w % B, pen = w / B;
+        const int base = (pen / NQ) * NQ2 + (pen % NQ);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+          t[k] = bA[(base + k * NQ) * B + b];
+          t[NQ + k] = bB[(base + k * NQ) * B + b];
+        }
+      },
+      [&](int, double (&t)[2 * NQ], double (&o)[NQ]) {
+        double u[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) u[k] = t[k];
+        matvec<Lf, NQ, NQ, false, NQ>(u, o);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) o[k] = fma(g1, o[k], t[NQ + k]);
+      },
+      [&](int w, double (&o)[NQ]) {
+        const int b = w % B, pen = w / B;
+        const int base = (pen / NQ) * NQ2 + (pen % NQ);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) bB[(base + k * NQ) * B + b] = o[k];
+      });
+  __syncthreads();
+
+  // P6: direction-2 pencils: u = vq o T + g2 Lf_2 T + B, then N^T along 2;
+  // written into A in place as (NQ,NQ,NP) (each pencil has a single owner).
+  phase<NQ2 * B, NT, 3 * NQ, NP>(
+      tid,
+      [&](int w, double (&t)[3 * NQ]) {
+        const int b = w % B, pen = w / B;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+          t[k] = bA[(pen + k * NQ2) * B + b];
+          t[NQ + k] = bB[(pen + k * NQ2) * B + b];
+          t[2 * NQ + k] = svq[pen + k * NQ2];
+        }
+      },
+      [&](int, double (&t)[3 * NQ], double (&o)[NP]) {
+        double u[NQ], l[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) u[k] = t[k];
+        matvec<Lf, NQ, NQ, false, NQ>(u, l);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) u[k] = fma(t[2 * NQ + k], t[k], fma(g2, l[k], t[NQ + k]));
+        matvec<Nf, NP, NQ, true, NP>(u, o);
+      },
+      [&](int w, double (&o)[NP]) {
+        const int b = w % B, pen = w / B;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) bA[(pen + i * NQ2) * B + b] = o[i];
+      });
+  __syncthreads();
+
+  // P7: N^T along direction 1: A (NQ,NQ,NP) -> B (NQ,NP,NP).
+  {
+    using PI = Pencils<1, NQ, NQ, NP>;
+    using PO = Pencils<1, NQ, NP, NP>;
+    phase<PI::COUNT * B, NT, NQ, NP>(
+        tid,
+        [&](int w, double (&t)[NQ]) {
+          const int b = w % B, base = PI::base(w / B);
+#pragma unroll
+          for (int k = 0; k < NQ; ++k) t[k] = bA[(base + k * PI::STRIDE) * B + b];
+        },
+        [&](int, double (&t)[NQ], double (&o)[NP]) { matvec<Nf, NP, NQ, true, NP>(t, o); },
+        [&](int w, double (&o)[NP]) {
+          const int b = w % B, base = PO::base(w / B);
+#pragma unroll
+          for (int i = 0; i < NP; ++i) bB[(base + i * PO::STRIDE) * B + b] = o[i];
+        });
+  }
+  __syncthreads();
+
+  // P8: N^T along direction 0 fused with the assembly.
+  phase<NP2 * B, NT, NQ, NP>(
+      tid,
+      [&](int w, double (&t)[NQ]) {
+        const int b = w % B, pen = w / B;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) t[k] = bB[(pen * NQ + k) * B + b];
+      },
+      [&](int, double (&t)[NQ], double (&o)[NP]) { matvec<Nf, NP, NQ, true, NP>(t, o); },
+      [&](int w, double (&o)[NP]) {
+        const int b = w % B, pen = w / B, v = v0 + b;
+        if (v >= nvec) return;
+        const int i2 = pen % NP, i3 = pen / NP;
+        const bool inner_pen = i2 > 0 && i2 < NP - 1 && i3 > 0 && i3 < NP - 1;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          const int node = smap[pen * NP + i];
+          if (node < 0) continue;
+          double* dst = Y + (int64_t)node * ldy + v;
+          if (i > 0 && i < NP - 1 && inner_pen) {
+            if (ACCUM) *dst += o[i];
+            else *dst = o[i];
+          } else {
+            unsafeAtomicAdd(dst, o[i]);
+          }
+        }
+      });
+}
+
+template <int NP, int NQ, int B, int NT, bool ACCUM>
+hipError_t launch_box(const ApplyLaunch& a, hipStream_t s) {
+  const int ntiles = (a.nvec + B - 1) / B;
+  const int64_t nitems = a.ncells * ntiles;
+  const int64_t chunk = (nitems + kXcds - 1) / kXcds;
+  constexpr size_t lds = box_lds_bytes(NP, NQ, B);
+  static_assert(lds <= kLdsMax, "LDS");
+  auto k = apply_box_kernel<NP, NQ, B, NT, ACCUM>;
+  if (lds > 64 * 1024) {
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+  }
+  hipLaunchKernelGGL(k, dim3((unsigned)(chunk * kXcds)), dim3(NT), lds, s, a.map, a.order, a.geo,
+                     a.vq, a.X, a.Y, a.ldx, a.ldy, a.nvec, ntiles, nitems, chunk);
+  return hipGetLastError();
+}
+
+template <int NP, int NQ, int CFG>
+hipError_t try_cfg(const ApplyLaunch& a, hipStream_t s, bool& done) {
+  constexpr BoxCfg c = box_cfg(NP, NQ, CFG);
+  if constexpr (c.B > 0) {
+    if (a.cfg == CFG) {
+      done = true;
+      return a.accumulate ? launch_box<NP, NQ, c.B, c.NT, true>(a, s)
+                          : launch_box<NP, NQ, c.B, c.NT, false>(a, s);
+    }
+  }
+  return hipSuccess;
+}
+
+template <int NP, int NQ>
+hipError_t launch_pq(const ApplyLaunch& a, hipStream_t s) {
+  bool done = false;
+  hipError_t err = hipSuccess;
+  if (!done) err = try_cfg<NP, NQ, 0>(a, s, done);
+  if (!done) err = try_cfg<NP, NQ, 1>(a, s, done);
+  if (!done) err = try_cfg<NP, NQ, 2>(a, s, done);
+  if (!done) err = try_cfg<NP, NQ, 3>(a, s, done);
+  return done ? err : hipErrorInvalidValue;
+}
+
+}  // namespace
+
+template <>
+hipError_t launch_apply_box_p<MF_P>(const Operator& op, const ApplyLaunch& a, hipStream_t s) {
+  switch (op.q - MF_P) {
+    case 1: return launch_pq<MF_P + 1, MF_P + 1>(a, s);
+    case 2: return launch_pq<MF_P + 1, MF_P + 2>(a, s);
+    case 3: return launch_pq<MF_P + 1, MF_P + 3>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mf

@@ -130,11 +130,15 @@ int mf_create_operator(const mf_box_mesh* mesh, int p, int q, double mu, const d
   op->nq = q;
   op->mu = mu;
   op->sigma = sigma;
+  op->cfg = -1;
   op->t = make_tables(p, q);
   const int np = op->np, nq = op->nq, np3 = np * np * np, nq3 = nq * nq * nq;
   const int64_t Nx = nodes_per_dir(*mesh, p, 0), Ny = nodes_per_dir(*mesh, p, 1),
                 Nz = nodes_per_dir(*mesh, p, 2);
   op->ndofs = Nx * Ny * Nz;
+  op->nodes[0] = Nx;
+  op->nodes[1] = Ny;
+  op->nodes[2] = Nz;
   op->ncells = (int64_t)mesh->n[0] * mesh->n[1] * mesh->n[2];
   if (op->ndofs >= (int64_t)1 << 31) {
     delete op;
@@ -193,6 +197,8 @@ int mf_create_operator(const mf_box_mesh* mesh, int p, int q, double mu, const d
       for (int k = 0; k < 3; ++k) acc += Ji[3 * s + k] * Ji[3 * d + k];
       G[3 * s + d] = mu * detJ * acc;
     }
+  // axis-aligned cells: the off-diagonal entries vanish exactly (J diagonal)
+  op->box = G[1] == 0.0 && G[2] == 0.0 && G[5] == 0.0;
   std::vector<double> geo(E * 6);
   for (int64_t e = 0; e < E; ++e) {
     double* g = &geo[e * 6];
@@ -228,7 +234,10 @@ int mf_create_operator(const mf_box_mesh* mesh, int p, int q, double mu, const d
     if (e2 != hipSuccess) return hip_fail(e2, "hipMemcpy");
     return MF_OK;
   };
+  const int nn[3] = {mesh->n[0], mesh->n[1], mesh->n[2]};
+  std::vector<int32_t> order = cell_order(nn);
   int s = alloc_copy((void**)&op->d_map, map.data(), map.size() * sizeof(int32_t));
+  if (!s) s = alloc_copy((void**)&op->d_order, order.data(), order.size() * sizeof(int32_t));
   if (!s) s = alloc_copy((void**)&op->d_geo, geo.data(), geo.size() * sizeof(double));
   if (!s) s = alloc_copy((void**)&op->d_vq, vq.data(), vq.size() * sizeof(double));
   if (s) {
@@ -243,6 +252,8 @@ void mf_destroy_operator(mf_operator* handle) {
   if (!handle) return;
   Operator* op = reinterpret_cast<Operator*>(handle);
   if (op->d_map) (void)hipFree(op->d_map);
+  if (op->d_order) (void)hipFree(op->d_order);
+  for (hipEvent_t e : op->ev) (void)hipEventDestroy(e);
   if (op->d_geo) (void)hipFree(op->d_geo);
   if (op->d_vq) (void)hipFree(op->d_vq);
   delete op;
@@ -265,7 +276,7 @@ static bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes)
 }
 
 static int apply_common(mf_operator* handle, const double* X, double* Y, int nvec, int64_t ldx,
-                        int64_t ldy, int prec, void* stream, bool zero_first) {
+                        int64_t ldy, int prec, void* stream, bool accumulate) {
   if (!handle) return fail(MF_ERR_ARG, "operator is NULL");
   if (!X || !Y) return fail(MF_ERR_ARG, "X and Y must be non-NULL device pointers");
   if (nvec < 1) return fail(MF_ERR_ARG, "nvec must be >= 1");
@@ -279,6 +290,7 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
 
   ApplyLaunch a{};
   a.map = op->d_map;
+  a.order = op->d_order;
   a.geo = op->d_geo;
   a.vq = op->d_vq;
   a.X = X;
@@ -289,23 +301,89 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
   a.nvec = nvec;
   a.threads = 256;
   a.vtile = choose_vtile_f64(op->np, op->nq, nvec);
-  if (zero_first) {
-    hipError_t err = launch_zero_rows(Y, op->ndofs, nvec, ldy, s);
+  a.cfg = op->cfg >= 0 ? op->cfg : choose_cfg_box(op->np, op->nq, nvec);
+  a.accumulate = accumulate;
+
+  hipEvent_t* ev = nullptr;
+  if (op->ev_slots > 0) {
+    ev = &op->ev[3 * op->ev_next];
+    op->ev_next = (op->ev_next + 1) % op->ev_slots;
+    if (op->ev_count < op->ev_slots) ++op->ev_count;
+    (void)hipEventRecord(ev[0], s);
+  }
+  hipError_t err = hipSuccess;
+  if (!accumulate) {
+    err = op->box ? launch_zero_shared_rows(Y, op->nodes, op->p, nvec, ldy, s)
+                  : launch_zero_rows(Y, op->ndofs, nvec, ldy, s);
     if (err != hipSuccess) return hip_fail(err, "zero kernel launch");
   }
-  hipError_t err = launch_apply_f64(*op, a, s);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  err = op->box ? launch_apply_box(*op, a, s) : launch_apply_f64(*op, a, s);
   if (err != hipSuccess) return hip_fail(err, "apply kernel launch");
+  if (ev) (void)hipEventRecord(ev[2], s);
   return MF_OK;
 }
 
 int mf_apply(mf_operator* handle, const double* X, double* Y, int nvec, int64_t ldx, int64_t ldy,
              int prec, void* stream) {
-  return apply_common(handle, X, Y, nvec, ldx, ldy, prec, stream, true);
+  return apply_common(handle, X, Y, nvec, ldx, ldy, prec, stream, /*accumulate=*/false);
 }
 
 int mf_apply_add(mf_operator* handle, const double* X, double* Y, int nvec, int64_t ldx,
                  int64_t ldy, int prec, void* stream) {
-  return apply_common(handle, X, Y, nvec, ldx, ldy, prec, stream, false);
+  return apply_common(handle, X, Y, nvec, ldx, ldy, prec, stream, /*accumulate=*/true);
+}
+
+int mf_set_launch(mf_operator* handle, int general, int cfg) {
+  if (!handle) return fail(MF_ERR_ARG, "operator is NULL");
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  if (cfg < -1 || cfg >= kBoxCfgs) return fail(MF_ERR_ARG, "cfg out of range");
+  if (cfg >= 0 && !apply_box_supported(op->p, op->q, cfg))
+    return fail(MF_ERR_UNSUPPORTED, "launch shape does not fit this (p, q)");
+  if (general) op->box = false;
+  op->cfg = cfg;
+  return MF_OK;
+}
+
+int mf_timing(mf_operator* handle, int slots) {
+  if (!handle) return fail(MF_ERR_ARG, "operator is NULL");
+  if (slots < 0 || slots > 100000) return fail(MF_ERR_ARG, "slots out of range");
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  for (hipEvent_t e : op->ev) (void)hipEventDestroy(e);
+  op->ev.assign(3 * (size_t)slots, nullptr);
+  for (auto& e : op->ev) {
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) {
+      op->ev_slots = 0;
+      return hip_fail(err, "hipEventCreate");
+    }
+  }
+  op->ev_slots = slots;
+  op->ev_next = 0;
+  op->ev_count = 0;
+  return MF_OK;
+}
+
+int mf_timing_read(mf_operator* handle, int* count, double* zero_ms, double* kernel_ms) {
+  if (!handle) return fail(MF_ERR_ARG, "operator is NULL");
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  double z = 0.0, k = 0.0;
+  for (int i = 0; i < op->ev_count; ++i) {
+    hipError_t err = hipEventSynchronize(op->ev[3 * i + 2]);
+    if (err != hipSuccess) return hip_fail(err, "hipEventSynchronize");
+    float a = 0.f, b = 0.f;
+    err = hipEventElapsedTime(&a, op->ev[3 * i], op->ev[3 * i + 1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&b, op->ev[3 * i + 1], op->ev[3 * i + 2]);
+    if (err != hipSuccess) return hip_fail(err, "hipEventElapsedTime");
+    z += a;
+    k += b;
+  }
+  if (count) *count = op->ev_count;
+  if (zero_ms) *zero_ms = z;
+  if (kernel_ms) *kernel_ms = k;
+  op->ev_count = 0;
+  op->ev_next = 0;
+  return MF_OK;
 }
 
 int mf_zero(double* Y, int64_t nrows, int ncols, int64_t ld, void* stream) {

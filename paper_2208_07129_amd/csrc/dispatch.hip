@@ -18,7 +18,66 @@ __global__ void zero_rows_kernel(double* __restrict__ Y, int64_t nrows, int ncol
   }
 }
 
+__global__ void zero_shared_rows_kernel(double* __restrict__ Y, int64_t Nx, int64_t Ny,
+                                        int64_t Nz, int p, int ncols, int64_t ld) {
+  const int64_t total = Nx * Ny * Nz * ncols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / ncols, c = i % ncols;
+    const int64_t gx = r % Nx, gy = (r / Nx) % Ny, gz = r / (Nx * Ny);
+    if (gx % p == 0 || gy % p == 0 || gz % p == 0) Y[r * ld + c] = 0.0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_zero_shared_rows(double* Y, const int64_t nodes[3], int p, int ncols, int64_t ld,
+                                   hipStream_t s) {
+  const int64_t total = nodes[0] * nodes[1] * nodes[2] * ncols;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(zero_shared_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, Y, nodes[0],
+                     nodes[1], nodes[2], p, ncols, ld);
+  return hipGetLastError();
+}
+
+bool apply_box_supported(int p, int q, int cfg) {
+  if (p < 1 || p > kMaxP || q < p + 1 || q > p + kMaxQExtra || cfg < 0 || cfg >= kBoxCfgs)
+    return false;
+  return box_cfg(p + 1, q, cfg).B > 0;
+}
+
+int choose_cfg_box(int np, int nq, int nvec) {
+  // the default shape, unless the columns fill a smaller tile better
+  const int b0 = box_cfg(np, nq, 0).B;
+  if (nvec >= b0) return 0;
+  int best = 0, bestB = b0;
+  for (int c = 1; c < kBoxCfgs; ++c) {
+    const int b = box_cfg(np, nq, c).B;
+    if (b >= nvec && b < bestB) {
+      best = c;
+      bestB = b;
+    }
+  }
+  return best;
+}
+
+hipError_t launch_apply_box(const Operator& op, const ApplyLaunch& a, hipStream_t s) {
+  switch (op.p) {
+    case 1: return launch_apply_box_p<1>(op, a, s);
+    case 2: return launch_apply_box_p<2>(op, a, s);
+    case 3: return launch_apply_box_p<3>(op, a, s);
+    case 4: return launch_apply_box_p<4>(op, a, s);
+    case 5: return launch_apply_box_p<5>(op, a, s);
+    case 6: return launch_apply_box_p<6>(op, a, s);
+    case 7: return launch_apply_box_p<7>(op, a, s);
+    case 8: return launch_apply_box_p<8>(op, a, s);
+    case 9: return launch_apply_box_p<9>(op, a, s);
+    case 10: return launch_apply_box_p<10>(op, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_zero_rows(double* Y, int64_t nrows, int ncols, int64_t ld, hipStream_t s) {
   const int64_t total = nrows * ncols;
@@ -31,17 +90,16 @@ hipError_t launch_zero_rows(double* Y, int64_t nrows, int ncols, int64_t ld, hip
 
 bool apply_f64_supported(int p, int q) {
   if (p < 1 || p > kMaxP || q < p + 1 || q > p + kMaxQExtra) return false;
-  return f64_lds_bytes(p + 1, q, 1) <= 64 * 1024;
+  return f64_bmax(p + 1, q) >= 1;
 }
 
 int choose_vtile_f64(int np, int nq, int nvec) {
-  // enough (vector, pencil) work items to occupy 256 threads in the
-  // pencil stages, as many as the 64 KiB LDS budget allows
-  int vt = 256 / (nq * nq);
-  if (vt < 1) vt = 1;
-  while (vt > 1 && f64_lds_bytes(np, nq, vt) > 64 * 1024) --vt;
-  if (vt > nvec) vt = nvec;
-  return vt;
+  // the default tile, or for fewer columns the smallest built tile covering them
+  const int bd = f64_bdef(np, nq);
+  if (nvec >= bd) return bd;
+  for (int b = 1; b <= bd; ++b)
+    if (b >= nvec && f64_tile_built(np, nq, b)) return b;
+  return bd;
 }
 
 hipError_t launch_apply_f64(const Operator& op, const ApplyLaunch& a, hipStream_t s) {

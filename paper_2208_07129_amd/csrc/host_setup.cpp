@@ -1,75 +1,26 @@
-// Host-side setup of the matrix-free operator: 1D rules, 1D basis tables with
-// the weight folding of Sec. 3.2.4, and the structured-mesh numbering.
+// Host-side setup of the matrix-free operator: 1D rules and basis tables (the
+// constexpr code of sf_tables.h, evaluated at run time) and mesh validation.
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <stdexcept>
 
 #include "mf_internal.h"
+#include "sf_tables.h"
 
 namespace mf {
-
-namespace {
-
-// Legendre P_n(x) with first and second derivatives (Bonnet recurrence).
-void legendre(int n, double x, double& P, double& dP, double& ddP) {
-  double p0 = 1.0, p1 = 0.0, d1 = 0.0, dd1 = 0.0;  // p0 = P_{k-1}, p1 = P_{k-2}
-  double d0 = 0.0, dd0 = 0.0;
-  for (int k = 1; k <= n; ++k) {
-    const double pk = ((2.0 * k - 1.0) * x * p0 - (k - 1.0) * p1) / k;
-    const double dk = x * d0 + k * p0;
-    const double ddk = x * dd0 + (k + 1.0) * d0;
-    p1 = p0;
-    p0 = pk;
-    d1 = d0;
-    d0 = dk;
-    dd1 = dd0;
-    dd0 = ddk;
-  }
-  (void)d1;
-  (void)dd1;
-  P = p0;
-  dP = d0;
-  ddP = dd0;
-}
-
-}  // namespace
 
 Rule1D gauss_rule(int n) {
   Rule1D r;
   r.x.resize(n);
   r.w.resize(n);
-  for (int i = 0; i < n; ++i) {
-    // Chebyshev-like initial guess, ascending order
-    double x = -std::cos(M_PI * (i + 0.75) / (n + 0.5));
-    double P, dP, ddP;
-    for (int it = 0; it < 100; ++it) {
-      legendre(n, x, P, dP, ddP);
-      const double dx = P / dP;
-      x -= dx;
-      if (std::fabs(dx) < 1e-17) break;
-    }
-    legendre(n, x, P, dP, ddP);
-    r.x[i] = x;
-    r.w[i] = 2.0 / ((1.0 - x * x) * dP * dP);
-  }
+  ct::gauss(n, r.x.data(), r.w.data());
   return r;
 }
 
 std::vector<double> gll_points(int p) {
   std::vector<double> x(p + 1);
-  x[0] = -1.0;
-  x[p] = 1.0;
-  for (int i = 1; i < p; ++i) {
-    double t = -std::cos(M_PI * i / p);
-    double P, dP, ddP;
-    for (int it = 0; it < 100; ++it) {
-      legendre(p, t, P, dP, ddP);
-      const double dt = dP / ddP;
-      t -= dt;
-      if (std::fabs(dt) < 1e-17) break;
-    }
-    x[i] = t;
-  }
+  ct::gll(p, x.data());
   return x;
 }
 
@@ -77,55 +28,16 @@ Tables1D make_tables(int p, int q) {
   Tables1D t;
   t.np = p + 1;
   t.nq = q;
-  Rule1D g = gauss_rule(q);
-  t.xq = g.x;
-  t.wq = g.w;
-  t.xn = gll_points(p);
-  const int np = t.np, nq = t.nq;
-  t.N.assign(nq * np, 0.0);
-  t.D.assign(nq * np, 0.0);
-  for (int a = 0; a < nq; ++a) {
-    const double x = t.xq[a];
-    for (int i = 0; i < np; ++i) {
-      double L = 1.0;
-      for (int m = 0; m < np; ++m)
-        if (m != i) L *= (x - t.xn[m]) / (t.xn[i] - t.xn[m]);
-      double dL = 0.0;
-      for (int l = 0; l < np; ++l) {
-        if (l == i) continue;
-        double term = 1.0 / (t.xn[i] - t.xn[l]);
-        for (int m = 0; m < np; ++m)
-          if (m != i && m != l) term *= (x - t.xn[m]) / (t.xn[i] - t.xn[m]);
-        dL += term;
-      }
-      t.N[a * np + i] = L;
-      t.D[a * np + i] = dL;
-    }
-  }
-  // Collocation derivative on the Gauss points, barycentric form:
-  // Dt(a,b) = (lam_b / lam_a) / (x_a - x_b) for a != b, rows sum to zero.
-  std::vector<double> lam(nq, 1.0);
-  for (int b = 0; b < nq; ++b)
-    for (int m = 0; m < nq; ++m)
-      if (m != b) lam[b] /= (t.xq[b] - t.xq[m]);
-  t.Dt.assign(nq * nq, 0.0);
-  for (int a = 0; a < nq; ++a) {
-    double diag = 0.0;
-    for (int b = 0; b < nq; ++b) {
-      if (a == b) continue;
-      const double v = (lam[b] / lam[a]) / (t.xq[a] - t.xq[b]);
-      t.Dt[a * nq + b] = v;
-      diag -= v;
-    }
-    t.Dt[a * nq + a] = diag;
-  }
-  // Weight folding (Sec. 3.2.4): quadrature weights move into the 1D matrices.
-  t.Nf.resize(nq * np);
-  t.Dtf.resize(nq * nq);
-  for (int a = 0; a < nq; ++a) {
-    for (int i = 0; i < np; ++i) t.Nf[a * np + i] = t.N[a * np + i] * std::sqrt(t.wq[a]);
-    for (int b = 0; b < nq; ++b) t.Dtf[a * nq + b] = t.Dt[a * nq + b] * std::sqrt(t.wq[a] / t.wq[b]);
-  }
+  t.xq.resize(q);
+  t.wq.resize(q);
+  t.xn.resize(p + 1);
+  t.N.resize(q * (p + 1));
+  t.D.resize(q * (p + 1));
+  t.Dt.resize(q * q);
+  t.Nf.resize(q * (p + 1));
+  t.Dtf.resize(q * q);
+  ct::tables(p + 1, q, t.xq.data(), t.wq.data(), t.xn.data(), t.N.data(), t.D.data(), t.Dt.data(),
+             t.Nf.data(), t.Dtf.data());
   return t;
 }
 
@@ -155,6 +67,54 @@ int validate_mesh(const mf_box_mesh* m) {
     if (!std::isfinite(L[k])) return fail(MF_ERR_ARG, "mesh: non-finite linear map");
   if (!(det3(L) > 0.0)) return fail(MF_ERR_ARG, "mesh: linear map must have positive determinant");
   return MF_OK;
+}
+
+std::vector<int32_t> cell_order(const int n[3]) {
+  struct Blk {
+    int lo[3], hi[3];
+  };
+  std::vector<Blk> blocks{Blk{{0, 0, 0}, {n[0], n[1], n[2]}}};
+  for (int level = 0; level < 3; ++level) {  // 8 blocks: one per XCD
+    std::vector<Blk> next;
+    for (const Blk& b : blocks) {
+      int d = 0;
+      for (int k = 1; k < 3; ++k)
+        if (b.hi[k] - b.lo[k] > b.hi[d] - b.lo[d]) d = k;
+      const int len = b.hi[d] - b.lo[d];
+      if (len < 2) {
+        next.push_back(b);
+        continue;
+      }
+      Blk a = b, c = b;
+      a.hi[d] = b.lo[d] + len / 2;
+      c.lo[d] = a.hi[d];
+      next.push_back(a);
+      next.push_back(c);
+    }
+    blocks.swap(next);
+  }
+  auto morton = [](uint32_t x, uint32_t y, uint32_t z) {
+    uint64_t code = 0;
+    for (int bit = 0; bit < 21; ++bit) {
+      code |= (uint64_t)((x >> bit) & 1) << (3 * bit);
+      code |= (uint64_t)((y >> bit) & 1) << (3 * bit + 1);
+      code |= (uint64_t)((z >> bit) & 1) << (3 * bit + 2);
+    }
+    return code;
+  };
+  std::vector<int32_t> order;
+  order.reserve((size_t)n[0] * n[1] * n[2]);
+  for (const Blk& b : blocks) {
+    std::vector<std::pair<uint64_t, int32_t>> cells;
+    for (int z = b.lo[2]; z < b.hi[2]; ++z)
+      for (int y = b.lo[1]; y < b.hi[1]; ++y)
+        for (int x = b.lo[0]; x < b.hi[0]; ++x)
+          cells.emplace_back(morton(x - b.lo[0], y - b.lo[1], z - b.lo[2]),
+                             (int32_t)(x + n[0] * (y + (int64_t)n[1] * z)));
+    std::sort(cells.begin(), cells.end());
+    for (auto& c : cells) order.push_back(c.second);
+  }
+  return order;
 }
 
 int64_t nodes_per_dir(const mf_box_mesh& m, int p, int d) {

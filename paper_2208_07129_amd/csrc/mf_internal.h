@@ -13,6 +13,7 @@ namespace mf {
 
 constexpr int kMaxP = 10;
 constexpr int kMaxQExtra = 3;  // q in [p+1, p+3]
+constexpr int kBoxCfgs = 4;    // launch shapes of the box-cell kernel
 
 // Error reporting: every entry point returns a status and stores a message.
 int fail(int status, const std::string& msg);
@@ -48,15 +49,24 @@ struct Operator {
   int64_t ncells = 0, ndofs = 0;
   double mu = 0.0, sigma = 0.0;
   // device arrays
+  int64_t nodes[3] = {0, 0, 0};  // nodes per direction of the full numbering
+  bool box = false;           // every cell axis-aligned: diagonal 3x3 factor
+  int cfg = 0;                // launch shape of the box kernel (tuned or default)
   int32_t* d_map = nullptr;   // E x np^3, -1 = constrained
+  int32_t* d_order = nullptr; // E: processing order of the cells
   double* d_geo = nullptr;    // E x 6: mu det J (J^-1 J^-T), (00,01,02,11,12,22)
   double* d_vq = nullptr;     // E x nq^3: det J (V + sigma)
   Tables1D t;
+  // optional per-launch timing (diagnostics): event triples around the zero
+  // fill and the fused kernel of each apply, in a ring
+  std::vector<hipEvent_t> ev;
+  int ev_slots = 0, ev_next = 0, ev_count = 0;
 };
 
 // ----------------------------------------------------------------- kernels
 struct ApplyLaunch {
   const int32_t* map;
+  const int32_t* order;
   const double* geo;
   const double* vq;
   const double* X;
@@ -64,14 +74,27 @@ struct ApplyLaunch {
   int64_t ldx, ldy;
   int64_t ncells;
   int nvec;
-  int vtile;    // vectors per workgroup tile
-  int threads;  // workgroup size
+  int vtile;    // vectors per workgroup tile (general kernel)
+  int threads;  // workgroup size (general kernel)
+  int cfg;      // launch shape index (box kernel)
+  bool accumulate;
 };
 
 // FP64 fused apply; returns hipSuccess or the launch error.
 hipError_t launch_apply_f64(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 // Zero rows [0, nrows) x columns [0, ncols) of a row-major array with stride ld.
 hipError_t launch_zero_rows(double* Y, int64_t nrows, int ncols, int64_t ld, hipStream_t s);
+// Zero the rows of nodes on cell faces (some grid index a multiple of p) of an
+// Nx x Ny x Nz node grid: the rows the box kernel assembles with atomics.
+hipError_t launch_zero_shared_rows(double* Y, const int64_t nodes[3], int p, int ncols, int64_t ld,
+                                   hipStream_t s);
+// FP64 fused apply for box cells.
+hipError_t launch_apply_box(const Operator& op, const ApplyLaunch& a, hipStream_t s);
+bool apply_box_supported(int p, int q, int cfg);
+int choose_cfg_box(int np, int nq, int nvec);
+// Processing order of the cells: 8 blocks by recursive bisection (one per XCD),
+// Morton order inside each block.
+std::vector<int32_t> cell_order(const int n[3]);
 bool apply_f64_supported(int p, int q);
 // Vectors per workgroup tile of the FP64 kernel (256 threads, LDS within 64 KiB).
 int choose_vtile_f64(int np, int nq, int nvec);

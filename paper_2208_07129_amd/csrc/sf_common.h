@@ -9,8 +9,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
 
 #include "mf_internal.h"
+#include "sf_tables.h"
 
 namespace mf {
 
@@ -24,26 +26,47 @@ __device__ inline int64_t xcd_item(int64_t wg, int64_t chunk) {
   return (wg % kXcds) * chunk + wg / kXcds;
 }
 
-// Weight-folded 1D matrices passed by value in the kernel-argument segment:
-// every lane reads the same entry at the same time, so the compiler serves them
-// with scalar loads.  N[a*NP + i], D[a*NQ + b].
+// Compile-time coefficient sources: M::at<K> is the K-th entry of a 1D matrix
+// as a constant expression, so contractions are emitted with literal
+// coefficients (uniform operands, nothing loaded or held in registers).
 template <int NP, int NQ>
-struct Mats {
-  double N[NQ * NP];
-  double D[NQ * NQ];
+struct MatN {  // folded N1D, NQ x NP, row-major
+  template <int K>
+  static constexpr double at = Tab<NP, NQ>::v.Nf[K];
+};
+template <int NP, int NQ>
+struct MatD {  // folded Dt, NQ x NQ, row-major
+  template <int K>
+  static constexpr double at = Tab<NP, NQ>::v.Dtf[K];
 };
 
+template <int NP, int NQ>
+struct MatL {  // Dtf^T Dtf, NQ x NQ, symmetric
+  template <int K>
+  static constexpr double at = Tab<NP, NQ>::v.Lf[K];
+};
+
+template <class M, bool TR, int LD, int O, typename T, int NIN, int... I>
+__device__ __forceinline__ T mrow(const T (&in)[NIN], std::integer_sequence<int, I...>) {
+  T acc = T(0);
+  // entries that are exactly zero (a Gauss point on a GLL node) are skipped
+  ((M::template at<(TR ? I * LD + O : O * LD + I)> != 0.0
+        ? (void)(acc = fma(T(M::template at<(TR ? I * LD + O : O * LD + I)>), in[I], acc))
+        : (void)0),
+   ...);
+  return acc;
+}
+
+template <class M, bool TR, int LD, typename T, int NIN, int NOUT, int... O>
+__device__ __forceinline__ void mvec(const T (&in)[NIN], T (&out)[NOUT],
+                                     std::integer_sequence<int, O...>) {
+  ((out[O] = mrow<M, TR, LD, O>(in, std::make_integer_sequence<int, NIN>{})), ...);
+}
+
 // out[o] = sum_i M(o, i) in[i]; M(o, i) = M[o*LD + i], or M[i*LD + o] if TR.
-template <int NOUT, int NIN, bool TR, int LD, typename T>
-__device__ __forceinline__ void matvec(const double* __restrict__ M, const T (&in)[NIN],
-                                       T (&out)[NOUT]) {
-#pragma unroll
-  for (int o = 0; o < NOUT; ++o) {
-    T acc = T(0);
-#pragma unroll
-    for (int i = 0; i < NIN; ++i) acc = fma(T(TR ? M[i * LD + o] : M[o * LD + i]), in[i], acc);
-    out[o] = acc;
-  }
+template <class M, int NOUT, int NIN, bool TR, int LD, typename T>
+__device__ __forceinline__ void matvec(const T (&in)[NIN], T (&out)[NOUT]) {
+  mvec<M, TR, LD>(in, out, std::make_integer_sequence<int, NOUT>{});
 }
 
 // Pencil geometry of an (S0, S1, S2) array for a contraction along DIR.
@@ -61,31 +84,86 @@ struct Pencils {
 
 // One 1D contraction stage over every (vector, pencil) work item of the tile:
 // dst (extent NOUT along DIR) = M applied along DIR to src (extents S0,S1,S2).
-template <int DIR, int S0, int S1, int S2, int NOUT, bool TR, int LD, typename T>
-__device__ __forceinline__ void stage(const T* __restrict__ src, T* __restrict__ dst,
-                                      const double* __restrict__ M, int B, int tid, int nthr) {
+template <class M, int DIR, int S0, int S1, int S2, int NOUT, bool TR, int LD, int B, int NT,
+          typename T>
+__device__ __forceinline__ void stage(const T* __restrict__ src, T* __restrict__ dst, int tid) {
   using PI = Pencils<DIR, S0, S1, S2>;
   using PO = Pencils<DIR, DIR == 0 ? NOUT : S0, DIR == 1 ? NOUT : S1, DIR == 2 ? NOUT : S2>;
   constexpr int NIN = PI::L;
-  for (int w = tid; w < PI::COUNT * B; w += nthr) {
+  for (int w = tid; w < PI::COUNT * B; w += NT) {
     const int b = w % B, pen = w / B;
     const int bi = PI::base(pen), bo = PO::base(pen);
     T r[NIN], o[NOUT];
 #pragma unroll
     for (int i = 0; i < NIN; ++i) r[i] = src[(bi + i * PI::STRIDE) * B + b];
-    matvec<NOUT, NIN, TR, LD>(M, r, o);
+    matvec<M, NOUT, NIN, TR, LD>(r, o);
 #pragma unroll
     for (int i = 0; i < NOUT; ++i) dst[(bo + i * PO::STRIDE) * B + b] = o[i];
   }
 }
 
+constexpr int kThreads = 256;             // workgroup size of the fused kernels
+constexpr size_t kLdsBudget = 64 * 1024;   // LDS per workgroup the kernels stay within
+
 // LDS bytes of the FP64 kernel: three cell buffers, the scaled potential and the map.
-inline size_t f64_lds_bytes(int np, int nq, int vtile) {
-  const size_t nq3 = (size_t)nq * nq * nq, np3 = (size_t)np * np * np;
-  return (3 * nq3 * vtile + nq3) * sizeof(double) + np3 * sizeof(int);
+constexpr size_t f64_lds_bytes(int np, int nq, int vtile) {
+  return (3 * (size_t)nq * nq * nq * vtile + (size_t)nq * nq * nq) * sizeof(double) +
+         (size_t)np * np * np * sizeof(int);
+}
+// Largest vector tile that fits the LDS budget (0 if none).
+constexpr int f64_bmax(int np, int nq) {
+  int b = 0;
+  while (f64_lds_bytes(np, nq, b + 1) <= kLdsBudget && b < 64) ++b;
+  return b;
+}
+// Default tile: enough (vector, pencil) items to occupy the workgroup in the
+// pencil stages, within the LDS budget.
+constexpr int f64_bdef(int np, int nq) {
+  int b = kThreads / (nq * nq);
+  if (b < 1) b = 1;
+  const int m = f64_bmax(np, nq);
+  return b < m ? b : m;
+}
+// Vector tiles instantiated per (np, nq): 1, 2, 4, 8 and the default, within budget.
+constexpr bool f64_tile_built(int np, int nq, int b) {
+  return b >= 1 && b <= f64_bmax(np, nq) && (b == 1 || b == 2 || b == 4 || b == 8 || b == f64_bdef(np, nq));
+}
+
+constexpr size_t kLdsMax = 160 * 1024;     // LDS per workgroup on gfx950
+
+// LDS bytes of the box-cell kernel: two cell buffers, the scaled potential, the map.
+constexpr size_t box_lds_bytes(int np, int nq, int vtile) {
+  return (2 * (size_t)nq * nq * nq * vtile + (size_t)nq * nq * nq) * sizeof(double) +
+         (size_t)np * np * np * sizeof(int);
+}
+
+// Launch shapes of the box-cell kernel: (vector tile B, threads NT).  B = 8 and
+// 16 make the [point][vector] LDS accesses of a 16-lane group hit 16 distinct
+// 8-byte bank pairs.  A shape that does not fit the LDS has B = 0.
+struct BoxCfg {
+  int B, NT;
+};
+constexpr BoxCfg box_cfg(int np, int nq, int idx) {
+  // 0: default (largest of 16/8/4/2/1 within 80 KiB, two workgroups per CU), 256 threads
+  // 1: B = 8, 256 threads;  2: B = 16, 512 threads;  3: B = 4, 128 threads
+  BoxCfg c{0, 256};
+  if (idx == 0) {
+    for (int b = 16; b >= 1; b /= 2)
+      if (box_lds_bytes(np, nq, b) <= 80 * 1024) return BoxCfg{b, 256};
+    for (int b = 16; b >= 1; b /= 2)
+      if (box_lds_bytes(np, nq, b) <= kLdsMax) return BoxCfg{b, 256};
+    return c;
+  }
+  if (idx == 1) c = BoxCfg{8, 256};
+  if (idx == 2) c = BoxCfg{16, 512};
+  if (idx == 3) c = BoxCfg{4, 128};
+  if (box_lds_bytes(np, nq, c.B) > kLdsMax) c.B = 0;
+  return c;
 }
 
 template <int P>
 hipError_t launch_apply_f64_p(const Operator& op, const ApplyLaunch& a, hipStream_t s);
+template <int P>
+hipError_t launch_apply_box_p(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 
 }  // namespace mf

@@ -24,7 +24,8 @@ PRECISIONS = {"fp64": MF_FP64, "fp32": MF_FP32_MFMA, "bf16": MF_BF16_MFMA}
 # Every symbol declared in include/mfmv.h.
 EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask", "mf_basis_1d",
            "mf_create_operator", "mf_destroy_operator", "mf_operator_info", "mf_apply",
-           "mf_apply_add", "mf_zero", "mf_last_error")
+           "mf_apply_add", "mf_zero", "mf_set_launch", "mf_timing", "mf_timing_read",
+           "mf_last_error")
 
 
 class MfError(RuntimeError):
@@ -62,6 +63,9 @@ def lib() -> ctypes.CDLL:
             "mf_apply": (I, [P, P, P, I, I64, I64, I, P]),
             "mf_apply_add": (I, [P, P, P, I, I64, I64, I, P]),
             "mf_zero": (I, [P, I64, I, I64, P]),
+            "mf_set_launch": (I, [P, I, I]),
+            "mf_timing": (I, [P, I]),
+            "mf_timing_read": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D)]),
             "mf_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -174,6 +178,18 @@ class Operator:
     def apply_ptr(self, X_ptr: int, Y_ptr: int, nvec: int, ldx: int, ldy: int,
                   prec: int = MF_FP64, stream=None):
         _check(lib().mf_apply(self._h, X_ptr, Y_ptr, nvec, ldx, ldy, prec, _stream_ptr(stream)))
+
+    def set_launch(self, general: bool = False, cfg: int = -1):
+        _check(lib().mf_set_launch(self._h, int(general), int(cfg)))
+
+    def timing(self, slots: int):
+        _check(lib().mf_timing(self._h, int(slots)))
+
+    def timing_read(self):
+        """(count, zero-fill ms summed, fused-kernel ms summed) since the last read."""
+        n, z, k = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().mf_timing_read(self._h, ctypes.byref(n), ctypes.byref(z), ctypes.byref(k)))
+        return n.value, z.value, k.value
 
     def apply_add_ptr(self, X_ptr: int, Y_ptr: int, nvec: int, ldx: int, ldy: int,
                       prec: int = MF_FP64, stream=None):

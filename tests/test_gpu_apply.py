@@ -35,9 +35,14 @@ def colrel(Y, Yref):
     return float((num / np.maximum(den, 1e-300)).max())
 
 
+def nan_like(X):
+    """Output buffer full of NaN: mf_apply must overwrite every row it owns."""
+    return torch.full(X.shape, float("nan"), dtype=torch.float64, device=X.device)
+
+
 def gpu_apply(op, X, precision="fp64"):
     Xd = torch.from_numpy(np.ascontiguousarray(X)).to(dev())
-    Yd = op.apply(Xd, precision=precision)
+    Yd = op.apply(Xd, nan_like(Xd), precision=precision)
     torch.cuda.synchronize()
     return Yd.cpu().numpy()
 
@@ -144,8 +149,9 @@ def _sampled_parity(w, nrows, seed):
     orc = fo.Oracle(w.mesh, w.p, w.q, w.mu, w.V, w.sigma)
     X = w.X()
     Xd = torch.from_numpy(X).to(dev())
-    Yd = op.apply(Xd)
+    Yd = op.apply(Xd, nan_like(Xd))
     torch.cuda.synchronize()
+    assert not torch.isnan(Yd).any()
     rows = np.random.default_rng(seed).choice(orc.ndofs, nrows, replace=False)
     Yrows = Yd[torch.from_numpy(rows).to(dev())].cpu().numpy()
     Yref = orc.apply_rows(X, rows)
@@ -190,3 +196,70 @@ def test_config3_sampled_rows(nvec):
 def test_config5_sampled_rows():
     """Periodic [0,10]^3, 20^3 cells, p=6, q=7, sigma=0.5, 128 columns (the solve operator)."""
     _sampled_parity(W.config5(), 12, 5)
+
+
+BOX_CASES = [
+    # p, q, cells, bc, nvec
+    (2, 3, (3, 2, 2), W.BC_DIRICHLET0, 19),
+    (3, 5, (2, 2, 2), W.BC_PERIODIC, 33),
+    (4, 5, (1, 2, 2), W.BC_NONE, 17),
+    (6, 7, (2, 2, 2), W.BC_PERIODIC, 21),
+    (6, 8, (2, 1, 2), W.BC_DIRICHLET0, 9),
+    (8, 9, (2, 1, 1), W.BC_PERIODIC, 13),
+    (10, 11, (1, 1, 2), W.BC_NONE, 3),
+]
+
+
+@pytest.mark.parametrize("p,q,n,bc,nvec", BOX_CASES)
+def test_box_kernel_every_launch_shape(p, q, n, bc, nvec):
+    """Every built launch shape of the axis-aligned-cell kernel, plus the general kernel
+    forced on the same box mesh, against the oracle (ragged column tiles)."""
+    mesh = W.BoxMesh(n=n, lo=(0.0, -0.5, 0.25), hi=(1.0, 1.0, 1.5), bc=bc)
+    op, orc = build_pair(mesh, p, q)
+    X = np.random.default_rng(p * 7 + q).uniform(-1, 1, (orc.ndofs, nvec))
+    Yref = orc.apply(X)
+    ran = 0
+    for cfg in range(4):
+        try:
+            op.set_launch(False, cfg)
+        except mfmv.MfError as e:
+            assert e.status == mfmv.MF_ERR_UNSUPPORTED
+            continue
+        assert colrel(gpu_apply(op, X), Yref) <= TOL, cfg
+        ran += 1
+    assert ran >= 1
+    op.set_launch(True, -1)
+    assert colrel(gpu_apply(op, X), Yref) <= TOL
+
+
+def test_box_accumulate_and_timing():
+    mesh = W.BoxMesh(n=(3, 3, 2), bc=W.BC_DIRICHLET0)
+    op, orc = build_pair(mesh, 4, 5)
+    rng = np.random.default_rng(2)
+    X = rng.uniform(-1, 1, (orc.ndofs, 12))
+    Y0 = rng.uniform(-1, 1, (orc.ndofs, 12))
+    Yref = orc.apply(X)
+    Xd = torch.from_numpy(X).to(dev())
+    Yd = torch.from_numpy(Y0.copy()).to(dev())
+    op.timing(8)
+    op.apply(Xd, Yd, accumulate=True)
+    Y1 = op.apply(Xd, nan_like(Xd))
+    n, zero_ms, kern_ms = op.timing_read()
+    assert n == 2 and kern_ms > 0.0 and zero_ms >= 0.0
+    op.timing(0)
+    assert colrel(Yd.cpu().numpy(), Y0 + Yref) <= TOL
+    np.testing.assert_array_equal(Yd.cpu().numpy()[orc.constrained], Y0[orc.constrained])
+    assert colrel(Y1.cpu().numpy(), Yref) <= TOL
+
+
+def test_config2_general_kernel_matches_box_kernel():
+    """The general-geometry kernel (full 3x3 factor) and the box kernel agree at full size."""
+    w = W.config2()
+    op = mfmv.Operator.from_workload(w)
+    X = torch.from_numpy(w.X(16)).to(dev())
+    Yb = op.apply(X, nan_like(X))
+    op.set_launch(True, -1)
+    Yg = op.apply(X, nan_like(X))
+    torch.cuda.synchronize()
+    rel = (torch.linalg.norm(Yb - Yg, dim=0) / torch.linalg.norm(Yg, dim=0)).max().item()
+    assert rel <= TOL
