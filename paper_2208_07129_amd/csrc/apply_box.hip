@@ -28,21 +28,32 @@
 namespace mf {
 namespace {
 
-// One phase: every (vector, pencil) task w in [0, TASKS), R rounds per thread.
-// load(w, in) fills the inputs, comp(w, in, out) computes, store(w, out) writes.
+// One phase: every (vector, pencil) task w in [0, TASKS), R = ceil(TASKS/NT)
+// rounds per thread.  load(w, in) fills a round's inputs; comp(in, out) maps
+// all R rounds at once (multi-right-hand-side contractions); store(w, out)
+// writes a round.  All LDS reads of a phase are issued before any compute.
+template <int TASKS, int NT>
+struct Rounds {
+  static constexpr int R = (TASKS + NT - 1) / NT;
+  static constexpr bool EXACT = TASKS % NT == 0;
+};
 template <int TASKS, int NT, int NIN, int NOUT, class Load, class Comp, class Store>
 __device__ __forceinline__ void phase(int tid, Load load, Comp comp, Store store) {
-  constexpr int R = (TASKS + NT - 1) / NT;
-  constexpr bool EXACT = TASKS % NT == 0;
+  constexpr int R = Rounds<TASKS, NT>::R;
+  constexpr bool EXACT = Rounds<TASKS, NT>::EXACT;
   double in[R][NIN];
   double out[R][NOUT];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int w = tid + k * NT;
-    if (EXACT || k < R - 1 || w < TASKS) load(w, in[k]);
-  }
+    if (EXACT || k < R - 1 || w < TASKS) {
+      load(w, in[k]);
+    } else {
 #pragma unroll
-  for (int k = 0; k < R; ++k) comp(tid + k * NT, in[k], out[k]);
+      for (int i = 0; i < NIN; ++i) in[k][i] = 0.0;
+    }
+  }
+  comp(in, out);
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int w = tid + k * NT;
@@ -68,10 +79,16 @@ apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ o
   double* bA = lds;
   double* bB = bA + NQ3 * B;
   double* svq = bB + NQ3 * B;
-  int* smap = reinterpret_cast<int*>(svq + NQ3);
+  // per cell node: row offsets node*ldx and node*ldy, -1 for a constrained node
+  int64_t* sxo = reinterpret_cast<int64_t*>(svq + NQ3);
+  int64_t* syo = sxo + NP3;
   const int tid = threadIdx.x;
 
-  for (int i = tid; i < NP3; i += NT) smap[i] = cmap[e * NP3 + i];
+  for (int i = tid; i < NP3; i += NT) {
+    const int node = cmap[e * NP3 + i];
+    sxo[i] = node >= 0 ? (int64_t)node * ldx : -1;
+    syo[i] = node >= 0 ? (int64_t)node * ldy : -1;
+  }
   for (int i = tid; i < NQ3; i += NT) svq[i] = vq[e * NQ3 + i];
   const double g0 = geo[e * 6 + 0], g1 = geo[e * 6 + 3], g2 = geo[e * 6 + 5];
   __syncthreads();
@@ -80,14 +97,19 @@ apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ o
   phase<NP2 * B, NT, NP, NQ>(
       tid,
       [&](int w, double (&r)[NP]) {
+        // branch-free: invalid lanes (constrained node, column past nvec) read
+        // X[0] and select zero
         const int b = w % B, pen = w / B, v = v0 + b;
+        const bool vok = v < nvec;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-          const int node = smap[pen * NP + i];
-          r[i] = (node >= 0 && v < nvec) ? X[(int64_t)node * ldx + v] : 0.0;
+          const int64_t off = sxo[pen * NP + i];
+          const bool ok = vok && off >= 0;
+          const double x = X[ok ? off + v : 0];
+          r[i] = ok ? x : 0.0;
         }
       },
-      [&](int, double (&r)[NP], double (&o)[NQ]) { matvec<Nf, NQ, NP, false, NP>(r, o); },
+      [&](auto& r, auto& o) { matvec_multi<Nf, NQ, NP, false, NP>(r, o); },
       [&](int w, double (&o)[NQ]) {
         const int b = w % B, pen = w / B;
 #pragma unroll
@@ -106,7 +128,7 @@ apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ o
 #pragma unroll
           for (int i = 0; i < NP; ++i) r[i] = bA[(base + i * PI::STRIDE) * B + b];
         },
-        [&](int, double (&r)[NP], double (&o)[NQ]) { matvec<Nf, NQ, NP, false, NP>(r, o); },
+        [&](auto& r, auto& o) { matvec_multi<Nf, NQ, NP, false, NP>(r, o); },
         [&](int w, double (&o)[NQ]) {
           const int b = w % B, base = PO::base(w / B);
 #pragma unroll
@@ -123,7 +145,7 @@ apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ o
 #pragma unroll
           for (int i = 0; i < NP; ++i) r[i] = bB[(pen + i * NQ2) * B + b];
         },
-        [&](int, double (&r)[NP], double (&o)[NQ]) { matvec<Nf, NQ, NP, false, NP>(r, o); },
+        [&](auto& r, auto& o) { matvec_multi<Nf, NQ, NP, false, NP>(r, o); },
         [&](int w, double (&o)[NQ]) {
           const int b = w % B, pen = w / B;
 #pragma unroll
@@ -140,10 +162,11 @@ apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ o
 #pragma unroll
         for (int k = 0; k < NQ; ++k) t[k] = bA[(pen * NQ + k) * B + b];
       },
-      [&](int, double (&t)[NQ], double (&o)[NQ]) {
-        matvec<Lf, NQ, NQ, false, NQ>(t, o);
+      [&](auto& t, auto& o) {
+        matvec_multi<Lf, NQ, NQ, false, NQ>(t, o);
+        for (auto& ok : o)
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) o[k] *= g0;
+          for (int k = 0; k < NQ; ++k) ok[k] *= g0;
       },
       [&](int w, double (&o)[NQ]) {
         const int b = w % B, pen = w / B;
@@ -164,13 +187,18 @@ apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ o
           t[NQ + k] = bB[(base + k * NQ) * B + b];
         }
       },
-      [&](int, double (&t)[2 * NQ], double (&o)[NQ]) {
-        double u[NQ];
+      [&](auto& t, auto& o) {
+        constexpr int R = sizeof(t) / sizeof(t[0]);
+        double u[R][NQ];
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) u[k] = t[k];
-        matvec<Lf, NQ, NQ, false, NQ>(u, o);
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) o[k] = fma(g1, o[k], t[NQ + k]);
+          for (int k = 0; k < NQ; ++k) u[r][k] = t[r][k];
+        matvec_multi<Lf, NQ, NQ, false, NQ>(u, o);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int k = 0; k < NQ; ++k) o[r][k] = fma(g1, o[r][k], t[r][NQ + k]);
       },
       [&](int w, double (&o)[NQ]) {
         const int b = w % B, pen = w / B;
@@ -193,14 +221,20 @@ apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ o
           t[2 * NQ + k] = svq[pen + k * NQ2];
         }
       },
-      [&](int, double (&t)[3 * NQ], double (&o)[NP]) {
-        double u[NQ], l[NQ];
+      [&](auto& t, auto& o) {
+        constexpr int R = sizeof(t) / sizeof(t[0]);
+        double u[R][NQ], l[R][NQ];
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) u[k] = t[k];
-        matvec<Lf, NQ, NQ, false, NQ>(u, l);
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) u[k] = fma(t[2 * NQ + k], t[k], fma(g2, l[k], t[NQ + k]));
-        matvec<Nf, NP, NQ, true, NP>(u, o);
+          for (int k = 0; k < NQ; ++k) u[r][k] = t[r][k];
+        matvec_multi<Lf, NQ, NQ, false, NQ>(u, l);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int k = 0; k < NQ; ++k)
+            u[r][k] = fma(t[r][2 * NQ + k], t[r][k], fma(g2, l[r][k], t[r][NQ + k]));
+        matvec_multi<Nf, NP, NQ, true, NP>(u, o);
       },
       [&](int w, double (&o)[NP]) {
         const int b = w % B, pen = w / B;
@@ -220,7 +254,7 @@ apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ o
 #pragma unroll
           for (int k = 0; k < NQ; ++k) t[k] = bA[(base + k * PI::STRIDE) * B + b];
         },
-        [&](int, double (&t)[NQ], double (&o)[NP]) { matvec<Nf, NP, NQ, true, NP>(t, o); },
+        [&](auto& t, auto& o) { matvec_multi<Nf, NP, NQ, true, NP>(t, o); },
         [&](int w, double (&o)[NP]) {
           const int b = w % B, base = PO::base(w / B);
 #pragma unroll
@@ -237,7 +271,7 @@ apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ o
 #pragma unroll
         for (int k = 0; k < NQ; ++k) t[k] = bB[(pen * NQ + k) * B + b];
       },
-      [&](int, double (&t)[NQ], double (&o)[NP]) { matvec<Nf, NP, NQ, true, NP>(t, o); },
+      [&](auto& t, auto& o) { matvec_multi<Nf, NP, NQ, true, NP>(t, o); },
       [&](int w, double (&o)[NP]) {
         const int b = w % B, pen = w / B, v = v0 + b;
         if (v >= nvec) return;
@@ -245,9 +279,9 @@ apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ o
         const bool inner_pen = i2 > 0 && i2 < NP - 1 && i3 > 0 && i3 < NP - 1;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-          const int node = smap[pen * NP + i];
-          if (node < 0) continue;
-          double* dst = Y + (int64_t)node * ldy + v;
+          const int64_t off = syo[pen * NP + i];
+          if (off < 0) continue;
+          double* dst = Y + off + v;
           if (i > 0 && i < NP - 1 && inner_pen) {
             if (ACCUM) *dst += o[i];
             else *dst = o[i];
@@ -297,6 +331,10 @@ hipError_t launch_pq(const ApplyLaunch& a, hipStream_t s) {
   if (!done) err = try_cfg<NP, NQ, 1>(a, s, done);
   if (!done) err = try_cfg<NP, NQ, 2>(a, s, done);
   if (!done) err = try_cfg<NP, NQ, 3>(a, s, done);
+  if (!done) err = try_cfg<NP, NQ, 4>(a, s, done);
+  if (!done) err = try_cfg<NP, NQ, 5>(a, s, done);
+  if (!done) err = try_cfg<NP, NQ, 6>(a, s, done);
+  if (!done) err = try_cfg<NP, NQ, 7>(a, s, done);
   return done ? err : hipErrorInvalidValue;
 }
 

@@ -18,14 +18,22 @@ __global__ void zero_rows_kernel(double* __restrict__ Y, int64_t nrows, int ncol
   }
 }
 
-__global__ void zero_shared_rows_kernel(double* __restrict__ Y, int64_t Nx, int64_t Ny,
-                                        int64_t Nz, int p, int ncols, int64_t ld) {
-  const int64_t total = Nx * Ny * Nz * ncols;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / ncols, c = i % ncols;
-    const int64_t gx = r % Nx, gy = (r / Nx) % Ny, gz = r / (Nx * Ny);
-    if (gx % p == 0 || gy % p == 0 || gz % p == 0) Y[r * ld + c] = 0.0;
+// One workgroup per node line (gy, gz) of the Nx x Ny x Nz grid.  A line on a
+// cell-face plane (gy or gz a multiple of p) is zeroed whole; otherwise only the
+// rows gx = 0, p, 2p, ... are.  Each wavefront takes rows, lanes take columns,
+// so stores are contiguous and no per-element index arithmetic is needed.
+// Rows of cell-interior nodes are skipped: the box kernel writes them.
+__global__ void zero_shared_rows_kernel(double* __restrict__ Y, int Nx, int Ny, int p, int ncols,
+                                        int64_t ld) {
+  const int line = blockIdx.x;
+  const int gy = line % Ny, gz = line / Ny;
+  const bool full = (gy % p == 0) || (gz % p == 0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double* base = Y + (int64_t)line * Nx * ld;
+  const int step = full ? 1 : p;
+  for (int gx = wave * step; gx < Nx; gx += nw * step) {
+    double* row = base + (int64_t)gx * ld;
+    for (int c = lane; c < ncols; c += 64) row[c] = 0.0;
   }
 }
 
@@ -33,12 +41,10 @@ __global__ void zero_shared_rows_kernel(double* __restrict__ Y, int64_t Nx, int6
 
 hipError_t launch_zero_shared_rows(double* Y, const int64_t nodes[3], int p, int ncols, int64_t ld,
                                    hipStream_t s) {
-  const int64_t total = nodes[0] * nodes[1] * nodes[2] * ncols;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(zero_shared_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, Y, nodes[0],
-                     nodes[1], nodes[2], p, ncols, ld);
+  const int64_t lines = nodes[1] * nodes[2];
+  if (lines < 1) return hipSuccess;
+  hipLaunchKernelGGL(zero_shared_rows_kernel, dim3((unsigned)lines), dim3(256), 0, s, Y,
+                     (int)nodes[0], (int)nodes[1], p, ncols, ld);
   return hipGetLastError();
 }
 

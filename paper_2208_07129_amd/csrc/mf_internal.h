@@ -13,7 +13,7 @@ namespace mf {
 
 constexpr int kMaxP = 10;
 constexpr int kMaxQExtra = 3;  // q in [p+1, p+3]
-constexpr int kBoxCfgs = 4;    // launch shapes of the box-cell kernel
+constexpr int kBoxCfgs = 8;    // launch shapes of the box-cell kernel
 
 // Error reporting: every entry point returns a status and stores a message.
 int fail(int status, const std::string& msg);

@@ -69,6 +69,53 @@ __device__ __forceinline__ void matvec(const T (&in)[NIN], T (&out)[NOUT]) {
   mvec<M, TR, LD>(in, out, std::make_integer_sequence<int, NOUT>{});
 }
 
+// Multi-right-hand-side form: out[r][o] = sum_i M(o, i) in[r][i] for R pencils.
+// Each coefficient is formed once and used R times back to back (the R
+// accumulation chains are independent), which keeps the scalar constants
+// short-lived instead of parked in registers for the whole phase.
+template <class M, bool TR, int LD, int O, int I>
+constexpr double coef() {
+  return M::template at<(TR ? I * LD + O : O * LD + I)>;
+}
+template <class M, bool TR, int LD, int R, int O, int I, int FIRST, typename T, int NIN, int NOUT>
+__device__ __forceinline__ void mrhs_term(const T (&in)[R][NIN], T (&out)[R][NOUT]) {
+  constexpr double c = coef<M, TR, LD, O, I>();
+  if constexpr (I == FIRST) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r][O] = T(c) * in[r][I];
+  } else if constexpr (c != 0.0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r][O] = fma(T(c), in[r][I], out[r][O]);
+  }
+}
+template <class M, bool TR, int LD, int O, int... I>
+constexpr int first_nonzero(std::integer_sequence<int, I...>) {
+  constexpr int n = sizeof...(I);
+  constexpr double cs[n] = {coef<M, TR, LD, O, I>()...};
+  for (int i = 0; i < n; ++i)
+    if (cs[i] != 0.0) return i;
+  return 0;
+}
+template <class M, bool TR, int LD, int R, int O, typename T, int NIN, int NOUT, int... I>
+__device__ __forceinline__ void mrhs_row(const T (&in)[R][NIN], T (&out)[R][NOUT],
+                                         std::integer_sequence<int, I...> seq) {
+  constexpr int FIRST = first_nonzero<M, TR, LD, O>(seq);
+  (mrhs_term<M, TR, LD, R, O, I, FIRST>(in, out), ...);
+}
+template <class M, bool TR, int LD, int R, typename T, int NIN, int NOUT, int... O>
+__device__ __forceinline__ void mrhs_all(const T (&in)[R][NIN], T (&out)[R][NOUT],
+                                         std::integer_sequence<int, O...>) {
+  (mrhs_row<M, TR, LD, R, O>(in, out, std::make_integer_sequence<int, NIN>{}), ...);
+}
+// Multi-right-hand-side form: out[r][o] = sum_i M(o, i) in[r][i] for R pencils.
+// Each coefficient is formed once and used R times back to back (the R
+// accumulation chains are independent); the first nonzero term of a row starts
+// the sum with a multiply, exact zeros are skipped.
+template <class M, int NOUT, int NIN, bool TR, int LD, int R, typename T>
+__device__ __forceinline__ void matvec_multi(const T (&in)[R][NIN], T (&out)[R][NOUT]) {
+  mrhs_all<M, TR, LD, R>(in, out, std::make_integer_sequence<int, NOUT>{});
+}
+
 // Pencil geometry of an (S0, S1, S2) array for a contraction along DIR.
 template <int DIR, int S0, int S1, int S2>
 struct Pencils {
@@ -131,10 +178,11 @@ constexpr bool f64_tile_built(int np, int nq, int b) {
 
 constexpr size_t kLdsMax = 160 * 1024;     // LDS per workgroup on gfx950
 
-// LDS bytes of the box-cell kernel: two cell buffers, the scaled potential, the map.
+// LDS bytes of the box-cell kernel: two cell buffers, the scaled potential, and
+// the 64-bit X and Y row offsets of the cell's nodes.
 constexpr size_t box_lds_bytes(int np, int nq, int vtile) {
   return (2 * (size_t)nq * nq * nq * vtile + (size_t)nq * nq * nq) * sizeof(double) +
-         (size_t)np * np * np * sizeof(int);
+         2 * (size_t)np * np * np * sizeof(int64_t);
 }
 
 // Launch shapes of the box-cell kernel: (vector tile B, threads NT).  B = 8 and
@@ -144,19 +192,25 @@ struct BoxCfg {
   int B, NT;
 };
 constexpr BoxCfg box_cfg(int np, int nq, int idx) {
-  // 0: default (largest of 16/8/4/2/1 within 80 KiB, two workgroups per CU), 256 threads
+  // 0: default: B = 8 with 512 threads (the fastest shape measured for p = 6
+  //    and p = 8), else the largest of 4/2/1 that fits, 256 threads
   // 1: B = 8, 256 threads;  2: B = 16, 512 threads;  3: B = 4, 128 threads
+  // 4: B = 8, 512 threads;  5: B = 16, 256 threads;  6: B = 8, 128 threads;
+  // 7: B = 4, 256 threads
   BoxCfg c{0, 256};
   if (idx == 0) {
-    for (int b = 16; b >= 1; b /= 2)
-      if (box_lds_bytes(np, nq, b) <= 80 * 1024) return BoxCfg{b, 256};
-    for (int b = 16; b >= 1; b /= 2)
+    if (box_lds_bytes(np, nq, 8) <= 80 * 1024) return BoxCfg{8, 512};
+    for (int b = 4; b >= 1; b /= 2)
       if (box_lds_bytes(np, nq, b) <= kLdsMax) return BoxCfg{b, 256};
     return c;
   }
   if (idx == 1) c = BoxCfg{8, 256};
   if (idx == 2) c = BoxCfg{16, 512};
   if (idx == 3) c = BoxCfg{4, 128};
+  if (idx == 4) c = BoxCfg{8, 512};
+  if (idx == 5) c = BoxCfg{16, 256};
+  if (idx == 6) c = BoxCfg{8, 128};
+  if (idx == 7) c = BoxCfg{4, 256};
   if (box_lds_bytes(np, nq, c.B) > kLdsMax) c.B = 0;
   return c;
 }
