@@ -41,7 +41,7 @@ def cmd_stats(a):
     out = ["| kernel | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|"]
     for r in rows:
         name = r["Name"]
-        short = name.split("(")[0].replace("mf::(anonymous namespace)::", "").replace("void ", "")
+        short = name.replace("mf::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
         out.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
     text = "\n".join(out)
