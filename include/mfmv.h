@@ -139,7 +139,11 @@ int mf_operator_info(const mf_operator* op, int64_t* ndofs, int64_t* ncells, int
  *   Y: device, ndofs rows, row stride ldy >= nvec; constrained rows are
  *      written as zero (the action of C^T).  Y must not overlap X.
  *   prec: MF_FP64 evaluates every step in FP64 (FP64 atomic assembly).
- *         MF_FP32_MFMA / MF_BF16_MFMA: see mf_precision.
+ *         MF_FP32_MFMA / MF_BF16_MFMA: the sum-factorised contractions run on
+ *         the matrix cores (FP32 operands, or BF16 operands; FP32
+ *         accumulation), cell arrays are FP32, and each (cell, column) is
+ *         scaled by a power of two before the conversion and unscaled before
+ *         the FP64 assembly.  Built for axis-aligned cells only.
  * Stream-ordered on `stream`; allocates nothing, does not synchronise.
  * Errors: MF_ERR_ARG (null, nvec < 1, ld < nvec, overlap), MF_ERR_UNSUPPORTED
  * (precision not available for this p, q), MF_ERR_HIP (launch failure). */
@@ -167,6 +171,10 @@ int mf_zero(double* Y, int64_t nrows, int ncols, int64_t ld, void* stream);
  * not fit the LDS for this p, q). */
 int mf_set_launch(mf_operator* op, int general, int cfg);
 
+/* Launch shape of the mixed-precision kernel, 0..3, or -1 for the built-in
+ * choice by column count.  Errors as mf_set_launch. */
+int mf_set_launch_mixed(mf_operator* op, int cfg);
+
 /* Per-launch timing for diagnostics and benchmarks.  mf_timing(op, slots)
  * (slots > 0) makes every following mf_apply / mf_apply_add on this operator
  * record HIP events on its stream around the zero fill and around the fused
@@ -177,6 +185,50 @@ int mf_set_launch(mf_operator* op, int general, int cfg);
  * ring.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
 int mf_timing(mf_operator* op, int slots);
 int mf_timing_read(mf_operator* op, int* count, double* zero_ms, double* kernel_ms);
+
+/* ------------------------------------------------------------- batches ---- */
+
+/* A batch applies a list of operators, each to its own multivector,
+ *     Y_i := A_i X_i,  i = 0 .. nops-1,
+ * in one persistent launch: the (cell, column-tile) work items of all
+ * operators form one list (heaviest degree first) that a grid sized to the
+ * device's resident capacity drains through a global counter.  This is the
+ * single launch over every (cell, batch) pair of eq. basempigpu widened to
+ * several meshes, degrees and column counts.  Supported operators: axis-aligned
+ * cells, q = p + 1, p in [2, 8] (MF_ERR_UNSUPPORTED otherwise); at most 64 per
+ * batch.  The batch references the operators: they must outlive it.  */
+typedef struct mf_batch mf_batch;
+
+/* nvec[i]: columns of X_i / Y_i; prec: as mf_apply.  Allocates the work table
+ * and counter on the current device.  Errors: MF_ERR_ARG, MF_ERR_UNSUPPORTED,
+ * MF_ERR_HIP. */
+int mf_batch_create(int nops, mf_operator* const* ops, const int* nvec, int prec, mf_batch** out);
+void mf_batch_destroy(mf_batch* b);
+
+/* Launch shape of the persistent kernel, 0..2 (see the tuner): 0 = 512 threads
+ * with the largest column tile per degree within 80 KiB of LDS, 1 = 512
+ * threads with FP64 tiles of 8 (mixed 16), 2 = 256 threads with FP64 tiles of 4
+ * (mixed 8).  Rebuilds the work table (synchronous copy). */
+int mf_batch_set_launch(mf_batch* b, int cfg);
+
+/* Y_i := A_i X_i for every operator (arrays of nops device pointers in the
+ * caller's operator order; ldx / ldy may be NULL for ld = nvec).  Enqueues a
+ * counter reset, the zero fill of every Y_i's cell-face rows and the
+ * persistent kernel on `stream`; allocates nothing.  Outputs must not overlap
+ * each other or any input.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+int mf_batch_apply(mf_batch* b, const double* const* X, double* const* Y, const int64_t* ldx,
+                   const int64_t* ldy, void* stream);
+
+/* Capture the launches of mf_batch_apply for these X / Y into a HIP graph
+ * (stream must not be NULL) and keep its executable form; mf_batch_replay then
+ * launches the graph on a stream.  The graph is bound to the pointers given
+ * here; capture again for other buffers.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+int mf_batch_capture(mf_batch* b, const double* const* X, double* const* Y, const int64_t* ldx,
+                     const int64_t* ldy, void* stream);
+int mf_batch_replay(mf_batch* b, void* stream);
+
+/* Work items, launch shape and grid size of the batch (outputs may be NULL). */
+int mf_batch_info(const mf_batch* b, int64_t* items, int* cfg, int* grid);
 
 /* Message of the last error on this thread ("" if none). */
 const char* mf_last_error(void);

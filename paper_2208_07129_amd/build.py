@@ -39,12 +39,18 @@ def jobs():
     """(source, object, extra flags) for every translation unit."""
     out = [
         ("capi.cpp", "capi.o", []),
+        ("capi_batch.cpp", "capi_batch.o", []),
         ("host_setup.cpp", "host_setup.o", []),
         ("dispatch.hip", "dispatch.o", []),
     ]
     for p in range(1, MAX_P + 1):
         out.append(("apply_f64.hip", f"apply_f64_p{p}.o", [f"-DMF_P={p}"]))
         out.append(("apply_box.hip", f"apply_box_p{p}.o", [f"-DMF_P={p}"]))
+        out.append(("apply_mixed.hip", f"apply_mixed_p{p}.o", [f"-DMF_P={p}"]))
+    for prec in range(3):
+        for cfg in range(3):
+            out.append(("apply_batched.hip", f"apply_batched_{prec}_{cfg}.o",
+                        [f"-DMF_BPREC={prec}", f"-DMF_BCFG={cfg}"]))
     return out
 
 

@@ -285,7 +285,11 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
   const size_t xb = ((op->ndofs - 1) * ldx + nvec) * sizeof(double);
   const size_t yb = ((op->ndofs - 1) * ldy + nvec) * sizeof(double);
   if (overlaps(X, xb, Y, yb)) return fail(MF_ERR_ARG, "X and Y overlap");
-  if (prec != MF_FP64) return fail(MF_ERR_UNSUPPORTED, "precision not available");
+  if (prec != MF_FP64 && prec != MF_FP32_MFMA && prec != MF_BF16_MFMA)
+    return fail(MF_ERR_UNSUPPORTED, "unknown precision");
+  const bool mixed = prec != MF_FP64;
+  if (mixed && !op->box)
+    return fail(MF_ERR_UNSUPPORTED, "mixed precision is built for axis-aligned cells only");
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   ApplyLaunch a{};
@@ -301,7 +305,10 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
   a.nvec = nvec;
   a.threads = 256;
   a.vtile = choose_vtile_f64(op->np, op->nq, nvec);
-  a.cfg = op->cfg >= 0 ? op->cfg : choose_cfg_box(op->np, op->nq, nvec);
+  if (mixed)
+    a.cfg = op->mcfg >= 0 ? op->mcfg : choose_cfg_mixed(op->np, op->nq, nvec);
+  else
+    a.cfg = op->cfg >= 0 ? op->cfg : choose_cfg_box(op->np, op->nq, nvec);
   a.accumulate = accumulate;
 
   hipEvent_t* ev = nullptr;
@@ -318,7 +325,8 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
     if (err != hipSuccess) return hip_fail(err, "zero kernel launch");
   }
   if (ev) (void)hipEventRecord(ev[1], s);
-  err = op->box ? launch_apply_box(*op, a, s) : launch_apply_f64(*op, a, s);
+  err = mixed ? launch_apply_mixed(*op, a, prec, s)
+              : (op->box ? launch_apply_box(*op, a, s) : launch_apply_f64(*op, a, s));
   if (err != hipSuccess) return hip_fail(err, "apply kernel launch");
   if (ev) (void)hipEventRecord(ev[2], s);
   return MF_OK;
@@ -342,6 +350,16 @@ int mf_set_launch(mf_operator* handle, int general, int cfg) {
     return fail(MF_ERR_UNSUPPORTED, "launch shape does not fit this (p, q)");
   if (general) op->box = false;
   op->cfg = cfg;
+  return MF_OK;
+}
+
+int mf_set_launch_mixed(mf_operator* handle, int cfg) {
+  if (!handle) return fail(MF_ERR_ARG, "operator is NULL");
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  if (cfg < -1 || cfg >= kMixedCfgs) return fail(MF_ERR_ARG, "cfg out of range");
+  if (cfg >= 0 && !apply_mixed_supported(op->p, op->q, cfg))
+    return fail(MF_ERR_UNSUPPORTED, "launch shape does not fit this (p, q)");
+  op->mcfg = cfg;
   return MF_OK;
 }
 

@@ -37,7 +37,63 @@ __global__ void zero_shared_rows_kernel(double* __restrict__ Y, int Nx, int Ny, 
   }
 }
 
+// Batched form: one workgroup per node line of any operator of the batch.
+__global__ void batch_zero_kernel(const BatchOp* __restrict__ ops, int nops, BatchPtrs ptrs) {
+  const int64_t g = blockIdx.x;
+  int o = 0;
+  while (o + 1 < nops && ops[o + 1].line_begin <= g) ++o;
+  const BatchOp& op = ops[o];
+  const int line = (int)(g - op.line_begin);
+  const int Nx = op.nodes[0], Ny = op.nodes[1], p = op.p;
+  const int gy = line % Ny, gz = line / Ny;
+  const bool full = (gy % p == 0) || (gz % p == 0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int64_t ld = ptrs.ldy[o];
+  const int ncols = ptrs.nvec[o];
+  double* base = ptrs.Y[o] + (int64_t)line * Nx * ld;
+  const int step = full ? 1 : p;
+  for (int gx = wave * step; gx < Nx; gx += nw * step) {
+    double* row = base + (int64_t)gx * ld;
+    for (int c = lane; c < ncols; c += 64) row[c] = 0.0;
+  }
+}
+
+__global__ void reset_counter_kernel(int* counter) { *counter = 0; }
+
 }  // namespace
+
+hipError_t launch_batch_zero(const BatchOp* ops, int nops, const BatchPtrs& ptrs, int64_t lines,
+                             hipStream_t s) {
+  if (lines < 1) return hipSuccess;
+  hipLaunchKernelGGL(batch_zero_kernel, dim3((unsigned)lines), dim3(256), 0, s, ops, nops, ptrs);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(int* counter, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched(int prec, int bcfg, const BatchOp* ops, int nops, int64_t total,
+                          int* counter, const BatchPtrs& ptrs, int grid, hipStream_t s) {
+#define MF_BATCH_CASE(P, C) \
+  if (prec == P && bcfg == C) return launch_batched_kernel<P, C>(ops, nops, total, counter, ptrs, grid, s);
+  MF_BATCH_CASE(MF_FP64, 0) MF_BATCH_CASE(MF_FP64, 1) MF_BATCH_CASE(MF_FP64, 2)
+  MF_BATCH_CASE(MF_FP32_MFMA, 0) MF_BATCH_CASE(MF_FP32_MFMA, 1) MF_BATCH_CASE(MF_FP32_MFMA, 2)
+  MF_BATCH_CASE(MF_BF16_MFMA, 0) MF_BATCH_CASE(MF_BF16_MFMA, 1) MF_BATCH_CASE(MF_BF16_MFMA, 2)
+#undef MF_BATCH_CASE
+  return hipErrorInvalidValue;
+}
+
+int batched_blocks_per_cu(int prec, int bcfg) {
+#define MF_BATCH_CASE(P, C) \
+  if (prec == P && bcfg == C) return batched_occupancy<P, C>();
+  MF_BATCH_CASE(MF_FP64, 0) MF_BATCH_CASE(MF_FP64, 1) MF_BATCH_CASE(MF_FP64, 2)
+  MF_BATCH_CASE(MF_FP32_MFMA, 0) MF_BATCH_CASE(MF_FP32_MFMA, 1) MF_BATCH_CASE(MF_FP32_MFMA, 2)
+  MF_BATCH_CASE(MF_BF16_MFMA, 0) MF_BATCH_CASE(MF_BF16_MFMA, 1) MF_BATCH_CASE(MF_BF16_MFMA, 2)
+#undef MF_BATCH_CASE
+  return 0;
+}
 
 hipError_t launch_zero_shared_rows(double* Y, const int64_t nodes[3], int p, int ncols, int64_t ld,
                                    hipStream_t s) {
@@ -67,6 +123,42 @@ int choose_cfg_box(int np, int nq, int nvec) {
     }
   }
   return best;
+}
+
+bool apply_mixed_supported(int p, int q, int cfg) {
+  if (p < 1 || p > kMaxP || q < p + 1 || q > p + kMaxQExtra || cfg < 0 || cfg >= kMixedCfgs)
+    return false;
+  return mixed_cfg(p + 1, q, cfg).B > 0;
+}
+
+int choose_cfg_mixed(int np, int nq, int nvec) {
+  const int b0 = mixed_cfg(np, nq, 0).B;
+  if (nvec >= b0) return 0;
+  int best = 0, bestB = b0;
+  for (int c = 1; c < kMixedCfgs; ++c) {
+    const int b = mixed_cfg(np, nq, c).B;
+    if (b >= nvec && b < bestB) {
+      best = c;
+      bestB = b;
+    }
+  }
+  return best;
+}
+
+hipError_t launch_apply_mixed(const Operator& op, const ApplyLaunch& a, int prec, hipStream_t s) {
+  switch (op.p) {
+    case 1: return launch_apply_mixed_p<1>(op, a, prec, s);
+    case 2: return launch_apply_mixed_p<2>(op, a, prec, s);
+    case 3: return launch_apply_mixed_p<3>(op, a, prec, s);
+    case 4: return launch_apply_mixed_p<4>(op, a, prec, s);
+    case 5: return launch_apply_mixed_p<5>(op, a, prec, s);
+    case 6: return launch_apply_mixed_p<6>(op, a, prec, s);
+    case 7: return launch_apply_mixed_p<7>(op, a, prec, s);
+    case 8: return launch_apply_mixed_p<8>(op, a, prec, s);
+    case 9: return launch_apply_mixed_p<9>(op, a, prec, s);
+    case 10: return launch_apply_mixed_p<10>(op, a, prec, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_apply_box(const Operator& op, const ApplyLaunch& a, hipStream_t s) {

@@ -14,6 +14,9 @@ namespace mf {
 constexpr int kMaxP = 10;
 constexpr int kMaxQExtra = 3;  // q in [p+1, p+3]
 constexpr int kBoxCfgs = 8;    // launch shapes of the box-cell kernel
+constexpr int kMixedCfgs = 4;  // launch shapes of the mixed-precision kernel
+constexpr int kBatchCfgs = 3;  // launch shapes of the persistent batched kernel
+constexpr int kMaxBatch = 64;  // operators per batch
 
 // Error reporting: every entry point returns a status and stores a message.
 int fail(int status, const std::string& msg);
@@ -52,6 +55,7 @@ struct Operator {
   int64_t nodes[3] = {0, 0, 0};  // nodes per direction of the full numbering
   bool box = false;           // every cell axis-aligned: diagonal 3x3 factor
   int cfg = 0;                // launch shape of the box kernel (tuned or default)
+  int mcfg = -1;              // launch shape of the mixed-precision kernel
   int32_t* d_map = nullptr;   // E x np^3, -1 = constrained
   int32_t* d_order = nullptr; // E: processing order of the cells
   double* d_geo = nullptr;    // E x 6: mu det J (J^-1 J^-T), (00,01,02,11,12,22)
@@ -80,6 +84,35 @@ struct ApplyLaunch {
   bool accumulate;
 };
 
+// One operator of a batch, as the persistent kernel sees it (device array).
+struct BatchOp {
+  const int32_t* map;
+  const int32_t* order;
+  const double* geo;
+  const double* vq;
+  int64_t item_begin;  // first work item of this operator in the batch's list
+  int64_t ncells;
+  int ntiles;          // column tiles
+  int64_t line_begin;  // first node line (gy, gz) of this operator in the batch's zero fill
+  int p;
+  int nodes[3];
+};
+// Per-call multivector pointers, passed by value in the kernel arguments.
+struct BatchPtrs {
+  const double* X[kMaxBatch];
+  double* Y[kMaxBatch];
+  int64_t ldx[kMaxBatch];
+  int64_t ldy[kMaxBatch];
+  int nvec[kMaxBatch];
+};
+hipError_t launch_batched(int prec, int bcfg, const BatchOp* ops, int nops, int64_t total,
+                          int* counter, const BatchPtrs& ptrs, int grid, hipStream_t s);
+int batched_blocks_per_cu(int prec, int bcfg);
+// Batched shared-row zero fill and counter reset (kernels, graph-capturable).
+hipError_t launch_batch_zero(const BatchOp* ops, int nops, const BatchPtrs& ptrs, int64_t lines,
+                             hipStream_t s);
+hipError_t launch_reset_counter(int* counter, hipStream_t s);
+
 // FP64 fused apply; returns hipSuccess or the launch error.
 hipError_t launch_apply_f64(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 // Zero rows [0, nrows) x columns [0, ncols) of a row-major array with stride ld.
@@ -91,6 +124,10 @@ hipError_t launch_zero_shared_rows(double* Y, const int64_t nodes[3], int p, int
 // FP64 fused apply for box cells.
 hipError_t launch_apply_box(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 bool apply_box_supported(int p, int q, int cfg);
+// Mixed-precision (FP32 / BF16 matrix-core) apply for box cells.
+hipError_t launch_apply_mixed(const Operator& op, const ApplyLaunch& a, int prec, hipStream_t s);
+bool apply_mixed_supported(int p, int q, int cfg);
+int choose_cfg_mixed(int np, int nq, int nvec);
 int choose_cfg_box(int np, int nq, int nvec);
 // Processing order of the cells: 8 blocks by recursive bisection (one per XCD),
 // Morton order inside each block.

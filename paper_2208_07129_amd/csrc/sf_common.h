@@ -215,8 +215,64 @@ constexpr BoxCfg box_cfg(int np, int nq, int idx) {
   return c;
 }
 
+// LDS bytes of the mixed-precision kernel: 64-bit X and Y row offsets, two FP32
+// cell buffers, the FP32 scaled potential and one exponent per column.
+constexpr size_t mixed_lds_bytes(int np, int nq, int vtile) {
+  return 2 * (size_t)np * np * np * sizeof(int64_t) +
+         (2 * (size_t)nq * nq * nq * vtile + (size_t)nq * nq * nq) * sizeof(float) +
+         (size_t)vtile * sizeof(int);
+}
+// Launch shapes of the mixed-precision kernel (B columns, NT threads):
+// 0: default B = 16, 512 threads (B = 8 if that exceeds 80 KiB of LDS);
+// 1: B = 16, 256;  2: B = 8, 256;  3: B = 8, 512.
+constexpr BoxCfg mixed_cfg(int np, int nq, int idx) {
+  BoxCfg c{0, 512};
+  if (idx == 0) {
+    if (mixed_lds_bytes(np, nq, 16) <= 80 * 1024) return BoxCfg{16, 512};
+    for (int b = 8; b >= 1; b /= 2)
+      if (mixed_lds_bytes(np, nq, b) <= kLdsMax) return BoxCfg{b, b >= 8 ? 512 : 256};
+    return c;
+  }
+  if (idx == 1) c = BoxCfg{16, 256};
+  if (idx == 2) c = BoxCfg{8, 256};
+  if (idx == 3) c = BoxCfg{8, 512};
+  if (mixed_lds_bytes(np, nq, c.B) > kLdsMax) c.B = 0;
+  return c;
+}
+
+// ---------------------------------------------------------------- batches
+// Launch shapes of the persistent batched kernel (kinds q = p + 1, p = 2..8):
+// 0: 512 threads, the largest tile per kind within 80 KiB (FP64 8 or 4,
+//    mixed 16 or 8);  1: 512 threads, FP64 B = 8 / mixed B = 16 for every kind;
+// 2: 256 threads, FP64 B = 4 / mixed B = 8.
+constexpr int kBatchMinP = 2, kBatchMaxP = 8;
+constexpr int batch_threads(int bcfg) { return bcfg == 2 ? 256 : 512; }
+constexpr int batch_tile(int prec, int bcfg, int np, int nq) {
+  const bool f64 = prec == MF_FP64;
+  if (bcfg == 1) return f64 ? 8 : 16;
+  if (bcfg == 2) return f64 ? 4 : 8;
+  if (f64) return box_lds_bytes(np, nq, 8) <= 80 * 1024 ? 8 : 4;
+  return mixed_lds_bytes(np, nq, 16) <= 80 * 1024 ? 16 : 8;
+}
+constexpr size_t batch_lds_bytes(int prec, int bcfg) {
+  size_t m = 0;
+  for (int p = kBatchMinP; p <= kBatchMaxP; ++p) {
+    const int n = p + 1, b = batch_tile(prec, bcfg, n, n);
+    const size_t l = prec == MF_FP64 ? box_lds_bytes(n, n, b) : mixed_lds_bytes(n, n, b);
+    if (l > m) m = l;
+  }
+  return m;
+}
+template <int PREC, int BCFG>
+hipError_t launch_batched_kernel(const BatchOp* ops, int nops, int64_t total, int* counter,
+                                 const BatchPtrs& ptrs, int grid, hipStream_t s);
+template <int PREC, int BCFG>
+int batched_occupancy();
+
 template <int P>
 hipError_t launch_apply_f64_p(const Operator& op, const ApplyLaunch& a, hipStream_t s);
+template <int P>
+hipError_t launch_apply_mixed_p(const Operator& op, const ApplyLaunch& a, int prec, hipStream_t s);
 template <int P>
 hipError_t launch_apply_box_p(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 

@@ -24,7 +24,9 @@ PRECISIONS = {"fp64": MF_FP64, "fp32": MF_FP32_MFMA, "bf16": MF_BF16_MFMA}
 # Every symbol declared in include/mfmv.h.
 EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask", "mf_basis_1d",
            "mf_create_operator", "mf_destroy_operator", "mf_operator_info", "mf_apply",
-           "mf_apply_add", "mf_zero", "mf_set_launch", "mf_timing", "mf_timing_read",
+           "mf_apply_add", "mf_zero", "mf_set_launch", "mf_set_launch_mixed", "mf_timing",
+           "mf_timing_read", "mf_batch_create", "mf_batch_destroy", "mf_batch_set_launch",
+           "mf_batch_apply", "mf_batch_capture", "mf_batch_replay", "mf_batch_info",
            "mf_last_error")
 
 
@@ -64,9 +66,17 @@ def lib() -> ctypes.CDLL:
             "mf_apply_add": (I, [P, P, P, I, I64, I64, I, P]),
             "mf_zero": (I, [P, I64, I, I64, P]),
             "mf_set_launch": (I, [P, I, I]),
+            "mf_set_launch_mixed": (I, [P, I]),
             "mf_timing": (I, [P, I]),
             "mf_timing_read": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D)]),
             "mf_last_error": (ctypes.c_char_p, []),
+            "mf_batch_create": (I, [I, P, P, I, ctypes.POINTER(P)]),
+            "mf_batch_destroy": (None, [P]),
+            "mf_batch_set_launch": (I, [P, I]),
+            "mf_batch_apply": (I, [P, P, P, P, P, P]),
+            "mf_batch_capture": (I, [P, P, P, P, P, P]),
+            "mf_batch_replay": (I, [P, P]),
+            "mf_batch_info": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(I), ctypes.POINTER(I)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -182,6 +192,9 @@ class Operator:
     def set_launch(self, general: bool = False, cfg: int = -1):
         _check(lib().mf_set_launch(self._h, int(general), int(cfg)))
 
+    def set_launch_mixed(self, cfg: int = -1):
+        _check(lib().mf_set_launch_mixed(self._h, int(cfg)))
+
     def timing(self, slots: int):
         _check(lib().mf_timing(self._h, int(slots)))
 
@@ -214,3 +227,60 @@ class Operator:
 
 def zero_ptr(Y_ptr: int, nrows: int, ncols: int, ld: int, stream=None):
     _check(lib().mf_zero(Y_ptr, nrows, ncols, ld, _stream_ptr(stream)))
+
+
+class Batch:
+    """Y_i := A_i X_i for a list of operators in one persistent launch (see mf_batch_*)."""
+
+    def __init__(self, ops: Sequence[Operator], nvec: Sequence[int], precision: str = "fp64"):
+        self._h = ctypes.c_void_p()
+        self.ops = list(ops)
+        self.nvec = [int(v) for v in nvec]
+        n = len(self.ops)
+        handles = (ctypes.c_void_p * n)(*[o._h.value for o in self.ops])
+        nv = (ctypes.c_int * n)(*self.nvec)
+        _check(lib().mf_batch_create(n, handles, nv, PRECISIONS[precision], ctypes.byref(self._h)))
+        self._keep = (handles, nv)
+
+    def close(self):
+        if self._h:
+            lib().mf_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_launch(self, cfg: int):
+        _check(lib().mf_batch_set_launch(self._h, int(cfg)))
+
+    def info(self):
+        items, cfg, grid = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().mf_batch_info(self._h, ctypes.byref(items), ctypes.byref(cfg), ctypes.byref(grid)))
+        return {"items": items.value, "cfg": cfg.value, "grid": grid.value}
+
+    def _arrays(self, Xs, Ys):
+        n = len(self.ops)
+        if len(Xs) != n or len(Ys) != n:
+            raise ValueError("one X and one Y per operator")
+        for X, Y, op, nv in zip(Xs, Ys, self.ops, self.nvec):
+            if X.shape != (op.ndofs, nv) or Y.shape != (op.ndofs, nv) or X.stride(1) != 1 or Y.stride(1) != 1:
+                raise ValueError("X_i, Y_i must be (ndofs_i, nvec_i) with unit column stride")
+        xp = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs])
+        yp = (ctypes.c_void_p * n)(*[Y.data_ptr() for Y in Ys])
+        lx = (ctypes.c_int64 * n)(*[X.stride(0) for X in Xs])
+        ly = (ctypes.c_int64 * n)(*[Y.stride(0) for Y in Ys])
+        return xp, yp, lx, ly
+
+    def apply(self, Xs, Ys, stream=None):
+        xp, yp, lx, ly = self._arrays(Xs, Ys)
+        _check(lib().mf_batch_apply(self._h, xp, yp, lx, ly, _stream_ptr(stream)))
+
+    def capture(self, Xs, Ys, stream):
+        xp, yp, lx, ly = self._arrays(Xs, Ys)
+        _check(lib().mf_batch_capture(self._h, xp, yp, lx, ly, _stream_ptr(stream)))
+
+    def replay(self, stream=None):
+        _check(lib().mf_batch_replay(self._h, _stream_ptr(stream)))

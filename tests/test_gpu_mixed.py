@@ -1,0 +1,123 @@
+"""GPU parity of the mixed-precision apply (FP32 / BF16 matrix-core contractions,
+FP64 assembly) against the FP64 CPU oracle.
+
+Gate: FP32 per-column relative error <= 1e-6.  BF16 operands carry a unit
+roundoff of 2^-9 (about 1.95e-3) into each of the nine contraction stages;
+adding those worst-case gives about 1.8e-2, so BF16 is held to 3e-2 (measured
+errors are reported; they sit near 8e-3 on the p = 8 workload).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fe_oracle as fo
+from paper_2208_07129_amd import mfmv
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-6
+BF16_TOL = 3e-2
+
+
+def dev():
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def colrel(Y, Yref):
+    """max over columns of |Y_j - Yref_j| / |Yref_j|, each column scaled by its largest
+    reference entry first so that the norms neither overflow nor underflow."""
+    s = np.abs(Yref).max(axis=0)
+    s[s == 0.0] = 1.0
+    d, r = (Y - Yref) / s, Yref / s
+    return float((np.linalg.norm(d, axis=0) / np.linalg.norm(r, axis=0)).max())
+
+
+def vfun(x):
+    return np.sin(x[..., 0]) + x[..., 1] * x[..., 2] - 0.3
+
+
+def run(op, X, prec):
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).to(dev())
+    Yd = torch.full(Xd.shape, float("nan"), dtype=torch.float64, device=dev())
+    op.apply(Xd, Yd, precision=prec)
+    torch.cuda.synchronize()
+    return Yd.cpu().numpy()
+
+
+CASES = [
+    (2, 3, (3, 2, 2), W.BC_DIRICHLET0, 19),
+    (4, 5, (2, 2, 2), W.BC_PERIODIC, 33),
+    (6, 7, (2, 2, 2), W.BC_PERIODIC, 21),
+    (6, 8, (2, 1, 2), W.BC_NONE, 9),
+    (8, 9, (2, 1, 1), W.BC_DIRICHLET0, 17),
+]
+
+
+@pytest.mark.parametrize("p,q,n,bc,nvec", CASES)
+def test_mixed_small_meshes_every_shape(p, q, n, bc, nvec):
+    mesh = W.BoxMesh(n=n, lo=(0.0, -0.5, 0.25), hi=(1.0, 1.0, 1.5), bc=bc)
+    Vq = vfun(mfmv.quad_points(mesh, q))
+    op = mfmv.Operator(mesh, p, q, 0.5, Vq, 0.2)
+    orc = fo.Oracle(mesh, p, q, 0.5, vfun, 0.2)
+    X = np.random.default_rng(p + 10 * q).uniform(-1, 1, (orc.ndofs, nvec))
+    Yref = orc.apply(X)
+    for cfg in range(4):
+        try:
+            op.set_launch_mixed(cfg)
+        except mfmv.MfError:
+            continue
+        e32 = colrel(run(op, X, "fp32"), Yref)
+        e16 = colrel(run(op, X, "bf16"), Yref)
+        assert e32 <= FP32_TOL, (cfg, e32)
+        assert e16 <= BF16_TOL, (cfg, e16)
+        if bc == W.BC_DIRICHLET0:
+            assert np.all(run(op, X, "fp32")[orc.constrained] == 0.0)
+
+
+def test_per_column_scaling_extreme_magnitudes():
+    """Columns at 1e200 and 1e-200 are outside FP32's range; the per-(cell, column)
+    power-of-two scaling keeps their relative error at the FP32 level."""
+    mesh = W.BoxMesh(n=(2, 2, 2), bc=W.BC_PERIODIC)
+    Vq = vfun(mfmv.quad_points(mesh, 5))
+    op = mfmv.Operator(mesh, 4, 5, 0.5, Vq, 0.2)
+    orc = fo.Oracle(mesh, 4, 5, 0.5, vfun, 0.2)
+    X = np.random.default_rng(3).uniform(-1, 1, (orc.ndofs, 4))
+    X[:, 1] *= 1e200
+    X[:, 2] *= 1e-200
+    X[:, 3] = 0.0
+    Y = run(op, X, "fp32")
+    Yref = orc.apply(X)
+    assert np.all(Y[:, 3] == 0.0)
+    assert colrel(Y[:, :3], Yref[:, :3]) <= FP32_TOL
+
+
+def test_mixed_rejected_on_sheared_cells():
+    mesh = W.BoxMesh(n=(2, 2, 2), bc=W.BC_NONE,
+                     lin=np.array([[1.0, 0.3, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]))
+    op = mfmv.Operator(mesh, 2, 3, 0.5, None, 0.0)
+    X = torch.zeros((op.ndofs, 4), dtype=torch.float64, device=dev())
+    with pytest.raises(mfmv.MfError) as e:
+        op.apply(X, precision="fp32")
+    assert e.value.status == mfmv.MF_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("nvec", [16, 64])
+def test_config3_mixed_sampled_rows(nvec):
+    """Periodic unit cube 12^3, p=8, q=9: FP32 within 1e-6 of the oracle on sampled rows;
+    BF16 error reported."""
+    w = W.config3(nvec)
+    op = mfmv.Operator.from_workload(w)
+    orc = fo.Oracle(w.mesh, w.p, w.q, w.mu, w.V, w.sigma)
+    X = w.X()
+    Xd = torch.from_numpy(X).to(dev())
+    rows = np.random.default_rng(nvec).choice(orc.ndofs, 8, replace=False)
+    Yref = orc.apply_rows(X, rows)
+    idx = torch.from_numpy(rows).to(dev())
+    for prec, tol in (("fp32", FP32_TOL), ("bf16", BF16_TOL)):
+        Yd = op.apply(Xd, precision=prec)
+        Yr = Yd[idx].cpu().numpy()
+        rel = float(np.linalg.norm(Yr - Yref) / np.linalg.norm(Yref))
+        print(f"config3 nvec={nvec} {prec} sampled rel err {rel:.3e}")
+        assert rel <= tol
