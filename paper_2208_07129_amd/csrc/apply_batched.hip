@@ -36,7 +36,7 @@ __device__ __forceinline__ void run_kind(double* lds, const BatchOp& op, const B
   const int64_t e = op.order[local / op.ntiles];
   const int v0 = (int)(local % op.ntiles) * B;
   if constexpr (PREC == MF_FP64)
-    box_cell_tile<NP, NQ, B, NT, false>(lds, op.map, op.geo, op.vq, ptrs.X[o], ptrs.Y[o],
+    box_cell_tile<NP, NQ, B, 1, NT, false>(lds, op.grid, op.geo, op.vq, ptrs.X[o], ptrs.Y[o],
                                          ptrs.ldx[o], ptrs.ldy[o], ptrs.nvec[o], e, v0);
   else
     mixed_cell_tile<NP, NQ, B, NT, false, PREC>(lds, op.map, op.geo, op.vq, ptrs.X[o], ptrs.Y[o],

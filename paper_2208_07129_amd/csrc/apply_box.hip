@@ -13,9 +13,10 @@
 namespace mf {
 namespace {
 
-template <int NP, int NQ, int B, int NT, bool ACCUM>
-__global__ void __launch_bounds__(NT)
-apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ order,
+template <int NP, int NQ, int B, int C, int NT, bool ACCUM>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, NT),
+                               amdgpu_waves_per_eu(box_waves_per_eu(NP, NQ, B, NT))))
+apply_box_kernel(const GridDesc grid, const int32_t* __restrict__ order,
                  const double* __restrict__ geo, const double* __restrict__ vq,
                  const double* __restrict__ X, double* __restrict__ Y, int64_t ldx, int64_t ldy,
                  int nvec, int ntiles, int64_t nitems, int64_t chunk) {
@@ -24,24 +25,63 @@ apply_box_kernel(const int32_t* __restrict__ cmap, const int32_t* __restrict__ o
   if (item >= nitems) return;
   const int64_t e = order[item / ntiles];
   const int v0 = (int)(item % ntiles) * B;
-  box_cell_tile<NP, NQ, B, NT, ACCUM>(lds, cmap, geo, vq, X, Y, ldx, ldy, nvec, e, v0);
+  box_cell_tile<NP, NQ, B, C, NT, ACCUM>(lds, grid, geo, vq, X, Y, ldx, ldy, nvec, e, v0);
 }
 
-template <int NP, int NQ, int B, int NT, bool ACCUM>
+// Persistent grid: the workgroups of each XCD take that XCD's contiguous item
+// range in an interleaved order (box_items), so cells sharing nodes still run
+// close in time on one XCD.
+template <int NP, int NQ, int B, int C, int NT, bool ACCUM>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, NT),
+                               amdgpu_waves_per_eu(box_waves_per_eu(NP, NQ, B, NT))))
+apply_box_pers_kernel(const GridDesc grid, const int32_t* __restrict__ order,
+                      const double* __restrict__ geo, const double* __restrict__ vq,
+                      const double* __restrict__ X, double* __restrict__ Y, int64_t ldx,
+                      int64_t ldy, int nvec, int ntiles, int64_t nitems, int64_t chunk) {
+  extern __shared__ double lds[];
+  const int64_t W = gridDim.x / kXcds;  // workgroups per XCD
+  const int64_t xcd = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+  const int64_t begin = xcd * chunk;
+  const int64_t end = begin + chunk < nitems ? begin + chunk : nitems;
+  box_items<NP, NQ, B, C, NT, ACCUM>(lds, grid, order, geo, vq, X, Y, ldx, ldy, nvec, ntiles,
+                                      begin + j, end, W);
+}
+
+template <int NP, int NQ, int B, int C, int NT, bool ACCUM, bool PERS>
 hipError_t launch_box(const ApplyLaunch& a, hipStream_t s) {
   const int ntiles = (a.nvec + B - 1) / B;
   const int64_t nitems = a.ncells * ntiles;
   const int64_t chunk = (nitems + kXcds - 1) / kXcds;
   constexpr size_t lds = box_lds_bytes(NP, NQ, B);
   static_assert(lds <= kLdsMax, "LDS");
-  auto k = apply_box_kernel<NP, NQ, B, NT, ACCUM>;
-  if (lds > 64 * 1024) {
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  using Kern = void (*)(const GridDesc, const int32_t*, const double*, const double*,
+                       const double*, double*, int64_t, int64_t, int, int, int64_t, int64_t);
+  Kern k;
+  if constexpr (PERS) k = apply_box_pers_kernel<NP, NQ, B, C, NT, ACCUM>;
+  else k = apply_box_kernel<NP, NQ, B, C, NT, ACCUM>;
+  static int per_cu = -1, cus = 0;  // resident capacity, queried once per instantiation
+  if (per_cu < 0) {
+    if (lds > 64 * 1024) {
+      hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (err != hipSuccess) return err;
+    }
+    int dev = 0, n = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, NT, lds);
     if (err != hipSuccess) return err;
+    per_cu = n < 1 ? 1 : n;
   }
-  hipLaunchKernelGGL(k, dim3((unsigned)(chunk * kXcds)), dim3(NT), lds, s, a.map, a.order, a.geo,
-                     a.vq, a.X, a.Y, a.ldx, a.ldy, a.nvec, ntiles, nitems, chunk);
+  int64_t blocks = chunk * kXcds;
+  if (PERS) {
+    int64_t resident = (int64_t)per_cu * cus;
+    resident -= resident % kXcds;
+    if (resident < kXcds) resident = kXcds;
+    if (resident < blocks) blocks = resident;
+  }
+  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(NT), lds, s, a.grid, a.order, a.geo, a.vq,
+                     a.X, a.Y, a.ldx, a.ldy, a.nvec, ntiles, nitems, chunk);
   return hipGetLastError();
 }
 
@@ -51,8 +91,8 @@ hipError_t try_cfg(const ApplyLaunch& a, hipStream_t s, bool& done) {
   if constexpr (c.B > 0) {
     if (a.cfg == CFG) {
       done = true;
-      return a.accumulate ? launch_box<NP, NQ, c.B, c.NT, true>(a, s)
-                          : launch_box<NP, NQ, c.B, c.NT, false>(a, s);
+      return a.accumulate ? launch_box<NP, NQ, c.B, c.C, c.NT, true, c.pers>(a, s)
+                          : launch_box<NP, NQ, c.B, c.C, c.NT, false, c.pers>(a, s);
     }
   }
   return hipSuccess;
@@ -70,6 +110,8 @@ hipError_t launch_pq(const ApplyLaunch& a, hipStream_t s) {
   if (!done) err = try_cfg<NP, NQ, 5>(a, s, done);
   if (!done) err = try_cfg<NP, NQ, 6>(a, s, done);
   if (!done) err = try_cfg<NP, NQ, 7>(a, s, done);
+  if (!done) err = try_cfg<NP, NQ, 8>(a, s, done);
+  if (!done) err = try_cfg<NP, NQ, 9>(a, s, done);
   return done ? err : hipErrorInvalidValue;
 }
 

@@ -10,11 +10,17 @@
 //   T   = (N x N x N) U_e                          (Alg. 1, eq. tc1-tc3)
 //   T  <- det J (V + sigma) o T + sum_s g_s Lf_s T  (eq. helmholtz, eq. mjacobian)
 //   V_e = (N x N x N)^T T;  Y += Q_e^T V_e         (Sec. 3.2.3)
-// Only two cell buffers live in LDS (the general kernel needs three).  Inside
-// a phase each thread owns R pencils and issues all their LDS reads before
-// computing.  Nodes interior to the cell have exactly one contributor and are
-// written with plain stores; nodes on cell faces, edges and corners use FP64
-// atomics (their rows are zeroed beforehand).
+// Every 1D contraction runs in even-odd form (eo_matvec).  Only two cell
+// buffers live in LDS (the general kernel needs three).
+//
+// Work split: a tile of B columns is cut into G = B / C groups of C adjacent
+// columns; a task is one (pencil, column group), so a thread applies every
+// coefficient to C columns (and R pencils when the tasks outnumber the
+// threads), and with C = 2 its LDS and global accesses are 16 bytes wide.
+// Inside a phase each thread issues all its LDS reads before computing.
+// Nodes interior to the cell have exactly one contributor and are written
+// with plain stores; nodes on cell faces, edges and corners use FP64 atomics
+// (their rows are zeroed beforehand).
 #pragma once
 
 #include "mf_internal.h"
@@ -23,267 +29,414 @@
 
 namespace mf {
 
-// One phase: every (vector, pencil) task w in [0, TASKS), R = ceil(TASKS/NT)
-// rounds per thread.  load(w, in) fills a round's inputs; comp(in, out) maps
-// all R rounds at once (multi-right-hand-side contractions); store(w, out)
-// writes a round.  All LDS reads of a phase are issued before any compute.
-template <int TASKS, int NT>
-struct Rounds {
-  static constexpr int R = (TASKS + NT - 1) / NT;
-  static constexpr bool EXACT = TASKS % NT == 0;
+// C adjacent columns of one LDS point <-> rows row .. row+C-1 of a register
+// block d[RN][N] at entry i.
+template <int C, int RN, int N>
+__device__ __forceinline__ void lds_get(const double* __restrict__ p, double (&d)[RN][N], int row,
+                                        int i) {
+  if constexpr (C == 1) {
+    d[row][i] = p[0];
+  } else {
+    static_assert(C == 2, "C is 1 or 2");
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    d[row][i] = v.x;
+    d[row + 1][i] = v.y;
+  }
+}
+template <int C, int RN, int N>
+__device__ __forceinline__ void lds_put(double* __restrict__ p, const double (&s)[RN][N], int row,
+                                        int i) {
+  if constexpr (C == 1) {
+    p[0] = s[row][i];
+  } else {
+    *reinterpret_cast<double2*>(p) = make_double2(s[row][i], s[row + 1][i]);
+  }
+}
+
+// Task rounds of a phase with PENS pencils: T tasks, R per thread.
+template <int PENS, int G, int NT>
+struct Tasks {
+  static constexpr int T = PENS * G;
+  static constexpr int R = (T + NT - 1) / NT;
+  static constexpr bool EXACT = T % NT == 0;
+  // task of round k, clamped to task 0 past the end (its reads stay in
+  // bounds; its results are not stored)
+  __device__ static inline int clamp(int w) { return (EXACT || w < T) ? w : 0; }
+  __device__ static inline bool live(int k, int w) { return EXACT || k < R - 1 || w < T; }
 };
-template <int TASKS, int NT, int NIN, int NOUT, class Load, class Comp, class Store>
-__device__ __forceinline__ void phase(int tid, Load load, Comp comp, Store store) {
-  constexpr int R = Rounds<TASKS, NT>::R;
-  constexpr bool EXACT = Rounds<TASKS, NT>::EXACT;
-  double in[R][NIN];
-  double out[R][NOUT];
+
+// One contraction along DIR: dst (extent NOUT along DIR) = Mat applied to src
+// (extents S0, S1, S2), in place allowed when src and dst are one buffer and
+// every pencil keeps its positions (each pencil has a single owner).
+template <class Mat, bool TR, int LD, int DIR, int S0, int S1, int S2, int NOUT, int B, int C,
+          int NT>
+__device__ __forceinline__ void box_stage(const double* src, double* dst, int tid) {
+  using PI = Pencils<DIR, S0, S1, S2>;
+  using PO = Pencils<DIR, DIR == 0 ? NOUT : S0, DIR == 1 ? NOUT : S1, DIR == 2 ? NOUT : S2>;
+  constexpr int NIN = PI::L, G = B / C;
+  using TK = Tasks<PI::COUNT, G, NT>;
+  constexpr int R = TK::R;
+  double in[R * C][NIN], out[R * C][NOUT];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int w = TK::clamp(tid + k * NT);
+    const int g = w % G, bi = PI::base(w / G);
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) lds_get<C>(src + (bi + i * PI::STRIDE) * B + g * C, in, k * C, i);
+  }
+  eo_matvec<Mat, NOUT, NIN, TR, LD, R * C>(in, out);
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int w = tid + k * NT;
-    if (EXACT || k < R - 1 || w < TASKS) {
-      load(w, in[k]);
-    } else {
+    if (!TK::live(k, w)) continue;
+    const int g = w % G, bo = PO::base(w / G);
 #pragma unroll
-      for (int i = 0; i < NIN; ++i) in[k][i] = 0.0;
+    for (int i = 0; i < NOUT; ++i) lds_put<C>(dst + (bo + i * PO::STRIDE) * B + g * C, out, k * C, i);
+  }
+}
+
+// Per-thread registers of one work item's extraction: for each of the R1
+// tasks (direction-0 pencil (i2, i3), column group) of this thread, the NP
+// node numbers of the pencil (-1 for a constrained node) and the gathered X
+// values of its C columns.  The same thread owns the same tasks in the last
+// phase, so the node numbers also drive the assembly.
+template <int NP, int B, int C, int NT>
+struct BoxGather {
+  static constexpr int G = B / C;
+  using TK = Tasks<NP * NP, G, NT>;
+  static constexpr int T1 = TK::T;
+  static constexpr int R1 = TK::R;
+  int node[R1][NP];
+  double x[R1 * C][NP];
+
+  // Node numbers from the structured-grid arithmetic: cell e at (cx, cy, cz),
+  // local node (i1, i2, i3) -> grid node (cx p + i1, ...) with the periodic
+  // wrap, -1 on the boundary of a zero-Dirichlet mesh.
+  __device__ __forceinline__ void load_grid(const GridDesc& gd, int64_t e, int tid) {
+    const int ei = (int)e;
+    const int cx = ei % gd.n[0], cy = (ei / gd.n[0]) % gd.n[1], cz = ei / (gd.n[0] * gd.n[1]);
+#pragma unroll
+    for (int k = 0; k < R1; ++k) {
+      const int pen = TK::clamp(tid + k * NT) / G;
+      const int i2 = pen % NP, i3 = pen / NP;
+      int gy = cy * gd.p + i2, gz = cz * gd.p + i3;
+      if (gy == gd.N[1]) gy = 0;  // only reachable on a periodic mesh
+      if (gz == gd.N[2]) gz = 0;
+      const bool yz_bnd =
+          gd.dirichlet && (gy == 0 || gy == gd.N[1] - 1 || gz == 0 || gz == gd.N[2] - 1);
+      const int rowbase = gd.N[0] * (gy + gd.N[1] * gz);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        int gx = cx * gd.p + i;
+        if (gx == gd.N[0]) gx = 0;
+        const bool bnd = yz_bnd || (gd.dirichlet && (gx == 0 || gx == gd.N[0] - 1));
+        node[k][i] = bnd ? -1 : rowbase + gx;
+      }
     }
   }
-  comp(in, out);
+  // branch-free: invalid lanes (constrained node, columns past nvec, task past
+  // the tile) read X[0] and select zero.  C = 2 needs nvec, ldx even and X
+  // 16-byte aligned (checked by the host).
+  __device__ __forceinline__ void load_x(const double* __restrict__ X, int64_t ldx, int nvec, int v0,
+                                         int tid) {
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
+    for (int k = 0; k < R1; ++k) {
+      const int w = tid + k * NT;
+      const int v = v0 + (w % G) * C;
+      const bool wok = w < T1 && v < nvec;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        const bool ok = wok && node[k][i] >= 0;
+        const int64_t at = ok ? (int64_t)node[k][i] * ldx + v : 0;
+        if constexpr (C == 1) {
+          const double xv = X[at];
+          x[k][i] = ok ? xv : 0.0;
+        } else {
+          const double2 xv = *reinterpret_cast<const double2*>(X + at);
+          x[2 * k][i] = ok ? xv.x : 0.0;
+          x[2 * k + 1][i] = ok ? xv.y : 0.0;
+        }
+      }
+    }
+  }
+};
+
+// P1: N along direction 0 from the gathered registers (consumed) -> A (NQ,NP,NP).
+template <int NP, int NQ, int B, int C, int NT>
+__device__ __forceinline__ void box_p1(double* __restrict__ bA, BoxGather<NP, B, C, NT>& Gt,
+                                       int tid) {
+  using GT = BoxGather<NP, B, C, NT>;
+  constexpr int R1 = GT::R1, G = GT::G;
+  double o[R1 * C][NQ];
+  eo_matvec<MatN<NP, NQ>, NQ, NP, false, NP, R1 * C>(Gt.x, o);
+#pragma unroll
+  for (int k = 0; k < R1; ++k) {
     const int w = tid + k * NT;
-    if (EXACT || k < R - 1 || w < TASKS) store(w, out[k]);
+    if (!GT::TK::live(k, w)) continue;
+    const int g = w % G, pen = w / G;
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) lds_put<C>(bA + (pen * NQ + a) * B + g * C, o, k * C, a);
+  }
+}
+
+// P2 .. P7 (barrier-separated; starts after the barrier that follows P1):
+// N along 1 and 2, the collapsed derivative terms, the mass term and N^T along
+// 2 and 1.  Leaves (NQ,NP,NP) in B.
+template <int NP, int NQ, int B, int C, int NT>
+__device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restrict__ bB,
+                                        const double* __restrict__ svq, double g0, double g1,
+                                        double g2, int tid) {
+  constexpr int NQ2 = NQ * NQ, G = B / C;
+  using Nf = MatN<NP, NQ>;
+  using Lf = MatL<NP, NQ>;
+  using TK = Tasks<NQ2, G, NT>;
+  constexpr int R = TK::R;
+
+  // P2, P3: N along directions 1 and 2 -> T in A (NQ,NQ,NQ).
+  box_stage<Nf, false, NP, 1, NQ, NP, NP, NQ, B, C, NT>(bA, bB, tid);
+  __syncthreads();
+  box_stage<Nf, false, NP, 2, NQ, NQ, NP, NQ, B, C, NT>(bB, bA, tid);
+  __syncthreads();
+
+  // P4: B = g0 Lf_0 T (direction-0 pencils).
+  {
+    double t[R * C][NQ], o[R * C][NQ];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int w = TK::clamp(tid + k * NT);
+      const int g = w % G, pen = w / G;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) lds_get<C>(bA + (pen * NQ + q) * B + g * C, t, k * C, q);
+    }
+    eo_matvec<Lf, NQ, NQ, false, NQ, R * C>(t, o);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int w = tid + k * NT;
+      if (!TK::live(k, w)) continue;
+      const int g = w % G, pen = w / G;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) o[k * C + c][q] *= g0;
+        lds_put<C>(bB + (pen * NQ + q) * B + g * C, o, k * C, q);
+      }
+    }
+  }
+  __syncthreads();
+
+  // P5: B += g1 Lf_1 T (direction-1 pencils).
+  {
+    double t[R * C][NQ], b[R * C][NQ], o[R * C][NQ];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int w = TK::clamp(tid + k * NT);
+      const int g = w % G, pen = w / G;
+      const int base = (pen / NQ) * NQ2 + (pen % NQ);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        lds_get<C>(bA + (base + q * NQ) * B + g * C, t, k * C, q);
+        lds_get<C>(bB + (base + q * NQ) * B + g * C, b, k * C, q);
+      }
+    }
+    eo_matvec<Lf, NQ, NQ, false, NQ, R * C>(t, o);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int w = tid + k * NT;
+      if (!TK::live(k, w)) continue;
+      const int g = w % G, pen = w / G;
+      const int base = (pen / NQ) * NQ2 + (pen % NQ);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) o[k * C + c][q] = fma(g1, o[k * C + c][q], b[k * C + c][q]);
+        lds_put<C>(bB + (base + q * NQ) * B + g * C, o, k * C, q);
+      }
+    }
+  }
+  __syncthreads();
+
+  // P6: direction-2 pencils: u = vq o T + B + g2 Lf_2 T, then N^T along 2;
+  // written into A in place as (NQ,NQ,NP) (each pencil has a single owner).
+  {
+    double t[R * C][NQ], acc[R * C][NQ], l[R * C][NQ], o[R * C][NP];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int w = TK::clamp(tid + k * NT);
+      const int g = w % G, pen = w / G;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        lds_get<C>(bA + (pen + q * NQ2) * B + g * C, t, k * C, q);
+        lds_get<C>(bB + (pen + q * NQ2) * B + g * C, acc, k * C, q);
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const double sv = svq[pen + q * NQ2];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[k * C + c][q] = fma(sv, t[k * C + c][q], acc[k * C + c][q]);
+      }
+    }
+    eo_matvec<Lf, NQ, NQ, false, NQ, R * C>(t, l);
+#pragma unroll
+    for (int r = 0; r < R * C; ++r)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[r][q] = fma(g2, l[r][q], acc[r][q]);
+    eo_matvec<Nf, NP, NQ, true, NP, R * C>(acc, o);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int w = tid + k * NT;
+      if (!TK::live(k, w)) continue;
+      const int g = w % G, pen = w / G;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) lds_put<C>(bA + (pen + i * NQ2) * B + g * C, o, k * C, i);
+    }
+  }
+  __syncthreads();
+
+  // P7: N^T along direction 1: A (NQ,NQ,NP) -> B (NQ,NP,NP).
+  box_stage<Nf, true, NP, 1, NQ, NQ, NP, NP, B, C, NT>(bA, bB, tid);
+  __syncthreads();
+}
+
+// P8: N^T along direction 0 and the assembly of this thread's pencils.
+template <int NP, int NQ, int B, int C, int NT, bool ACCUM>
+__device__ __forceinline__ void box_p8(const double* __restrict__ bB,
+                                       const BoxGather<NP, B, C, NT>& Gt, double* __restrict__ Y,
+                                       int64_t ldy, int nvec, int v0, int tid) {
+  using GT = BoxGather<NP, B, C, NT>;
+  constexpr int R1 = GT::R1, G = GT::G;
+  double t[R1 * C][NQ], o[R1 * C][NP];
+#pragma unroll
+  for (int k = 0; k < R1; ++k) {
+    const int w = GT::TK::clamp(tid + k * NT);
+    const int g = w % G, pen = w / G;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) lds_get<C>(bB + (pen * NQ + q) * B + g * C, t, k * C, q);
+  }
+  eo_matvec<MatN<NP, NQ>, NP, NQ, true, NP, R1 * C>(t, o);
+#pragma unroll
+  for (int k = 0; k < R1; ++k) {
+    const int w = tid + k * NT;
+    const int g = w % G, pen = w / G, v = v0 + g * C;
+    if (w >= GT::T1 || v >= nvec) continue;
+    const int i2 = pen % NP, i3 = pen / NP;
+    const bool inner_pen = i2 > 0 && i2 < NP - 1 && i3 > 0 && i3 < NP - 1;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int node = Gt.node[k][i];
+      if (node < 0) continue;
+      double* dst = Y + (int64_t)node * ldy + v;
+      if (i > 0 && i < NP - 1 && inner_pen) {
+        if constexpr (C == 1) {
+          if (ACCUM) *dst += o[k][i];
+          else *dst = o[k][i];
+        } else {
+          double2* d2 = reinterpret_cast<double2*>(dst);
+          double2 val = make_double2(o[2 * k][i], o[2 * k + 1][i]);
+          if (ACCUM) {
+            const double2 old = *d2;
+            val.x += old.x;
+            val.y += old.y;
+          }
+          *d2 = val;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) unsafeAtomicAdd(dst + c, o[k * C + c][i]);
+      }
+    }
+  }
+}
+
+// Persistent form of the item loop: the workgroup owns items it0, it0 + W,
+// ... < end (cell = order[item / ntiles], columns (item % ntiles) B ..).  The
+// X values (and scaled potential) of item i+1 are loaded into registers while
+// item i runs its contractions, so the extraction latency hides behind
+// arithmetic instead of idling the workgroup; node numbers are recomputed from
+// the grid for the assembly rather than held through the contractions.
+template <int NP, int NQ, int B, int C, int NT, bool ACCUM>
+__device__ __forceinline__ void box_items(double* __restrict__ lds, const GridDesc& grid,
+                                          const int32_t* __restrict__ order,
+                                          const double* __restrict__ geo,
+                                          const double* __restrict__ vq,
+                                          const double* __restrict__ X, double* __restrict__ Y,
+                                          int64_t ldx, int64_t ldy, int nvec, int ntiles,
+                                          int64_t it, int64_t end, int64_t W) {
+  constexpr int NQ3 = NQ * NQ * NQ;
+  constexpr int RV = (NQ3 + NT - 1) / NT;
+  double* bA = lds;
+  double* bB = bA + NQ3 * B;
+  double* svq = bB + NQ3 * B;
+  const int tid = threadIdx.x;
+  if (it >= end) return;
+  auto load_vq = [&](int64_t e, double (&r)[RV]) {
+#pragma unroll
+    for (int k = 0; k < RV; ++k) {
+      const int i = tid + k * NT;
+      r[k] = vq[e * NQ3 + (i < NQ3 ? i : 0)];
+    }
+  };
+  BoxGather<NP, B, C, NT> cur;
+  double vqc[RV];
+  {
+    const int64_t e = order[it / ntiles];
+    cur.load_grid(grid, e, tid);
+    cur.load_x(X, ldx, nvec, (int)(it % ntiles) * B, tid);
+    load_vq(e, vqc);
+  }
+  for (;;) {
+    const int64_t e = order[it / ntiles];
+    const int v0 = (int)(it % ntiles) * B;
+    const double g0 = geo[e * 6 + 0], g1 = geo[e * 6 + 3], g2 = geo[e * 6 + 5];
+#pragma unroll
+    for (int k = 0; k < RV; ++k)
+      if (RV * NT == NQ3 || tid + k * NT < NQ3) svq[tid + k * NT] = vqc[k];
+    box_p1<NP, NQ, B, C, NT>(bA, cur, tid);
+    const int64_t nx = it + W;
+    if (nx < end) {  // prefetch the next item into the registers P1 just freed
+      const int64_t en = order[nx / ntiles];
+      cur.load_grid(grid, en, tid);
+      cur.load_x(X, ldx, nvec, (int)(nx % ntiles) * B, tid);
+      load_vq(en, vqc);
+    }
+    __syncthreads();
+    box_mid<NP, NQ, B, C, NT>(bA, bB, svq, g0, g1, g2, tid);
+    {
+      BoxGather<NP, B, C, NT> here;  // node numbers only (x unused)
+      here.load_grid(grid, e, tid);
+      box_p8<NP, NQ, B, C, NT, ACCUM>(bB, here, Y, ldy, nvec, v0, tid);
+    }
+    if (nx >= end) break;
+    it = nx;
+    // no barrier here: the next P1 writes A and svq, whose last readers (P6,
+    // P7) are behind barriers; B is rewritten only after the barrier that
+    // follows the next P1, when every thread has finished this P8.
   }
 }
 
 // One (cell e, columns v0 .. v0+B-1) work item.  `lds` holds
 // box_lds_bytes(NP, NQ, B) bytes; the caller synchronises the workgroup
 // before reusing it for another item.
-template <int NP, int NQ, int B, int NT, bool ACCUM>
-__device__ __forceinline__ void box_cell_tile(double* __restrict__ lds,
-                                              const int32_t* __restrict__ cmap,
+template <int NP, int NQ, int B, int C, int NT, bool ACCUM>
+__device__ __forceinline__ void box_cell_tile(double* __restrict__ lds, const GridDesc& grid,
                                               const double* __restrict__ geo,
                                               const double* __restrict__ vq,
                                               const double* __restrict__ X, double* __restrict__ Y,
                                               int64_t ldx, int64_t ldy, int nvec, int64_t e,
                                               int v0) {
-  constexpr int NP2 = NP * NP, NP3 = NP * NP * NP, NQ2 = NQ * NQ, NQ3 = NQ * NQ * NQ;
-  using Nf = MatN<NP, NQ>;
-  using Lf = MatL<NP, NQ>;
+  constexpr int NQ3 = NQ * NQ * NQ;
   double* bA = lds;
   double* bB = bA + NQ3 * B;
   double* svq = bB + NQ3 * B;
-  // per cell node: row offsets node*ldx and node*ldy, -1 for a constrained node
-  int64_t* sxo = reinterpret_cast<int64_t*>(svq + NQ3);
-  int64_t* syo = sxo + NP3;
   const int tid = threadIdx.x;
-
-  for (int i = tid; i < NP3; i += NT) {
-    const int node = cmap[e * NP3 + i];
-    sxo[i] = node >= 0 ? (int64_t)node * ldx : -1;
-    syo[i] = node >= 0 ? (int64_t)node * ldy : -1;
-  }
+  BoxGather<NP, B, C, NT> Gt;
+  Gt.load_grid(grid, e, tid);
   for (int i = tid; i < NQ3; i += NT) svq[i] = vq[e * NQ3 + i];
   const double g0 = geo[e * 6 + 0], g1 = geo[e * 6 + 3], g2 = geo[e * 6 + 5];
+  Gt.load_x(X, ldx, nvec, v0, tid);
+  box_p1<NP, NQ, B, C, NT>(bA, Gt, tid);
   __syncthreads();
-
-  // P1: extraction fused with N along direction 0: (NP,NP,NP) -> A (NQ,NP,NP).
-  phase<NP2 * B, NT, NP, NQ>(
-      tid,
-      [&](int w, double (&r)[NP]) {
-        // branch-free: invalid lanes (constrained node, column past nvec) read
-        // X[0] and select zero
-        const int b = w % B, pen = w / B, v = v0 + b;
-        const bool vok = v < nvec;
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-          const int64_t off = sxo[pen * NP + i];
-          const bool ok = vok && off >= 0;
-          const double x = X[ok ? off + v : 0];
-          r[i] = ok ? x : 0.0;
-        }
-      },
-      [&](auto& r, auto& o) { matvec_multi<Nf, NQ, NP, false, NP>(r, o); },
-      [&](int w, double (&o)[NQ]) {
-        const int b = w % B, pen = w / B;
-#pragma unroll
-        for (int a = 0; a < NQ; ++a) bA[(pen * NQ + a) * B + b] = o[a];
-      });
-  __syncthreads();
-
-  // P2, P3: N along directions 1 and 2 -> T in A (NQ,NQ,NQ).
-  {
-    using PI = Pencils<1, NQ, NP, NP>;
-    using PO = Pencils<1, NQ, NQ, NP>;
-    phase<PI::COUNT * B, NT, NP, NQ>(
-        tid,
-        [&](int w, double (&r)[NP]) {
-          const int b = w % B, base = PI::base(w / B);
-#pragma unroll
-          for (int i = 0; i < NP; ++i) r[i] = bA[(base + i * PI::STRIDE) * B + b];
-        },
-        [&](auto& r, auto& o) { matvec_multi<Nf, NQ, NP, false, NP>(r, o); },
-        [&](int w, double (&o)[NQ]) {
-          const int b = w % B, base = PO::base(w / B);
-#pragma unroll
-          for (int a = 0; a < NQ; ++a) bB[(base + a * PO::STRIDE) * B + b] = o[a];
-        });
-  }
-  __syncthreads();
-  {
-    using PI = Pencils<2, NQ, NQ, NP>;
-    phase<PI::COUNT * B, NT, NP, NQ>(
-        tid,
-        [&](int w, double (&r)[NP]) {
-          const int b = w % B, pen = w / B;
-#pragma unroll
-          for (int i = 0; i < NP; ++i) r[i] = bB[(pen + i * NQ2) * B + b];
-        },
-        [&](auto& r, auto& o) { matvec_multi<Nf, NQ, NP, false, NP>(r, o); },
-        [&](int w, double (&o)[NQ]) {
-          const int b = w % B, pen = w / B;
-#pragma unroll
-          for (int a = 0; a < NQ; ++a) bA[(pen + a * NQ2) * B + b] = o[a];
-        });
-  }
-  __syncthreads();
-
-  // P4: B = g0 Lf_0 T (direction-0 pencils).
-  phase<NQ2 * B, NT, NQ, NQ>(
-      tid,
-      [&](int w, double (&t)[NQ]) {
-        const int b = w % B, pen = w / B;
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) t[k] = bA[(pen * NQ + k) * B + b];
-      },
-      [&](auto& t, auto& o) {
-        matvec_multi<Lf, NQ, NQ, false, NQ>(t, o);
-        for (auto& ok : o)
-#pragma unroll
-          for (int k = 0; k < NQ; ++k) ok[k] *= g0;
-      },
-      [&](int w, double (&o)[NQ]) {
-        const int b = w % B, pen = w / B;
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) bB[(pen * NQ + k) * B + b] = o[k];
-      });
-  __syncthreads();
-
-  // P5: B += g1 Lf_1 T (direction-1 pencils).
-  phase<NQ2 * B, NT, 2 * NQ, NQ>(
-      tid,
-      [&](int w, double (&t)[2 * NQ]) {
-        const int b = w % B, pen = w / B;
-        const int base = (pen / NQ) * NQ2 + (pen % NQ);
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-          t[k] = bA[(base + k * NQ) * B + b];
-          t[NQ + k] = bB[(base + k * NQ) * B + b];
-        }
-      },
-      [&](auto& t, auto& o) {
-        constexpr int R = sizeof(t) / sizeof(t[0]);
-        double u[R][NQ];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int k = 0; k < NQ; ++k) u[r][k] = t[r][k];
-        matvec_multi<Lf, NQ, NQ, false, NQ>(u, o);
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int k = 0; k < NQ; ++k) o[r][k] = fma(g1, o[r][k], t[r][NQ + k]);
-      },
-      [&](int w, double (&o)[NQ]) {
-        const int b = w % B, pen = w / B;
-        const int base = (pen / NQ) * NQ2 + (pen % NQ);
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) bB[(base + k * NQ) * B + b] = o[k];
-      });
-  __syncthreads();
-
-  // P6: direction-2 pencils: u = vq o T + g2 Lf_2 T + B, then N^T along 2;
-  // written into A in place as (NQ,NQ,NP) (each pencil has a single owner).
-  phase<NQ2 * B, NT, 3 * NQ, NP>(
-      tid,
-      [&](int w, double (&t)[3 * NQ]) {
-        const int b = w % B, pen = w / B;
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-          t[k] = bA[(pen + k * NQ2) * B + b];
-          t[NQ + k] = bB[(pen + k * NQ2) * B + b];
-          t[2 * NQ + k] = svq[pen + k * NQ2];
-        }
-      },
-      [&](auto& t, auto& o) {
-        constexpr int R = sizeof(t) / sizeof(t[0]);
-        double u[R][NQ], l[R][NQ];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int k = 0; k < NQ; ++k) u[r][k] = t[r][k];
-        matvec_multi<Lf, NQ, NQ, false, NQ>(u, l);
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int k = 0; k < NQ; ++k)
-            u[r][k] = fma(t[r][2 * NQ + k], t[r][k], fma(g2, l[r][k], t[r][NQ + k]));
-        matvec_multi<Nf, NP, NQ, true, NP>(u, o);
-      },
-      [&](int w, double (&o)[NP]) {
-        const int b = w % B, pen = w / B;
-#pragma unroll
-        for (int i = 0; i < NP; ++i) bA[(pen + i * NQ2) * B + b] = o[i];
-      });
-  __syncthreads();
-
-  // P7: N^T along direction 1: A (NQ,NQ,NP) -> B (NQ,NP,NP).
-  {
-    using PI = Pencils<1, NQ, NQ, NP>;
-    using PO = Pencils<1, NQ, NP, NP>;
-    phase<PI::COUNT * B, NT, NQ, NP>(
-        tid,
-        [&](int w, double (&t)[NQ]) {
-          const int b = w % B, base = PI::base(w / B);
-#pragma unroll
-          for (int k = 0; k < NQ; ++k) t[k] = bA[(base + k * PI::STRIDE) * B + b];
-        },
-        [&](auto& t, auto& o) { matvec_multi<Nf, NP, NQ, true, NP>(t, o); },
-        [&](int w, double (&o)[NP]) {
-          const int b = w % B, base = PO::base(w / B);
-#pragma unroll
-          for (int i = 0; i < NP; ++i) bB[(base + i * PO::STRIDE) * B + b] = o[i];
-        });
-  }
-  __syncthreads();
-
-  // P8: N^T along direction 0 fused with the assembly.
-  phase<NP2 * B, NT, NQ, NP>(
-      tid,
-      [&](int w, double (&t)[NQ]) {
-        const int b = w % B, pen = w / B;
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) t[k] = bB[(pen * NQ + k) * B + b];
-      },
-      [&](auto& t, auto& o) { matvec_multi<Nf, NP, NQ, true, NP>(t, o); },
-      [&](int w, double (&o)[NP]) {
-        const int b = w % B, pen = w / B, v = v0 + b;
-        if (v >= nvec) return;
-        const int i2 = pen % NP, i3 = pen / NP;
-        const bool inner_pen = i2 > 0 && i2 < NP - 1 && i3 > 0 && i3 < NP - 1;
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-          const int64_t off = syo[pen * NP + i];
-          if (off < 0) continue;
-          double* dst = Y + off + v;
-          if (i > 0 && i < NP - 1 && inner_pen) {
-            if (ACCUM) *dst += o[i];
-            else *dst = o[i];
-          } else {
-            unsafeAtomicAdd(dst, o[i]);
-          }
-        }
-      });
+  box_mid<NP, NQ, B, C, NT>(bA, bB, svq, g0, g1, g2, tid);
+  box_p8<NP, NQ, B, C, NT, ACCUM>(bB, Gt, Y, ldy, nvec, v0, tid);
 }
 
 }  // namespace mf

@@ -5,6 +5,7 @@
 #include <new>
 
 #include "mf_internal.h"
+#include "sf_common.h"
 
 namespace mf {
 
@@ -139,6 +140,12 @@ int mf_create_operator(const mf_box_mesh* mesh, int p, int q, double mu, const d
   op->nodes[0] = Nx;
   op->nodes[1] = Ny;
   op->nodes[2] = Nz;
+  for (int d = 0; d < 3; ++d) {
+    op->grid.n[d] = mesh->n[d];
+    op->grid.N[d] = (int)op->nodes[d];
+  }
+  op->grid.p = p;
+  op->grid.dirichlet = mesh->bc == MF_BC_DIRICHLET0 ? 1 : 0;
   op->ncells = (int64_t)mesh->n[0] * mesh->n[1] * mesh->n[2];
   if (op->ndofs >= (int64_t)1 << 31) {
     delete op;
@@ -293,6 +300,7 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   ApplyLaunch a{};
+  a.grid = op->grid;
   a.map = op->d_map;
   a.order = op->d_order;
   a.geo = op->d_geo;
@@ -309,6 +317,8 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
     a.cfg = op->mcfg >= 0 ? op->mcfg : choose_cfg_mixed(op->np, op->nq, nvec);
   else
     a.cfg = op->cfg >= 0 ? op->cfg : choose_cfg_box(op->np, op->nq, nvec);
+  if (!mixed && op->box && !box_pairs_ok(X, Y, nvec, ldx, ldy))
+    a.cfg = box_cfg_single(op->np, op->nq, a.cfg);
   a.accumulate = accumulate;
 
   hipEvent_t* ev = nullptr;

@@ -55,6 +55,7 @@ static int build_table(Batch* b, int cfg) {
     for (int j = 0; j < 3; ++j) d.nodes[j] = (int)op->nodes[j];
     d.item_begin = items;
     d.line_begin = lines;
+    d.grid = op->grid;
     items += op->ncells * d.ntiles;
     lines += op->nodes[1] * op->nodes[2];
   }

@@ -7,13 +7,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mfmv.h"
+#include "mfmv.h"  // from the repository include directory (-I)
 
 namespace mf {
 
 constexpr int kMaxP = 10;
 constexpr int kMaxQExtra = 3;  // q in [p+1, p+3]
-constexpr int kBoxCfgs = 8;    // launch shapes of the box-cell kernel
+constexpr int kBoxCfgs = 10;   // launch shapes of the box-cell kernel
 constexpr int kMixedCfgs = 4;  // launch shapes of the mixed-precision kernel
 constexpr int kBatchCfgs = 3;  // launch shapes of the persistent batched kernel
 constexpr int kMaxBatch = 64;  // operators per batch
@@ -46,6 +46,16 @@ int64_t nodes_per_dir(const mf_box_mesh& m, int p, int d);
 void lin_matrix(const mf_box_mesh& m, double L[9]);
 
 // --------------------------------------------------------------- operator
+// Structured node grid of a box mesh: cells n[], nodes N[] per direction,
+// degree p; node numbers follow from index arithmetic (periodic wrap when
+// N = n p, boundary nodes constrained when dirichlet).
+struct GridDesc {
+  int n[3];
+  int N[3];
+  int p;
+  int dirichlet;
+};
+
 struct Operator {
   int device = 0;
   int p = 0, q = 0, np = 0, nq = 0;
@@ -53,6 +63,7 @@ struct Operator {
   double mu = 0.0, sigma = 0.0;
   // device arrays
   int64_t nodes[3] = {0, 0, 0};  // nodes per direction of the full numbering
+  GridDesc grid{};
   bool box = false;           // every cell axis-aligned: diagonal 3x3 factor
   int cfg = 0;                // launch shape of the box kernel (tuned or default)
   int mcfg = -1;              // launch shape of the mixed-precision kernel
@@ -69,6 +80,7 @@ struct Operator {
 
 // ----------------------------------------------------------------- kernels
 struct ApplyLaunch {
+  GridDesc grid;
   const int32_t* map;
   const int32_t* order;
   const double* geo;
@@ -94,6 +106,7 @@ struct BatchOp {
   int64_t ncells;
   int ntiles;          // column tiles
   int64_t line_begin;  // first node line (gy, gz) of this operator in the batch's zero fill
+  GridDesc grid;
   int p;
   int nodes[3];
 };
@@ -129,6 +142,12 @@ hipError_t launch_apply_mixed(const Operator& op, const ApplyLaunch& a, int prec
 bool apply_mixed_supported(int p, int q, int cfg);
 int choose_cfg_mixed(int np, int nq, int nvec);
 int choose_cfg_box(int np, int nq, int nvec);
+// Two-column (16-byte) accesses need even nvec and leading dimensions and
+// 16-byte aligned multivectors.
+inline bool box_pairs_ok(const double* X, const double* Y, int nvec, int64_t ldx, int64_t ldy) {
+  return nvec % 2 == 0 && ldx % 2 == 0 && ldy % 2 == 0 &&
+         reinterpret_cast<uintptr_t>(X) % 16 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0;
+}
 // Processing order of the cells: 8 blocks by recursive bisection (one per XCD),
 // Morton order inside each block.
 std::vector<int32_t> cell_order(const int n[3]);

@@ -33,18 +33,151 @@ template <int NP, int NQ>
 struct MatN {  // folded N1D, NQ x NP, row-major
   template <int K>
   static constexpr double at = Tab<NP, NQ>::v.Nf[K];
+  static constexpr double get(int k) { return Tab<NP, NQ>::v.Nf[k]; }
 };
 template <int NP, int NQ>
 struct MatD {  // folded Dt, NQ x NQ, row-major
   template <int K>
   static constexpr double at = Tab<NP, NQ>::v.Dtf[K];
+  static constexpr double get(int k) { return Tab<NP, NQ>::v.Dtf[k]; }
 };
 
 template <int NP, int NQ>
 struct MatL {  // Dtf^T Dtf, NQ x NQ, symmetric
   template <int K>
   static constexpr double at = Tab<NP, NQ>::v.Lf[K];
+  static constexpr double get(int k) { return Tab<NP, NQ>::v.Lf[k]; }
 };
+
+// ------------------------------------------------------------ even-odd form
+// Points and nodes of the 1D rules are symmetric about the cell centre, so the
+// folded interpolation matrix N (and its transpose) is centrosymmetric,
+// M(m-1-o, n-1-i) = M(o, i), the folded derivative Dt is anti-centrosymmetric
+// and Lf = Dt^T Dt is centrosymmetric again.  For such an m x n matrix,
+//   y_o +- y_{m-1-o} = sum_{i < n/2} (M(o,i) +- M(o,n-1-i)) (x_i +- x_{n-1-i})
+//                      [+ 2 M(o, n/2) x_{n/2} in the sum, odd n]
+// and the middle row (odd m) sees only the even part.  This halves the
+// coefficient uses of a contraction and cuts its arithmetic by about a
+// quarter (the Kronecker structure itself is unchanged).
+template <class M, bool TR, int LD>
+constexpr double mco(int o, int i) {
+  return M::get(TR ? i * LD + o : o * LD + i);
+}
+template <class M, int NOUT, int NIN, bool TR, int LD>
+constexpr bool centrosymmetric() {
+  for (int o = 0; o < NOUT; ++o)
+    for (int i = 0; i < NIN; ++i) {
+      const double a = mco<M, TR, LD>(o, i), b = mco<M, TR, LD>(NOUT - 1 - o, NIN - 1 - i);
+      const double d = a - b, s = (a < 0 ? -a : a) + 1.0;
+      if ((d < 0 ? -d : d) > 1e-13 * s) return false;
+    }
+  return true;
+}
+template <int N, class F, int... I>
+__device__ __forceinline__ void sfor_(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+// compile-time loop: f(std::integral_constant<int, i>) for i = 0 .. N-1
+template <int N, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  sfor_<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+// Coefficients of the even / odd half-problems of an NOUT x NIN matrix.
+template <class M, int NOUT, int NIN, bool TR, int LD>
+struct EoMat {
+  static constexpr int HI = NIN / 2, HO = NOUT / 2;
+  static constexpr int MI = NIN % 2, MO = NOUT % 2;
+  // even part of row o (o < HO, or the middle row o = HO of an odd NOUT) on
+  // folded column i (i < HI: x_i + x_{n-1-i}; i = HI of an odd NIN: x_mid)
+  static constexpr double e(int o, int i) {
+    if (2 * i + 1 == NIN || 2 * o + 1 == NOUT) return mco<M, TR, LD>(o, i);
+    return 0.5 * (mco<M, TR, LD>(o, i) + mco<M, TR, LD>(o, NIN - 1 - i));
+  }
+  // odd part of row o < HO on folded column i < HI (x_i - x_{n-1-i})
+  static constexpr double d(int o, int i) {
+    return 0.5 * (mco<M, TR, LD>(o, i) - mco<M, TR, LD>(o, NIN - 1 - i));
+  }
+  static constexpr int first_e(int o) {
+    for (int i = 0; i < HI + MI; ++i)
+      if (e(o, i) != 0.0) return i;
+    return -1;
+  }
+  static constexpr int first_d(int o) {
+    for (int i = 0; i < HI; ++i)
+      if (d(o, i) != 0.0) return i;
+    return -1;
+  }
+};
+
+// y[r] = M x[r] for RN right-hand sides in even-odd form.  x is folded in
+// place (x[r][i] <- x_i + x_{n-1-i}, x[r][n-1-i] <- x_i - x_{n-1-i}) and is
+// not usable afterwards.  Every coefficient is a literal used RN times back to
+// back; exact zeros are skipped.
+template <class M, int NOUT, int NIN, bool TR, int LD, int RN>
+__device__ __forceinline__ void eo_matvec(double (&x)[RN][NIN], double (&y)[RN][NOUT]) {
+  using E = EoMat<M, NOUT, NIN, TR, LD>;
+  static_assert(centrosymmetric<M, NOUT, NIN, TR, LD>(), "matrix is not centrosymmetric");
+#pragma unroll
+  for (int r = 0; r < RN; ++r)
+#pragma unroll
+    for (int i = 0; i < E::HI; ++i) {
+      const double a = x[r][i], b = x[r][NIN - 1 - i];
+      x[r][i] = a + b;
+      x[r][NIN - 1 - i] = a - b;
+    }
+  sfor<E::HO + E::MO>([&](auto O) {
+    constexpr int o = decltype(O)::value;
+    double ev[RN], od[RN];
+    constexpr int fe = E::first_e(o);
+    if constexpr (fe < 0) {
+#pragma unroll
+      for (int r = 0; r < RN; ++r) ev[r] = 0.0;
+    } else {
+      sfor<E::HI + E::MI>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr double c = E::e(o, i);
+        if constexpr (i == fe) {
+#pragma unroll
+          for (int r = 0; r < RN; ++r) ev[r] = c * x[r][i];
+        } else if constexpr (i > fe && c != 0.0) {
+#pragma unroll
+          for (int r = 0; r < RN; ++r) ev[r] = fma(c, x[r][i], ev[r]);
+        }
+      });
+    }
+    if constexpr (o == E::HO) {  // middle row of an odd NOUT
+#pragma unroll
+      for (int r = 0; r < RN; ++r) y[r][o] = ev[r];
+    } else {
+      constexpr int fd = E::first_d(o);
+      if constexpr (fd < 0) {
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+          y[r][o] = ev[r];
+          y[r][NOUT - 1 - o] = ev[r];
+        }
+      } else {
+        sfor<E::HI>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          constexpr double c = E::d(o, i);
+          if constexpr (i == fd) {
+#pragma unroll
+            for (int r = 0; r < RN; ++r) od[r] = c * x[r][NIN - 1 - i];
+          } else if constexpr (i > fd && c != 0.0) {
+#pragma unroll
+            for (int r = 0; r < RN; ++r) od[r] = fma(c, x[r][NIN - 1 - i], od[r]);
+          }
+        });
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+          y[r][o] = ev[r] + od[r];
+          y[r][NOUT - 1 - o] = ev[r] - od[r];
+        }
+      }
+    }
+  });
+}
 
 template <class M, bool TR, int LD, int O, typename T, int NIN, int... I>
 __device__ __forceinline__ T mrow(const T (&in)[NIN], std::integer_sequence<int, I...>) {
@@ -178,41 +311,77 @@ constexpr bool f64_tile_built(int np, int nq, int b) {
 
 constexpr size_t kLdsMax = 160 * 1024;     // LDS per workgroup on gfx950
 
-// LDS bytes of the box-cell kernel: two cell buffers, the scaled potential, and
-// the 64-bit X and Y row offsets of the cell's nodes.
+// LDS bytes of the box-cell kernel: two cell buffers and the scaled potential
+// (node numbers stay in the registers of the threads that gather and assemble).
 constexpr size_t box_lds_bytes(int np, int nq, int vtile) {
-  return (2 * (size_t)nq * nq * nq * vtile + (size_t)nq * nq * nq) * sizeof(double) +
-         2 * (size_t)np * np * np * sizeof(int64_t);
+  return (2 * (size_t)nq * nq * nq * vtile + (size_t)nq * nq * nq) * sizeof(double) + 0 * np;
 }
 
-// Launch shapes of the box-cell kernel: (vector tile B, threads NT).  B = 8 and
-// 16 make the [point][vector] LDS accesses of a 16-lane group hit 16 distinct
-// 8-byte bank pairs.  A shape that does not fit the LDS has B = 0.
+// Launch shapes of the box-cell kernel: vector tile B, threads NT (0: the
+// fewest whole wavefronts that cover the largest phase, nq^2 B / C tasks),
+// columns per thread C, and the one-shot grid (one workgroup per item) or the
+// persistent grid (resident workgroups, next item prefetched).  B = 8 and 16
+// make the [point][vector] LDS accesses of the lanes of one pencil contiguous.
+// A shape that does not fit the LDS has B = 0.
 struct BoxCfg {
   int B, NT;
+  int C = 1;
+  bool pers = false;
 };
-constexpr BoxCfg box_cfg(int np, int nq, int idx) {
-  // 0: default: B = 8 with 512 threads (the fastest shape measured for p = 6
-  //    and p = 8), else the largest of 4/2/1 that fits, 256 threads
-  // 1: B = 8, 256 threads;  2: B = 16, 512 threads;  3: B = 4, 128 threads
-  // 4: B = 8, 512 threads;  5: B = 16, 256 threads;  6: B = 8, 128 threads;
-  // 7: B = 4, 256 threads
-  BoxCfg c{0, 256};
-  if (idx == 0) {
-    if (box_lds_bytes(np, nq, 8) <= 80 * 1024) return BoxCfg{8, 512};
-    for (int b = 4; b >= 1; b /= 2)
-      if (box_lds_bytes(np, nq, b) <= kLdsMax) return BoxCfg{b, 256};
-    return c;
+constexpr BoxCfg box_cfg_raw(int idx) {
+  switch (idx) {
+    case 1: return BoxCfg{8, 512, 1, false};
+    case 2: return BoxCfg{8, 256, 2, false};
+    case 3: return BoxCfg{8, 512, 1, true};
+    case 4: return BoxCfg{8, 256, 2, true};
+    case 5: return BoxCfg{8, 0, 1, true};
+    case 6: return BoxCfg{8, 0, 1, false};
+    case 7: return BoxCfg{4, 256, 1, false};
+    case 8: return BoxCfg{4, 0, 1, true};
+    case 9: return BoxCfg{4, 0, 1, false};
+    default: return BoxCfg{0, 256, 1, false};
   }
-  if (idx == 1) c = BoxCfg{8, 256};
-  if (idx == 2) c = BoxCfg{16, 512};
-  if (idx == 3) c = BoxCfg{4, 128};
-  if (idx == 4) c = BoxCfg{8, 512};
-  if (idx == 5) c = BoxCfg{16, 256};
-  if (idx == 6) c = BoxCfg{8, 128};
-  if (idx == 7) c = BoxCfg{4, 256};
-  if (box_lds_bytes(np, nq, c.B) > kLdsMax) c.B = 0;
+}
+constexpr BoxCfg box_cfg_fix(int np, int nq, BoxCfg c) {
+  if (c.NT == 0) {
+    const int tasks = nq * nq * (c.B / c.C);
+    c.NT = (tasks + 63) / 64 * 64;
+    if (c.NT > 1024) c.NT = 1024;
+  }
+  if (c.B == 0 || box_lds_bytes(np, nq, c.B) > kLdsMax) c.B = 0;
+  (void)np;
   return c;
+}
+constexpr BoxCfg box_cfg(int np, int nq, int idx) {
+  // 0: default (fastest measured per size class): one-shot, B = 8, fewest
+  //    whole wavefronts when two 8-column cell buffers fit in 80 KiB of LDS
+  //    (three workgroups per CU); else persistent B = 8 if it fits the LDS at
+  //    all, else persistent B = 4.  1 .. 9: fixed shapes, for the tuner.
+  if (idx == 0) {
+    if (box_lds_bytes(np, nq, 8) <= 80 * 1024) return box_cfg_fix(np, nq, box_cfg_raw(6));
+    if (box_lds_bytes(np, nq, 8) <= kLdsMax) return box_cfg_fix(np, nq, box_cfg_raw(5));
+    return box_cfg_fix(np, nq, box_cfg_raw(8));
+  }
+  return box_cfg_fix(np, nq, box_cfg_raw(idx));
+}
+// Shape with one column per thread and the same tile, used when a call cannot
+// take 16-byte column pairs (odd nvec or leading dimension, unaligned X or Y).
+constexpr int box_cfg_single(int np, int nq, int idx) {
+  const BoxCfg c = box_cfg(np, nq, idx);
+  if (c.C == 1) return idx;
+  if (c.B >= 8 && box_cfg(np, nq, c.pers ? 5 : 6).B > 0) return c.pers ? 5 : 6;
+  return c.pers ? 8 : 9;
+}
+// Workgroups per CU that the LDS allows, and the matching waves per SIMD the
+// register allocation must leave room for.
+constexpr int box_wg_per_cu(int np, int nq, int B) {
+  const size_t l = box_lds_bytes(np, nq, B);
+  int n = (int)(kLdsMax / (l > 0 ? l : 1));
+  return n < 1 ? 1 : (n > 8 ? 8 : n);
+}
+constexpr int box_waves_per_eu(int np, int nq, int B, int NT) {
+  const int w = (box_wg_per_cu(np, nq, B) * (NT / 64) + 3) / 4;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
 // LDS bytes of the mixed-precision kernel: 64-bit X and Y row offsets, two FP32

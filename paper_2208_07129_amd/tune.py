@@ -21,7 +21,7 @@ from typing import Optional, Sequence
 from . import mfmv
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mfmv_tune.json")
-N_BOX, N_MIXED, N_BATCH = 8, 4, 3
+N_BOX, N_MIXED, N_BATCH = mfmv.BOX_CFGS, mfmv.MIXED_CFGS, mfmv.BATCH_CFGS
 
 
 def _arch() -> str:

@@ -213,23 +213,52 @@ BOX_CASES = [
 @pytest.mark.parametrize("p,q,n,bc,nvec", BOX_CASES)
 def test_box_kernel_every_launch_shape(p, q, n, bc, nvec):
     """Every built launch shape of the axis-aligned-cell kernel, plus the general kernel
-    forced on the same box mesh, against the oracle (ragged column tiles)."""
+    forced on the same box mesh, against the oracle (ragged column tiles).  Each case
+    runs with the odd column count given (one column per thread everywhere) and the
+    next even one (two-column shapes take their 16-byte path)."""
     mesh = W.BoxMesh(n=n, lo=(0.0, -0.5, 0.25), hi=(1.0, 1.0, 1.5), bc=bc)
     op, orc = build_pair(mesh, p, q)
-    X = np.random.default_rng(p * 7 + q).uniform(-1, 1, (orc.ndofs, nvec))
+    cases = []
+    for nv in (nvec, nvec + 1):
+        X = np.random.default_rng(p * 7 + q + nv).uniform(-1, 1, (orc.ndofs, nv))
+        cases.append((X, orc.apply(X)))
+    for X, Yref in cases:
+        ran = 0
+        for cfg in range(mfmv.BOX_CFGS):
+            try:
+                op.set_launch(False, cfg)
+            except mfmv.MfError as e:
+                assert e.status == mfmv.MF_ERR_UNSUPPORTED
+                continue
+            assert colrel(gpu_apply(op, X), Yref) <= TOL, (X.shape[1], cfg)
+            ran += 1
+        assert ran >= 1
+    op.set_launch(True, -1)  # the general kernel on the same box mesh (irreversible)
+    for X, Yref in cases:
+        assert colrel(gpu_apply(op, X), Yref) <= TOL
+
+
+@pytest.mark.parametrize("layout", ["odd_ld", "unaligned"])
+def test_box_two_column_shapes_fall_back(layout):
+    """A two-column launch shape on a call that cannot take 16-byte column pairs (odd
+    leading dimension, 8-byte aligned multivectors) runs the one-column shape."""
+    mesh = W.BoxMesh(n=(2, 2, 2), bc=W.BC_PERIODIC)
+    op, orc = build_pair(mesh, 5, 6)
+    nvec = 10
+    X = np.random.default_rng(5).uniform(-1, 1, (orc.ndofs, nvec))
     Yref = orc.apply(X)
-    ran = 0
-    for cfg in range(4):
-        try:
-            op.set_launch(False, cfg)
-        except mfmv.MfError as e:
-            assert e.status == mfmv.MF_ERR_UNSUPPORTED
-            continue
-        assert colrel(gpu_apply(op, X), Yref) <= TOL, cfg
-        ran += 1
-    assert ran >= 1
-    op.set_launch(True, -1)
-    assert colrel(gpu_apply(op, X), Yref) <= TOL
+    ld = nvec + 1 if layout == "odd_ld" else nvec
+    off = 0 if layout == "odd_ld" else 1
+    Xb = torch.zeros(orc.ndofs * ld + off, dtype=torch.float64, device=dev())
+    Yb = torch.full_like(Xb, float("nan"))
+    Xb[off:].view(orc.ndofs, ld)[:, :nvec] = torch.from_numpy(X).to(dev())
+    for cfg in (0, 2, 3):
+        op.set_launch(False, cfg)
+        Yb.fill_(float("nan"))
+        op.apply_ptr(Xb.data_ptr() + 8 * off, Yb.data_ptr() + 8 * off, nvec, ld, ld)
+        torch.cuda.synchronize()
+        Y = Yb[off:].view(orc.ndofs, ld)[:, :nvec].cpu().numpy()
+        assert colrel(Y, Yref) <= TOL, (layout, cfg)
 
 
 def test_box_accumulate_and_timing():
