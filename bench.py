@@ -42,14 +42,27 @@ def flops_per_cell_vector(p: int, q: int) -> int:
     return 4 * (n ** 3 * m + n ** 2 * m ** 2 + n * m ** 3) + 12 * m ** 4 + 18 * m ** 3
 
 
+def _eo_flops(m: int, n: int) -> int:
+    """Flops of one even-odd matvec (m outputs, n inputs): fold 2 floor(n/2), per
+    output pair 2(h + mid) - 1 + 2h - 1 + 2, the middle row 2(h + mid) - 1."""
+    h, mi, ho, mo = n // 2, n % 2, m // 2, m % 2
+    return 2 * h + ho * (4 * h + 2 * mi) + mo * (2 * h + 2 * mi - 1)
+
+
 def executed_flops_per_cell_vector(p: int, q: int, box: bool) -> int:
-    """FP64 flops the axis-aligned-cell kernel executes per cell and column: N and N^T
-    stages as above, one collapsed symmetric contraction per direction 6 nq^4, and
-    7 nq^3 for the per-point scaling and sums (exact-zero coefficients not discounted)."""
+    """FP64 flops the axis-aligned-cell kernel executes per cell and column: every 1D
+    contraction in even-odd form, the collapsed symmetric derivative contraction
+    per direction, and the per-point scaling and sums (zero coefficients counted)."""
     n, m = p + 1, q
     if not box:
         return flops_per_cell_vector(p, q)
-    return 4 * (n ** 3 * m + n ** 2 * m ** 2 + n * m ** 3) + 6 * m ** 4 + 7 * m ** 3
+    interp = _eo_flops(m, n)      # N, nq x np
+    back = _eo_flops(n, m)        # N^T, np x nq
+    lap = _eo_flops(m, m)         # Lf, nq x nq
+    return (n * n * interp + m * n * interp + m * m * interp            # P1 - P3
+            + m * m * (lap + m) + m * m * (lap + 2 * m)                   # P4, P5
+            + m * m * (2 * m + lap + 2 * m + back)                        # P6
+            + m * n * back + n * n * back)                                # P7, P8
 
 
 def kernel_hash() -> str:
@@ -125,6 +138,100 @@ def cpu_baseline_leg(w, Y_gpu_rows_fn, sample_cells: int):
     }, rel
 
 
+def mixed_leg(op, X, Y64, nvec, steps, sptr, free):
+    """FP32 / BF16 matrix-core apply on the same workload: fused-kernel and step
+    time, speedup over the FP64 step, and the error of the result against the FP64
+    result (max over columns of the relative 2-norm error)."""
+    import torch
+    from paper_2208_07129_amd import mfmv
+    res = {}
+    base_ms = None
+    for name in ("fp64", "fp32", "bf16"):
+        prec = mfmv.PRECISIONS[name]
+        Yp = torch.empty_like(X)
+
+        def step():
+            op.apply_ptr(X.data_ptr(), Yp.data_ptr(), nvec, nvec, nvec, prec, sptr)
+        for _ in range(3):
+            step()
+        op.timing(steps)
+        for _ in range(steps):
+            step()
+        n_ev, zero_sum, kern_sum = op.timing_read()
+        op.timing(0)
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        for _ in range(steps):
+            step()
+        s1.record()
+        torch.cuda.synchronize()
+        ms = s0.elapsed_time(s1) / steps
+        if name == "fp64":
+            base_ms = ms
+            continue
+        err = (torch.linalg.norm(Yp - Y64, dim=0) / torch.linalg.norm(Y64, dim=0)).max().item()
+        res[name] = {"ms_per_step": ms, "kernel_ms": kern_sum / n_ev,
+                     "value": free * nvec / (ms * 1e-3) / 1e9, "unit": UNIT,
+                     "speedup_vs_fp64": base_ms / ms, "rel_err_vs_fp64": err}
+    return res
+
+
+def solve_leg(a) -> dict:
+    """Block-CG solve of (A + sigma M) X = B on the 20^3 periodic p = 6 mesh with 128
+    right-hand sides to a true FP64 relative residual of 1e-10 in every column:
+    Jacobi with the FP64 apply, Jacobi with the FP32 matrix-core apply inside FP64
+    iterative refinement, and the learned cell-local preconditioner (Jacobi fallback)
+    with the same mixed apply; network training time reported separately."""
+    import torch
+    from paper_2208_07129_amd import blockcg, mfmv, mlp
+    w = W.config5()
+    if a.nvec:
+        w.nvec = a.nvec
+    op = mfmv.Operator.from_workload(w)
+    B = torch.from_numpy(w.X()).cuda()
+    diag = mfmv.diagonal(op)
+    lam = blockcg.lanczos_extremes(op, steps=a.lanczos_steps)
+    out = {"metric": "time to 1e-10 relative residual (block CG, 128 RHS)", "unit": "s",
+           "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": w.name, "cells": int(op.ncells), "p": w.p, "q": w.q,
+                      "ndofs": int(op.ndofs), "nvec": w.nvec, "sigma": w.sigma},
+           "lanczos": lam, "solves": {}}
+    jac = blockcg.jacobi_preconditioner(diag)
+    runs = [("jacobi_fp64", jac, "fp64", None), ("jacobi_mixed_fp32", jac, "fp32", None)]
+    for name, M, prec, fb in runs:
+        torch.cuda.synchronize()
+        X, st = blockcg.solve(op, B, M, tol=1e-10, maxit=a.solve_maxit, inner_precision=prec,
+                              fallback=fb)
+        out["solves"][name] = {"seconds": st.seconds, "iterations": st.iterations,
+                               "refinements": st.refinements, "converged": st.converged,
+                               "rel_residual": st.rel_residual, "breakdown": st.breakdown}
+        print(json.dumps({name: out["solves"][name]}), file=sys.stderr, flush=True)
+        del X
+    # learned preconditioner: train on operator-generated pairs, judge, solve
+    t0 = time.perf_counter()
+    net = mlp.CellMLP(op, hidden=256, seed=0)
+    losses = mlp.train(net, diag, steps=a.train_steps, k=16, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    verdict = mlp.judge(net, diag, k=16)
+    out["training"] = {"seconds": t_train, "steps": a.train_steps, "loss_first": losses[0],
+                       "loss_last": float(np.mean(losses[-10:])), "judge": verdict}
+    use_net = verdict["ratio"] < 1.0
+    M = net.preconditioner(diag) if use_net else jac
+    X, st = blockcg.solve(op, B, M, tol=1e-10, maxit=a.solve_maxit, inner_precision="fp32",
+                          fallback=jac if use_net else None)
+    out["solves"]["learned_mixed_fp32"] = {
+        "seconds": st.seconds, "iterations": st.iterations, "refinements": st.refinements,
+        "converged": st.converged, "rel_residual": st.rel_residual, "breakdown": st.breakdown,
+        "network_used": use_net, "fallback_switches": st.precond_switches}
+    j = out["solves"]["jacobi_mixed_fp32"]
+    out["value"] = st.seconds
+    out["learned_vs_jacobi_mixed"] = {"time_ratio": st.seconds / j["seconds"],
+                                      "iteration_ratio": st.iterations / max(j["iterations"], 1)}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +242,13 @@ def main(argv=None):
     ap.add_argument("--nvec", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-cells", type=int, default=512)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP32 / BF16 matrix-core comparison of an FP64 run")
+    ap.add_argument("--solve", action="store_true",
+                    help="block-CG solve benchmark on the 20^3 p = 6 mesh (own JSON line)")
+    ap.add_argument("--solve-maxit", type=int, default=4000)
+    ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--lanczos-steps", type=int, default=120)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of X into Y (known bytes), for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -151,6 +265,9 @@ def main(argv=None):
         raise SystemExit("no HIP device")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.solve:
+        print(json.dumps(solve_leg(a)), flush=True)
+        return 0
     w = workload(a.workload, a.nvec)
     prec = mfmv.PRECISIONS[a.precision]
     op = mfmv.Operator.from_workload(w)
@@ -213,6 +330,8 @@ def main(argv=None):
                      "executed_frac": executed / (kern_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS},
         "zero_fill_ms": zero_ms,
     }
+    if a.precision == "fp64" and not a.no_mixed:
+        out["mixed"] = mixed_leg(op, X, Y, nvec, a.steps, sptr, free)
     if not a.no_cpu_baseline:
         def rows_fn(rows):
             idx = torch.from_numpy(np.asarray(rows)).to(dev)

@@ -1,0 +1,93 @@
+/* libmfmv: kernels of the learned cell-local preconditioner for block CG,
+ *   Z = sum_e Q_e^T W_e f_theta(Q_e R),
+ * with f_theta a small MLP (F = np^3 inputs and outputs, two hidden ReLU
+ * layers), Q_e the extraction of cell e's nodes (Sec. 3.2.3) and W_e the
+ * partition-of-unity weights (1 / number of cells sharing the node).  The
+ * network is applied to every (cell, column) of a residual block and trained
+ * on the GPU by these kernels; the method generates its own training pairs
+ * (residual -> error) with the operator apply.
+ *
+ * Batches are feature-major: an activation block is features x rows with row
+ * = e * k + j for cell e and column j of a k-column multivector, element
+ * (i, row) at V[i * ld + row].  BF16 data are passed as uint16_t (the upper
+ * half of an IEEE single, round to nearest even).  Every call is
+ * stream-ordered on `stream` (hipStream_t, NULL = default), allocates nothing
+ * and returns MF_OK or a negative mf_status (message in mf_last_error()).
+ */
+#ifndef MFMLP_H
+#define MFMLP_H
+
+#include <stdint.h>
+
+#include "mfmv.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C = op(A) op(B) on the matrix cores (BF16 operands, FP32 accumulation),
+ * then the epilogue, for every (m, n) < (M, N):
+ *   v = C[m][n] (+ bias[m]) (ReLU) (* [mask[m][n] > 0]),
+ *   out_f32[m*ld_f32 + n] = v (or += v with atomic != 0), and/or
+ *   out_bf16[m*ld_bf16 + n] = bf16(v).
+ * A is M x K row-major (lda), or K x M when ta != 0; B is K x N row-major
+ * (ldb), or N x K when tb != 0.  M, N, K, lda, ldb must be multiples of 8 and
+ * A, B 16-byte aligned.  kchunk > 0 splits K into ceil(K / kchunk) ranges run
+ * by separate workgroups (use with atomic != 0, no bias or ReLU, on a zeroed
+ * out_f32); kchunk <= 0 takes K whole.  bias (FP32, M), mask (BF16, ldmask),
+ * out_f32 and out_bf16 may be NULL (at least one output).  Errors:
+ * MF_ERR_ARG, MF_ERR_HIP. */
+int mf_mlp_gemm(int M, int N, int K, int ta, int tb, const uint16_t* A, int64_t lda,
+                const uint16_t* B, int64_t ldb, int kchunk, const float* bias, int relu,
+                const uint16_t* mask, int64_t ldmask, float* out_f32, int64_t ld_f32, int atomic,
+                uint16_t* out_bf16, int64_t ld_bf16, void* stream);
+
+/* Network input of every (cell, column): rho[row] = RMS over the cell's F =
+ * np^3 node values of column j of R (constrained nodes count as 0) and
+ * X0t[i][row] = bf16(R[node_i][j] / rho) (0 when rho = 0; rows F <= i < Fp
+ * zero).  With E != NULL also Tt[i][row] = E[node_i][j] / rho (FP32): the
+ * training target for the pair (R, E).  R and E are ndofs x k multivectors
+ * (ldr, lde >= k); X0t and Tt are Fp x (ncells k) with leading dimension
+ * ldx >= ncells k; rho has ncells k entries.  Fp >= F, multiple of 8.
+ * Errors: MF_ERR_ARG, MF_ERR_HIP. */
+int mf_cell_gather(mf_operator* op, int k, const double* R, int64_t ldr, const double* E,
+                   int64_t lde, int Fp, uint16_t* X0t, float* Tt, int64_t ldx, float* rho,
+                   void* stream);
+
+/* Z := Z0 + sum_e Q_e^T W_e (rho * Yt): the partition-of-unity assembly of
+ * the network outputs Yt (FP32, first F rows used, ldy >= ncells k) scaled
+ * back by rho, on top of Z0 = R / diag row-wise (the Jacobi term) when diag
+ * != NULL, else Z0 = 0.  Z (ndofs x k, ldz >= k) is overwritten; it must not
+ * be R.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+int mf_cell_scatter(mf_operator* op, int k, const float* Yt, int64_t ldy, const float* rho,
+                    const double* diag, const double* R, int64_t ldr, double* Z, int64_t ldz,
+                    void* stream);
+
+/* Mean squared error over rows and the first F features:
+ * *loss += sum_{i<F, n<N} (Yt - Tt)^2 / N (device double, accumulated), and
+ * dYt = bf16(2 (Yt - Tt) / N) (rows F <= i < Fp written as 0).  Yt, Tt, dYt
+ * share the leading dimension ld.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+int mf_mse_grad(int F, int Fp, int64_t N, const float* Yt, const float* Tt, int64_t ld,
+                uint16_t* dYt, double* loss, void* stream);
+
+/* out[m] = (accumulate ? out[m] : 0) + sum_{n<N} X[m*ld + n] for m < M (BF16
+ * X, FP32 out): bias gradients.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+int mf_row_sums(int M, int64_t N, const uint16_t* X, int64_t ld, float* out, int accumulate,
+                void* stream);
+
+/* One Adam step (step >= 1) on n FP32 parameters w with gradient g and
+ * moments m1, m2 (FP32, updated); with wbf != NULL the updated parameters are
+ * also written as BF16.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+int mf_adam(int64_t n, float* w, const float* g, float* m1, float* m2, uint16_t* wbf, float lr,
+            float beta1, float beta2, float eps, int step, void* stream);
+
+/* dst = bf16(src) (n values); mf_fill_f32: v[i] = x.  Errors: MF_ERR_ARG,
+ * MF_ERR_HIP. */
+int mf_to_bf16(int64_t n, const float* src, uint16_t* dst, void* stream);
+int mf_fill_f32(int64_t n, float* v, float x, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFMLP_H */

@@ -1,0 +1,85 @@
+/* libmfmv: building blocks of the block-CG solve of A X = B (A from
+ * mfmv.h, X and B multivectors of k columns) and of its Jacobi fallback
+ * preconditioner.
+ *
+ * All multivectors are dof-major FP64 device arrays: column j of row i at
+ * V[i * ld + j], ld >= k.  Every call is stream-ordered and asynchronous on
+ * `stream` (a hipStream_t, NULL = the default stream), allocates nothing and
+ * returns MF_OK or a negative mf_status (message in mf_last_error()).
+ * Arguments are checked on the host: NULL pointers, n < 0, k < 1, ld < k
+ * give MF_ERR_ARG; a failing HIP or rocBLAS launch gives MF_ERR_HIP.
+ */
+#ifndef MFSOLVE_H
+#define MFSOLVE_H
+
+#include <stdint.h>
+
+#include "mfmv.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Diagonal of the operator for point-Jacobi preconditioning of block CG: for
+ * every free dof i, diag[i] = A_ii = sum_e A^(e)_ii, the diagonal of the
+ * element matrices of eq. stiffnessmatinteg / eq. massmatinteg (with the
+ * potential and sigma) assembled over the cells that share i; constrained
+ * (Dirichlet) rows get 1.  On the affine cells of a box mesh the 3x3 factor G
+ * of eq. sjacobian is constant per cell, so the stiffness part separates into
+ * 1D sums of the folded basis and derivative tables (Sec. 3.2.4); the
+ * potential part sums det J (V + sigma) N_I^2 over the cell's quadrature
+ * points.  `diag` is a device array of mf_operator_info's ndofs entries owned
+ * by the caller.  Errors: MF_ERR_ARG (NULL), MF_ERR_HIP. */
+int mf_diagonal(mf_operator* op, double* diag, void* stream);
+
+/* C := alpha * A^T B + beta * C, the k x k Gram block of two n x k
+ * multivectors (block CG: P^T A P, P^T R, (A P)^T Z).  C is row-major with
+ * leading dimension ldc >= k, on the device; with beta = 0 its old contents
+ * are ignored.  A plain GEMM, run by rocBLAS dgemm.  Errors: MF_ERR_ARG,
+ * MF_ERR_HIP. */
+int mf_block_gram(int64_t n, int k, const double* A, int64_t lda, const double* B, int64_t ldb,
+                  double alpha, double beta, double* C, int ldc, void* stream);
+
+/* Y := beta * Y + alpha * P M, with P an n x kp multivector (ldp), M a kp x k
+ * row-major device matrix (ldm >= k) and Y n x k (ldy).  Y must not overlap P
+ * or M.  Block-CG updates X += P alpha, R -= (A P) alpha, Z += P beta.  A
+ * plain GEMM, run by rocBLAS dgemm.  Errors: MF_ERR_ARG (also for overlap),
+ * MF_ERR_HIP. */
+int mf_block_update(int64_t n, int k, int kp, double alpha, const double* P, int64_t ldp,
+                    const double* M, int ldm, double beta, double* Y, int64_t ldy, void* stream);
+
+/* out[j] := sum_i A[i*lda + j] B[i*ldb + j] for j < k: column dot products
+ * (residual norms with A = B, the descent check z_j^T r_j of the learned
+ * preconditioner).  `out` is a device array of k doubles.  Errors:
+ * MF_ERR_ARG, MF_ERR_HIP. */
+int mf_col_dots(int64_t n, int k, const double* A, int64_t lda, const double* B, int64_t ldb,
+                double* out, void* stream);
+
+/* Y := a X + b Y on n x k multivectors; with b = 0, Y is only written.  Y may
+ * equal X (same ld) but not overlap it otherwise.  Errors: MF_ERR_ARG,
+ * MF_ERR_HIP. */
+int mf_axpby(int64_t n, int k, double a, const double* X, int64_t ldx, double b, double* Y,
+             int64_t ldy, void* stream);
+
+/* Z := R / diag row-wise (Z[i*ldz + j] = R[i*ldr + j] / diag[i]): the point
+ * Jacobi preconditioner.  Z may equal R (same ld).  Errors: MF_ERR_ARG,
+ * MF_ERR_HIP. */
+int mf_jacobi(int64_t n, int k, const double* diag, const double* R, int64_t ldr, double* Z,
+              int64_t ldz, void* stream);
+
+/* X := G^{-1} S for a symmetric positive definite k x k block G and a k x m
+ * block S (row-major, leading dimensions k and m, device): Cholesky
+ * factorisation and two triangular solves in one workgroup, the k x k step of
+ * block CG (alpha = (P^T A P)^{-1} P^T R).  G and S are not modified; X must
+ * not overlap them.  If a pivot is not positive (G not numerically SPD),
+ * *status (device int) is set to that pivot's index + 1 and X is left
+ * unspecified; otherwise *status = 0.  Errors: MF_ERR_ARG (NULL, k < 1,
+ * m < 1), MF_ERR_UNSUPPORTED (k > 128 or m > 256), MF_ERR_HIP. */
+int mf_spd_solve(int k, int m, const double* G, const double* S, double* X, int* status,
+                 void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFSOLVE_H */

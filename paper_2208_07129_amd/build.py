@@ -21,6 +21,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libmfmv.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 MAX_P = 10
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
@@ -42,6 +43,10 @@ def jobs():
         ("capi_batch.cpp", "capi_batch.o", []),
         ("host_setup.cpp", "host_setup.o", []),
         ("dispatch.hip", "dispatch.o", []),
+        ("solver.hip", "solver.o", []),
+        ("capi_solver.cpp", "capi_solver.o", []),
+        ("mlp.hip", "mlp.o", []),
+        ("capi_mlp.cpp", "capi_mlp.o", []),
     ]
     for p in range(1, MAX_P + 1):
         out.append(("apply_f64.hip", f"apply_f64_p{p}.o", [f"-DMF_P={p}"]))
@@ -75,7 +80,8 @@ def build(nproc: int | None = None, verbose: bool = False) -> str:
                 print("compiled", objs[-1], flush=True)
     tmp = OUT + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
-           *[os.path.join(BUILD, o) for o in objs]]
+           *[os.path.join(BUILD, o) for o in objs], f"-L{ROCM_LIB}", "-lrocblas",
+           f"-Wl,-rpath,{ROCM_LIB}"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

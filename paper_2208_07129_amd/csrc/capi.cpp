@@ -247,6 +247,20 @@ int mf_create_operator(const mf_box_mesh* mesh, int p, int q, double mu, const d
   if (!s) s = alloc_copy((void**)&op->d_order, order.data(), order.size() * sizeof(int32_t));
   if (!s) s = alloc_copy((void**)&op->d_geo, geo.data(), geo.size() * sizeof(double));
   if (!s) s = alloc_copy((void**)&op->d_vq, vq.data(), vq.size() * sizeof(double));
+  if (!s) {
+    // 1D sums of the diagonal (mf_diagonal): [w N^2 (nq x np) | a | b | c]
+    const Tables1D& t = op->t;
+    std::vector<double> tab((size_t)q * np + 3 * np, 0.0);
+    for (int a = 0; a < q; ++a)
+      for (int i = 0; i < np; ++i) {
+        const double n = t.N[a * np + i], d = t.D[a * np + i], w = t.wq[a];
+        tab[a * np + i] = w * n * n;
+        tab[q * np + i] += w * d * d;
+        tab[q * np + np + i] += w * n * n;
+        tab[q * np + 2 * np + i] += w * d * n;
+      }
+    s = alloc_copy((void**)&op->d_dtab, tab.data(), tab.size() * sizeof(double));
+  }
   if (s) {
     mf_destroy_operator(reinterpret_cast<mf_operator*>(op));
     return s;
@@ -263,6 +277,7 @@ void mf_destroy_operator(mf_operator* handle) {
   for (hipEvent_t e : op->ev) (void)hipEventDestroy(e);
   if (op->d_geo) (void)hipFree(op->d_geo);
   if (op->d_vq) (void)hipFree(op->d_vq);
+  if (op->d_dtab) (void)hipFree(op->d_dtab);
   delete op;
 }
 

@@ -1,0 +1,149 @@
+// C ABI of the block-CG building blocks (include/mfsolve.h).  The Gram
+// blocks and block updates are plain GEMMs on row-major (dof-major)
+// multivectors and go to rocBLAS dgemm, read as column-major transposes; the
+// rest are the library's kernels (solver.hip).
+#include <mutex>
+#include <vector>
+
+#include <rocblas/rocblas.h>
+
+#include "mf_internal.h"
+#include "mfsolve.h"
+
+namespace mf {
+
+// One rocBLAS handle per device, created on first use and kept for the life
+// of the process (handles are not thread-safe: calls are serialised).
+static std::mutex g_blas_mutex;
+static std::vector<rocblas_handle> g_blas;
+
+static int blas_handle(rocblas_handle* h) {
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return hip_fail(err, "hipGetDevice");
+  if ((int)g_blas.size() <= dev) g_blas.resize(dev + 1, nullptr);
+  if (!g_blas[dev]) {
+    if (rocblas_create_handle(&g_blas[dev]) != rocblas_status_success)
+      return fail(MF_ERR_HIP, "rocblas_create_handle failed");
+  }
+  *h = g_blas[dev];
+  return MF_OK;
+}
+
+static int blas_fail(rocblas_status st, const char* what) {
+  return fail(MF_ERR_HIP, std::string(what) + ": " + rocblas_status_to_string(st));
+}
+
+static bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
+  const char* a0 = static_cast<const char*>(a);
+  const char* b0 = static_cast<const char*>(b);
+  return a0 < b0 + bn && b0 < a0 + an;
+}
+
+static size_t span_bytes(int64_t rows, int64_t cols, int64_t ld) {
+  return rows > 0 ? (size_t)((rows - 1) * ld + cols) * sizeof(double) : 0;
+}
+
+}  // namespace mf
+
+using namespace mf;
+
+extern "C" {
+
+int mf_diagonal(mf_operator* handle, double* diag, void* stream) {
+  if (!handle || !diag) return fail(MF_ERR_ARG, "operator and diag must be non-NULL");
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  hipError_t err = launch_diagonal(*op, op->d_dtab, diag, static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "diagonal kernel launch");
+  return MF_OK;
+}
+
+int mf_block_gram(int64_t n, int k, const double* A, int64_t lda, const double* B, int64_t ldb,
+                  double alpha, double beta, double* C, int ldc, void* stream) {
+  if (!A || !B || !C) return fail(MF_ERR_ARG, "A, B and C must be non-NULL");
+  if (n < 0 || k < 1 || lda < k || ldb < k || ldc < k)
+    return fail(MF_ERR_ARG, "need n >= 0, k >= 1, lda, ldb, ldc >= k");
+  if (n > INT32_MAX || lda > INT32_MAX || ldb > INT32_MAX)
+    return fail(MF_ERR_UNSUPPORTED, "n and leading dimensions must fit in 32 bits");
+  std::lock_guard<std::mutex> lock(g_blas_mutex);
+  rocblas_handle h;
+  if (int s = blas_handle(&h)) return s;
+  rocblas_set_stream(h, static_cast<hipStream_t>(stream));
+  // column-major: C^T (k x k) = B^T(k x n) * A(n x k)  <=>  row-major C = A^T B
+  rocblas_status st =
+      rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, k, k, (rocblas_int)n,
+                    &alpha, B, (rocblas_int)ldb, A, (rocblas_int)lda, &beta, C, ldc);
+  if (st != rocblas_status_success) return blas_fail(st, "rocblas_dgemm (gram)");
+  return MF_OK;
+}
+
+int mf_block_update(int64_t n, int k, int kp, double alpha, const double* P, int64_t ldp,
+                    const double* M, int ldm, double beta, double* Y, int64_t ldy, void* stream) {
+  if (!P || !M || !Y) return fail(MF_ERR_ARG, "P, M and Y must be non-NULL");
+  if (n < 0 || k < 1 || kp < 1 || ldp < kp || ldm < k || ldy < k)
+    return fail(MF_ERR_ARG, "need n >= 0, k, kp >= 1, ldp >= kp, ldm >= k, ldy >= k");
+  if (n > INT32_MAX || ldp > INT32_MAX || ldy > INT32_MAX)
+    return fail(MF_ERR_UNSUPPORTED, "n and leading dimensions must fit in 32 bits");
+  const size_t ys = span_bytes(n, k, ldy);
+  if (overlaps(Y, ys, P, span_bytes(n, kp, ldp)) || overlaps(Y, ys, M, span_bytes(kp, k, ldm)))
+    return fail(MF_ERR_ARG, "Y overlaps P or M");
+  if (n == 0) return MF_OK;
+  std::lock_guard<std::mutex> lock(g_blas_mutex);
+  rocblas_handle h;
+  if (int s = blas_handle(&h)) return s;
+  rocblas_set_stream(h, static_cast<hipStream_t>(stream));
+  // column-major: Y^T (k x n) = beta Y^T + alpha M^T (k x kp) P^T (kp x n)
+  rocblas_status st =
+      rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, k, (rocblas_int)n, kp,
+                    &alpha, M, ldm, P, (rocblas_int)ldp, &beta, Y, (rocblas_int)ldy);
+  if (st != rocblas_status_success) return blas_fail(st, "rocblas_dgemm (update)");
+  return MF_OK;
+}
+
+int mf_col_dots(int64_t n, int k, const double* A, int64_t lda, const double* B, int64_t ldb,
+                double* out, void* stream) {
+  if (!A || !B || !out) return fail(MF_ERR_ARG, "A, B and out must be non-NULL");
+  if (n < 0 || k < 1 || lda < k || ldb < k) return fail(MF_ERR_ARG, "need n >= 0, k >= 1, ld >= k");
+  hipError_t err = launch_col_dots(n, k, A, lda, B, ldb, out, static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "column-dot kernel launch");
+  return MF_OK;
+}
+
+int mf_axpby(int64_t n, int k, double a, const double* X, int64_t ldx, double b, double* Y,
+             int64_t ldy, void* stream) {
+  if (!X || !Y) return fail(MF_ERR_ARG, "X and Y must be non-NULL");
+  if (n < 0 || k < 1 || ldx < k || ldy < k) return fail(MF_ERR_ARG, "need n >= 0, k >= 1, ld >= k");
+  if (X != Y && overlaps(Y, span_bytes(n, k, ldy), X, span_bytes(n, k, ldx)))
+    return fail(MF_ERR_ARG, "Y overlaps X without being equal to it");
+  if (X == Y && ldx != ldy) return fail(MF_ERR_ARG, "in place needs ldx == ldy");
+  hipError_t err = launch_axpby(n, k, a, X, ldx, b, Y, ldy, static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "axpby kernel launch");
+  return MF_OK;
+}
+
+int mf_jacobi(int64_t n, int k, const double* diag, const double* R, int64_t ldr, double* Z,
+              int64_t ldz, void* stream) {
+  if (!diag || !R || !Z) return fail(MF_ERR_ARG, "diag, R and Z must be non-NULL");
+  if (n < 0 || k < 1 || ldr < k || ldz < k) return fail(MF_ERR_ARG, "need n >= 0, k >= 1, ld >= k");
+  if (Z != R && overlaps(Z, span_bytes(n, k, ldz), R, span_bytes(n, k, ldr)))
+    return fail(MF_ERR_ARG, "Z overlaps R without being equal to it");
+  if (Z == R && ldz != ldr) return fail(MF_ERR_ARG, "in place needs ldz == ldr");
+  hipError_t err = launch_jacobi(n, k, diag, R, ldr, Z, ldz, static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "Jacobi kernel launch");
+  return MF_OK;
+}
+
+int mf_spd_solve(int k, int m, const double* G, const double* S, double* X, int* status,
+                 void* stream) {
+  if (!G || !S || !X || !status) return fail(MF_ERR_ARG, "G, S, X and status must be non-NULL");
+  if (k < 1 || m < 1) return fail(MF_ERR_ARG, "need k, m >= 1");
+  if (k > spd_max_k() || m > 256) return fail(MF_ERR_UNSUPPORTED, "need k <= 128 and m <= 256");
+  const size_t xs = span_bytes(k, m, m);
+  if (overlaps(X, xs, G, span_bytes(k, k, k)) || overlaps(X, xs, S, xs))
+    return fail(MF_ERR_ARG, "X overlaps G or S");
+  hipError_t err = launch_spd_solve(k, m, G, S, X, status, static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "SPD solve kernel launch");
+  return MF_OK;
+}
+
+}  // extern "C"

@@ -71,6 +71,7 @@ struct Operator {
   int32_t* d_order = nullptr; // E: processing order of the cells
   double* d_geo = nullptr;    // E x 6: mu det J (J^-1 J^-T), (00,01,02,11,12,22)
   double* d_vq = nullptr;     // E x nq^3: det J (V + sigma)
+  double* d_dtab = nullptr;   // 1D sums of the diagonal (nq np + 3 np)
   Tables1D t;
   // optional per-launch timing (diagnostics): event triples around the zero
   // fill and the fused kernel of each apply, in a ring
@@ -142,6 +143,48 @@ hipError_t launch_apply_mixed(const Operator& op, const ApplyLaunch& a, int prec
 bool apply_mixed_supported(int p, int q, int cfg);
 int choose_cfg_mixed(int np, int nq, int nvec);
 int choose_cfg_box(int np, int nq, int nvec);
+// block-CG building blocks (solver.hip)
+hipError_t launch_diagonal(const Operator& op, const double* d_tab, double* diag, hipStream_t s);
+hipError_t launch_col_dots(int64_t n, int k, const double* A, int64_t lda, const double* B,
+                           int64_t ldb, double* out, hipStream_t s);
+hipError_t launch_axpby(int64_t n, int k, double a, const double* X, int64_t ldx, double b,
+                        double* Y, int64_t ldy, hipStream_t s);
+hipError_t launch_jacobi(int64_t n, int k, const double* diag, const double* R, int64_t ldr,
+                         double* Z, int64_t ldz, hipStream_t s);
+hipError_t launch_spd_solve(int k, int m, const double* G, const double* S, double* X, int* status,
+                            hipStream_t s);
+int spd_max_k();
+// learned-preconditioner kernels (mlp.hip)
+struct GemmEpi {  // epilogue of the BF16 matrix-core GEMM (see mfmlp.h)
+  const float* bias;
+  int relu;
+  const uint16_t* mask;
+  int64_t ldmask;
+  float* out_f32;
+  int64_t ld_f32;
+  int atomic;
+  uint16_t* out_bf16;
+  int64_t ld_bf16;
+};
+hipError_t launch_gemm_bf16(int M, int N, int K, bool ta, bool tb, const uint16_t* A, int64_t lda,
+                            const uint16_t* B, int64_t ldb, int kchunk, const GemmEpi& ep,
+                            hipStream_t s);
+hipError_t launch_cell_gather(const Operator& op, int k, const double* R, int64_t ldr,
+                              const double* E, int64_t lde, int Fp, uint16_t* X0t, float* Tt,
+                              int64_t ldx, float* rho, hipStream_t s);
+hipError_t launch_cell_scatter(const Operator& op, int k, const float* Yt, int64_t ldy,
+                               const float* rho, const double* diag, const double* R, int64_t ldr,
+                               double* Z, int64_t ldz, hipStream_t s);
+hipError_t launch_mse_grad(int F, int Fp, int64_t nrows, const float* Yt, const float* Tt,
+                           int64_t ld, uint16_t* dYt, double* loss, hipStream_t s);
+hipError_t launch_row_sums(int M, int64_t N, const uint16_t* X, int64_t ld, float* out,
+                           bool accumulate, hipStream_t s);
+hipError_t launch_adam(int64_t n, float* w, const float* g, float* m1, float* m2, uint16_t* wbf,
+                       float lr, float b1, float b2, float eps, int step, hipStream_t s);
+hipError_t launch_to_bf16(int64_t n, const float* src, uint16_t* dst, hipStream_t s);
+hipError_t launch_fill_f32(float* v, int64_t n, float x, hipStream_t s);
+
+
 // Two-column (16-byte) accesses need even nvec and leading dimensions and
 // 16-byte aligned multivectors.
 inline bool box_pairs_ok(const double* X, const double* Y, int nvec, int64_t ldx, int64_t ldy) {

@@ -1,0 +1,385 @@
+// Kernels of the learned cell-local preconditioner: a small MLP applied to
+// every (cell, column) of a residual block, trained on the GPU.
+//
+// Batch layout is feature-major: an activation block is [features][rows],
+// row = e * k + j for cell e and column j, so a layer is C = W^T X with the
+// long batch dimension as the GEMM's N and the weights as the row-major A
+// operand.  The GEMM runs on the gfx950 matrix cores
+// (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation): one 64 x 64
+// output tile per 256-thread workgroup, 2 x 2 waves of 32 x 32, K staged
+// through LDS in steps of 32 with k contiguous per lane, so every fragment is
+// one 16-byte LDS read.  Transposed operands (backward pass) are transposed
+// while being staged.  Epilogues fuse bias, ReLU, the ReLU mask of the
+// backward pass and the BF16 conversion; weight gradients split the batch
+// dimension across workgroups and add FP32 partial tiles atomically.
+#include <cmath>
+
+#include "mf_internal.h"
+#include "sf_common.h"
+
+namespace mf {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+namespace {
+
+constexpr int kTile = 64, kKStep = 32, kPad = 40;  // LDS rows of 80 bytes
+
+// C (M x N) = op(A) (M x K) * op(B) (K x N).  A: row-major M x K (lda), or,
+// with TA, stored K x M.  B: row-major K x N (ldb), or, with TB, stored N x K.
+// M, N, K multiples of 8 (8-element, 16-byte staging chunks).  blockIdx.z
+// takes the K range [z kchunk, (z+1) kchunk).
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256)
+gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A, int64_t lda,
+                 const uint16_t* __restrict__ B, int64_t ldb, int kchunk, GemmEpi ep) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[kTile][kPad];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile][kPad];  // [n][k]
+  const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(K, kb + kchunk);
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = kb; k0 < ke; k0 += kKStep) {
+    const uint4 zero = {0u, 0u, 0u, 0u};
+    if constexpr (!TA) {
+      const int m = t >> 2, kk = (t & 3) * 8;
+      uint4 v = zero;
+      if (m0 + m < M && k0 + kk < ke)
+        v = *reinterpret_cast<const uint4*>(A + (int64_t)(m0 + m) * lda + k0 + kk);
+      *reinterpret_cast<uint4*>(&As[m][kk]) = v;
+    } else {
+      const int kk = t >> 3, m = (t & 7) * 8;
+      uint4 v = zero;
+      if (k0 + kk < ke && m0 + m < M)
+        v = *reinterpret_cast<const uint4*>(A + (int64_t)(k0 + kk) * lda + m0 + m);
+      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) As[m + i][kk] = e[i];
+    }
+    if constexpr (TB) {
+      const int n = t >> 2, kk = (t & 3) * 8;
+      uint4 v = zero;
+      if (n0 + n < N && k0 + kk < ke)
+        v = *reinterpret_cast<const uint4*>(B + (int64_t)(n0 + n) * ldb + k0 + kk);
+      *reinterpret_cast<uint4*>(&Bs[n][kk]) = v;
+    } else {
+      const int kk = t >> 3, n = (t & 7) * 8;
+      uint4 v = zero;
+      if (k0 + kk < ke && n0 + n < N)
+        v = *reinterpret_cast<const uint4*>(B + (int64_t)(k0 + kk) * ldb + n0 + n);
+      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[n + i][kk] = e[i];
+    }
+    __syncthreads();
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+      b[i] = *reinterpret_cast<const bf16x8*>(&Bs[wn + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+
+  // D layout of the 16 x 16 tile: lane -> column lane % 16, rows 4 (lane / 16) + r
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m >= M || n >= N) continue;
+        float v = acc[i][j][r];
+        if (ep.bias) v += ep.bias[m];
+        if (ep.relu) v = v > 0.f ? v : 0.f;
+        if (ep.mask && !(bf16_to_f32(ep.mask[(int64_t)m * ep.ldmask + n]) > 0.f)) v = 0.f;
+        if (ep.out_f32) {
+          float* o = ep.out_f32 + (int64_t)m * ep.ld_f32 + n;
+          if (ep.atomic) unsafeAtomicAdd(o, v);
+          else *o = v;
+        }
+        if (ep.out_bf16) ep.out_bf16[(int64_t)m * ep.ld_bf16 + n] = f32_to_bf16(v);
+      }
+}
+
+// Partition-of-unity weight of a free node: 1 / (number of (cell, local
+// node) occurrences), per direction 2 on a shared cell face, 1 otherwise.
+__device__ inline double pou_weight(const GridDesc& g, int i1, int i2, int i3, int cx, int cy,
+                                    int cz) {
+  const int li[3] = {i1, i2, i3}, c[3] = {cx, cy, cz};
+  double w = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    const bool periodic = g.N[d] == g.n[d] * g.p;
+    const bool lo = li[d] == 0, hi = li[d] == g.p;
+    if (!(lo || hi)) continue;
+    const bool outer = !periodic && ((lo && c[d] == 0) || (hi && c[d] == g.n[d] - 1));
+    if (!outer) w *= 0.5;
+  }
+  return w;
+}
+
+// One workgroup per (cell, chunk of 64 columns); thread t: column t % 64,
+// node phase t / 64.  rho = RMS of the cell's residual column (over the
+// cell's F = np^3 node values, constrained nodes as 0); X0t[i][row] =
+// R[node_i][j] / rho as BF16 (rows i in [F, Fp) zero), Tt[i][row] =
+// E[node_i][j] / rho in FP32 when E is given (training targets).
+constexpr int kCols = 64;
+__global__ void __launch_bounds__(256)
+cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int64_t ldr,
+                   const double* __restrict__ E, int64_t lde, int Fp, uint16_t* __restrict__ X0t,
+                   float* __restrict__ Tt, int64_t ldx, float* __restrict__ rho) {
+  __shared__ double part[256];
+  const int e = blockIdx.x;
+  const int j0 = blockIdx.y * kCols;
+  const int t = threadIdx.x, jj = t % kCols, ph = t / kCols;
+  const int j = j0 + jj;
+  const int F = np * np * np;
+  const int cx = e % g.n[0], cy = (e / g.n[0]) % g.n[1], cz = e / (g.n[0] * g.n[1]);
+  double ss = 0.0;
+  if (j < k)
+    for (int i = ph; i < F; i += 4) {
+      const int node = grid_node(g, cx, cy, cz, i % np, (i / np) % np, i / (np * np));
+      if (node >= 0) {
+        const double x = R[(int64_t)node * ldr + j];
+        ss = fma(x, x, ss);
+      }
+    }
+  part[t] = ss;
+  __syncthreads();
+  double tot = part[jj] + part[jj + 64] + part[jj + 128] + part[jj + 192];
+  const double r = sqrt(tot / F);
+  const double s = r > 0.0 ? 1.0 / r : 0.0;
+  const int64_t row = (int64_t)e * k + j;
+  if (j >= k) return;
+  if (ph == 0) rho[row] = (float)r;
+  for (int i = ph; i < Fp; i += 4) {
+    double x = 0.0, y = 0.0;
+    if (i < F) {
+      const int node = grid_node(g, cx, cy, cz, i % np, (i / np) % np, i / (np * np));
+      if (node >= 0) {
+        x = R[(int64_t)node * ldr + j] * s;
+        if (E) y = E[(int64_t)node * lde + j] * s;
+      }
+    }
+    X0t[(int64_t)i * ldx + row] = f32_to_bf16((float)x);
+    if (Tt) Tt[(int64_t)i * ldx + row] = (float)y;
+  }
+}
+
+// Z[node][j] += w(node) rho[row] Yt[i][row] over the cell's free nodes
+// (partition-of-unity average of the cell-local predictions).
+__global__ void __launch_bounds__(256)
+cell_scatter_kernel(GridDesc g, int np, int k, const float* __restrict__ Yt, int64_t ldy,
+                    const float* __restrict__ rho, double* __restrict__ Z, int64_t ldz) {
+  const int e = blockIdx.x;
+  const int j0 = blockIdx.y * kCols;
+  const int t = threadIdx.x, jj = t % kCols, ph = t / kCols;
+  const int j = j0 + jj;
+  if (j >= k) return;
+  const int F = np * np * np;
+  const int cx = e % g.n[0], cy = (e / g.n[0]) % g.n[1], cz = e / (g.n[0] * g.n[1]);
+  const int64_t row = (int64_t)e * k + j;
+  const double r = rho[row];
+  for (int i = ph; i < F; i += 4) {
+    const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
+    const int node = grid_node(g, cx, cy, cz, i1, i2, i3);
+    if (node < 0) continue;
+    const double w = pou_weight(g, i1, i2, i3, cx, cy, cz);
+    unsafeAtomicAdd(Z + (int64_t)node * ldz + j, w * r * (double)Yt[(int64_t)i * ldy + row]);
+  }
+}
+
+// dYt = 2 (Yt - Tt) / nrows for features < F (0 for the padding), as BF16;
+// loss += sum (Yt - Tt)^2 / nrows.
+__global__ void __launch_bounds__(256)
+mse_grad_kernel(int F, int Fp, int64_t nrows, const float* __restrict__ Yt,
+                const float* __restrict__ Tt, int64_t ld, uint16_t* __restrict__ dYt,
+                double* __restrict__ loss) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  const int64_t total = (int64_t)Fp * nrows;
+  const float sc = 2.0f / (float)nrows;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / nrows);
+    const int64_t n = idx % nrows;
+    float d = 0.f;
+    if (i < F) {
+      d = Yt[(int64_t)i * ld + n] - Tt[(int64_t)i * ld + n];
+      acc += (double)d * d;
+    }
+    dYt[(int64_t)i * ld + n] = f32_to_bf16(sc * d);
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) unsafeAtomicAdd(loss, part[0] / (double)nrows);
+}
+
+// out[m] (+)= sum_n X[m][n] (BF16 rows): bias gradients.
+__global__ void __launch_bounds__(256)
+row_sums_kernel(int64_t N, const uint16_t* __restrict__ X, int64_t ld, float* __restrict__ out,
+                int accumulate) {
+  __shared__ float part[256];
+  const int m = blockIdx.x;
+  float acc = 0.f;
+  for (int64_t n = threadIdx.x; n < N; n += blockDim.x) acc += bf16_to_f32(X[(int64_t)m * ld + n]);
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[m] = (accumulate ? out[m] : 0.f) + part[0];
+}
+
+// Adam on FP32 master parameters; writes the BF16 copy when given.
+__global__ void adam_kernel(int64_t n, float* __restrict__ w, const float* __restrict__ grad,
+                            float* __restrict__ m1, float* __restrict__ m2,
+                            uint16_t* __restrict__ wbf, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = grad[i];
+    const float a = b1 * m1[i] + (1.f - b1) * gi;
+    const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+    m1[i] = a;
+    m2[i] = b;
+    const float wi = w[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
+    w[i] = wi;
+    if (wbf) wbf[i] = f32_to_bf16(wi);
+  }
+}
+
+__global__ void to_bf16_kernel(int64_t n, const float* __restrict__ src, uint16_t* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = f32_to_bf16(src[i]);
+}
+
+__global__ void fill_f32_kernel(float* __restrict__ v, int64_t n, float x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = x;
+}
+
+// Z := R / diag row-wise, or 0 when diag is null (start of the assembly).
+__global__ void init_z_kernel(double* __restrict__ Z, int64_t rows, int cols, int64_t ldz,
+                              const double* __restrict__ diag, const double* __restrict__ R,
+                              int64_t ldr) {
+  const int64_t total = rows * cols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols;
+    const int c = (int)(i % cols);
+    Z[r * ldz + c] = diag ? R[r * ldr + c] / diag[r] : 0.0;
+  }
+}
+
+unsigned blocks_for(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  if (b > 65536) b = 65536;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+hipError_t launch_gemm_bf16(int M, int N, int K, bool ta, bool tb, const uint16_t* A, int64_t lda,
+                            const uint16_t* B, int64_t ldb, int kchunk, const GemmEpi& ep,
+                            hipStream_t s) {
+  if (kchunk <= 0 || kchunk > K) kchunk = K;
+  kchunk = (kchunk + kKStep - 1) / kKStep * kKStep;
+  const int kz = (K + kchunk - 1) / kchunk;
+  dim3 grid((N + kTile - 1) / kTile, (M + kTile - 1) / kTile, kz);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, kchunk, ep);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, kchunk, ep);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, kchunk, ep);
+  else
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, kchunk, ep);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_gather(const Operator& op, int k, const double* R, int64_t ldr,
+                              const double* E, int64_t lde, int Fp, uint16_t* X0t, float* Tt,
+                              int64_t ldx, float* rho, hipStream_t s) {
+  dim3 grid((unsigned)op.ncells, (k + kCols - 1) / kCols);
+  hipLaunchKernelGGL(cell_gather_kernel, grid, dim3(256), 0, s, op.grid, op.np, k, R, ldr, E, lde,
+                     Fp, X0t, Tt, ldx, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_scatter(const Operator& op, int k, const float* Yt, int64_t ldy,
+                               const float* rho, const double* diag, const double* R, int64_t ldr,
+                               double* Z, int64_t ldz, hipStream_t s) {
+  hipLaunchKernelGGL(init_z_kernel, dim3(blocks_for(op.ndofs * k)), dim3(256), 0, s, Z, op.ndofs,
+                     k, ldz, diag, R, ldr);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  dim3 grid((unsigned)op.ncells, (k + kCols - 1) / kCols);
+  hipLaunchKernelGGL(cell_scatter_kernel, grid, dim3(256), 0, s, op.grid, op.np, k, Yt, ldy, rho,
+                     Z, ldz);
+  return hipGetLastError();
+}
+
+hipError_t launch_mse_grad(int F, int Fp, int64_t nrows, const float* Yt, const float* Tt,
+                           int64_t ld, uint16_t* dYt, double* loss, hipStream_t s) {
+  unsigned blocks = blocks_for((int64_t)Fp * nrows);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(mse_grad_kernel, dim3(blocks), dim3(256), 0, s, F, Fp, nrows, Yt, Tt, ld, dYt,
+                     loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_sums(int M, int64_t N, const uint16_t* X, int64_t ld, float* out,
+                           bool accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(row_sums_kernel, dim3(M), dim3(256), 0, s, N, X, ld, out, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(int64_t n, float* w, const float* g, float* m1, float* m2, uint16_t* wbf,
+                       float lr, float b1, float b2, float eps, int step, hipStream_t s) {
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, w, g, m1, m2, wbf, lr,
+                     b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(int64_t n, const float* src, uint16_t* dst, hipStream_t s) {
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* v, int64_t n, float x, hipStream_t s) {
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks_for(n)), dim3(256), 0, s, v, n, x);
+  return hipGetLastError();
+}
+
+}  // namespace mf

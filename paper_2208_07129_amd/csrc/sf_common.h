@@ -26,6 +26,19 @@ __device__ inline int64_t xcd_item(int64_t wg, int64_t chunk) {
   return (wg % kXcds) * chunk + wg / kXcds;
 }
 
+// Grid node of local node (i1, i2, i3) of cell (cx, cy, cz) on a structured
+// box mesh (periodic wrap; -1 for a zero-Dirichlet boundary node).
+__device__ inline int grid_node(const GridDesc& g, int cx, int cy, int cz, int i1, int i2, int i3) {
+  int gx = cx * g.p + i1, gy = cy * g.p + i2, gz = cz * g.p + i3;
+  if (gx == g.N[0]) gx = 0;
+  if (gy == g.N[1]) gy = 0;
+  if (gz == g.N[2]) gz = 0;
+  if (g.dirichlet && (gx == 0 || gx == g.N[0] - 1 || gy == 0 || gy == g.N[1] - 1 || gz == 0 ||
+                      gz == g.N[2] - 1))
+    return -1;
+  return gx + g.N[0] * (gy + g.N[1] * gz);
+}
+
 // Compile-time coefficient sources: M::at<K> is the K-th entry of a 1D matrix
 // as a constant expression, so contractions are emitted with literal
 // coefficients (uniform operands, nothing loaded or held in registers).

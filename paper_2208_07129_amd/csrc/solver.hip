@@ -1,0 +1,253 @@
+// Kernels of the block-CG building blocks: the operator diagonal (Jacobi),
+// column dot products, Y := aX + bY, the Jacobi scaling and the small SPD
+// solve of the k x k block step.  The Gram blocks and block updates are plain GEMMs and
+// go to rocBLAS (capi_solver.cpp).
+#include <cmath>
+
+#include "mf_internal.h"
+#include "sf_common.h"
+
+namespace mf {
+namespace {
+
+// One workgroup per cell.  `tab` = [wN2 (nq x np) | a (np) | b (np) | c (np)]
+// with wN2(q, i) = w_q N(q, i)^2, a(i) = sum_q w_q D(q, i)^2,
+// b(i) = sum_q w_q N(q, i)^2, c(i) = sum_q w_q D(q, i) N(q, i).  For the
+// affine cell the element-matrix diagonal is
+//   sum_{s,t} G_st prod_d T_{st,d}(i_d) + sum_Q det J (V + sigma)_Q prod_d wN2(q_d, i_d)
+// with T = a in the direction s = t, c in the directions s != t, b elsewhere.
+__global__ void diag_kernel(GridDesc g, const double* __restrict__ geo,
+                            const double* __restrict__ vq, const double* __restrict__ tab, int np,
+                            int nq, double* __restrict__ diag) {
+  extern __shared__ double sh[];
+  const int nq3 = nq * nq * nq, np3 = np * np * np;
+  const int tabn = nq * np + 3 * np;
+  const int64_t e = blockIdx.x;
+  double* svq = sh;
+  double* st = sh + nq3;
+  for (int i = threadIdx.x; i < nq3; i += blockDim.x) svq[i] = vq[e * nq3 + i];
+  for (int i = threadIdx.x; i < tabn; i += blockDim.x) st[i] = tab[i];
+  __syncthreads();
+  const double* wN2 = st;
+  const double* ta = st + nq * np;
+  const double* tb = ta + np;
+  const double* tc = tb + np;
+  const double* G = geo + e * 6;  // (00, 01, 02, 11, 12, 22)
+  const int ce = (int)e;
+  const int cx = ce % g.n[0], cy = (ce / g.n[0]) % g.n[1], cz = ce / (g.n[0] * g.n[1]);
+  for (int i = threadIdx.x; i < np3; i += blockDim.x) {
+    const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
+    const int node = grid_node(g, cx, cy, cz, i1, i2, i3);
+    if (node < 0) continue;
+    const double a1 = ta[i1], a2 = ta[i2], a3 = ta[i3];
+    const double b1 = tb[i1], b2 = tb[i2], b3 = tb[i3];
+    const double c1 = tc[i1], c2 = tc[i2], c3 = tc[i3];
+    double d = G[0] * a1 * b2 * b3 + G[3] * b1 * a2 * b3 + G[5] * b1 * b2 * a3 +
+               2.0 * (G[1] * c1 * c2 * b3 + G[2] * c1 * b2 * c3 + G[4] * b1 * c2 * c3);
+    double m = 0.0;
+    for (int q3 = 0; q3 < nq; ++q3) {
+      double m2 = 0.0;
+      for (int q2 = 0; q2 < nq; ++q2) {
+        double m1 = 0.0;
+        const double* v = svq + nq * (q2 + nq * q3);
+        for (int q1 = 0; q1 < nq; ++q1) m1 = fma(v[q1], wN2[q1 * np + i1], m1);
+        m2 = fma(m1, wN2[q2 * np + i2], m2);
+      }
+      m = fma(m2, wN2[q3 * np + i3], m);
+    }
+    unsafeAtomicAdd(diag + node, d + m);
+  }
+}
+
+// Constrained (zero-Dirichlet boundary) rows of the diagonal := 1.
+__global__ void diag_constrained_kernel(GridDesc g, double* __restrict__ diag) {
+  const int64_t total = (int64_t)g.N[0] * g.N[1] * g.N[2];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int gx = (int)(i % g.N[0]), gy = (int)((i / g.N[0]) % g.N[1]),
+              gz = (int)(i / ((int64_t)g.N[0] * g.N[1]));
+    if (gx == 0 || gx == g.N[0] - 1 || gy == 0 || gy == g.N[1] - 1 || gz == 0 || gz == g.N[2] - 1)
+      diag[i] = 1.0;
+  }
+}
+
+__global__ void fill_kernel(double* __restrict__ v, int64_t n, double x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = x;
+}
+
+// Column dot products out[j] = sum_i A[i, j] B[i, j]: rows in chunks of
+// kDotRows per workgroup; RPB = max(1, 256 / k) rows in flight per pass,
+// lanes over columns (coalesced), partial sums combined in LDS, one FP64
+// atomic per column per workgroup.
+constexpr int kDotRows = 2048;
+__global__ void __launch_bounds__(256)
+col_dots_kernel(int64_t n, int k, const double* __restrict__ A, int64_t lda,
+                const double* __restrict__ B, int64_t ldb, double* __restrict__ out) {
+  __shared__ double part[256];
+  const int t = threadIdx.x;
+  const int rpb = k < 256 ? 256 / k : 1;
+  const int64_t r0 = (int64_t)blockIdx.x * kDotRows;
+  const int64_t r1 = r0 + kDotRows < n ? r0 + kDotRows : n;
+  for (int j0 = 0; j0 < k; j0 += 256) {
+    const int j = j0 + (rpb > 1 ? t % k : t);
+    const int rr = rpb > 1 ? t / k : 0;
+    double acc = 0.0;
+    if (j < k && rr < rpb)
+      for (int64_t r = r0 + rr; r < r1; r += rpb) acc = fma(A[r * lda + j], B[r * ldb + j], acc);
+    part[t] = acc;
+    __syncthreads();
+    if (rpb > 1) {
+      if (t < k) {
+        double s = 0.0;
+        for (int m = 0; m < rpb; ++m) s += part[t + m * k];
+        unsafeAtomicAdd(out + t, s);
+      }
+    } else if (j < k) {
+      unsafeAtomicAdd(out + j, acc);
+    }
+    __syncthreads();
+  }
+}
+
+// Y := a X + b Y (b = 0: Y is not read).
+__global__ void axpby_kernel(int64_t n, int k, double a, const double* X, int64_t ldx, double b,
+                             double* Y, int64_t ldy) {
+  const int64_t total = n * k;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / k;
+    const int j = (int)(i % k);
+    const double x = a * X[r * ldx + j];
+    Y[r * ldy + j] = b == 0.0 ? x : fma(b, Y[r * ldy + j], x);
+  }
+}
+
+__global__ void jacobi_kernel(int64_t n, int k, const double* __restrict__ diag,
+                              const double* R, int64_t ldr, double* Z, int64_t ldz) {
+  const int64_t total = n * k;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / k;
+    const int j = (int)(i % k);
+    Z[r * ldz + j] = R[r * ldr + j] / diag[r];
+  }
+}
+
+// X := G^{-1} S (G k x k SPD, S k x m), one workgroup.  The lower Cholesky
+// factor is formed in LDS (right-looking, one column per step); each thread
+// then owns right-hand-side columns and runs the forward and backward
+// substitutions, keeping its column of X in global memory (L1/L2 resident).
+constexpr int kSpdMaxK = 128, kSpdThreads = 256;
+__global__ void __launch_bounds__(kSpdThreads)
+spd_solve_kernel(int k, int m, const double* __restrict__ G, const double* __restrict__ S,
+                 double* __restrict__ X, int* __restrict__ status) {
+  extern __shared__ double L[];  // k x k, row-major
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  for (int i = t; i < k * k; i += kSpdThreads) L[i] = G[i];
+  if (t == 0) bad = 0;
+  __syncthreads();
+  for (int c = 0; c < k; ++c) {
+    if (t == 0) {
+      const double d = L[c * k + c];
+      if (!(d > 0.0) || !isfinite(d)) bad = c + 1;
+      else L[c * k + c] = sqrt(d);
+    }
+    __syncthreads();
+    if (bad) break;
+    const double dc = L[c * k + c];
+    for (int r = c + 1 + t; r < k; r += kSpdThreads) L[r * k + c] /= dc;
+    __syncthreads();
+    // trailing lower triangle: rows r > c, columns c < s <= r
+    const int rem = k - c - 1;
+    for (int w = t; w < rem * rem; w += kSpdThreads) {
+      const int r = c + 1 + w / rem, s = c + 1 + w % rem;
+      if (s <= r) L[r * k + s] -= L[r * k + c] * L[s * k + c];
+    }
+    __syncthreads();
+  }
+  if (t == 0) *status = bad;
+  if (bad) return;
+  for (int j = t; j < m; j += kSpdThreads) {
+    // L y = s
+    for (int r = 0; r < k; ++r) {
+      double acc = S[r * m + j];
+      for (int c = 0; c < r; ++c) acc -= L[r * k + c] * X[c * m + j];
+      X[r * m + j] = acc / L[r * k + r];
+    }
+    // L^T x = y
+    for (int r = k - 1; r >= 0; --r) {
+      double acc = X[r * m + j];
+      for (int c = r + 1; c < k; ++c) acc -= L[c * k + r] * X[c * m + j];
+      X[r * m + j] = acc / L[r * k + r];
+    }
+  }
+}
+
+unsigned grid_for(int64_t total, int threads) {
+  int64_t b = (total + threads - 1) / threads;
+  if (b > 65536) b = 65536;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+hipError_t launch_diagonal(const Operator& op, const double* d_tab, double* diag, hipStream_t s) {
+  const int64_t nd = op.ndofs;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(nd, 256)), dim3(256), 0, s, diag, nd, 0.0);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const size_t lds = ((size_t)op.nq * op.nq * op.nq + (size_t)op.nq * op.np + 3 * op.np) * sizeof(double);
+  hipLaunchKernelGGL(diag_kernel, dim3((unsigned)op.ncells), dim3(256), lds, s, op.grid, op.d_geo,
+                     op.d_vq, d_tab, op.np, op.nq, diag);
+  err = hipGetLastError();
+  if (err != hipSuccess || !op.grid.dirichlet) return err;
+  hipLaunchKernelGGL(diag_constrained_kernel, dim3(grid_for(nd, 256)), dim3(256), 0, s, op.grid,
+                     diag);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_dots(int64_t n, int k, const double* A, int64_t lda, const double* B,
+                           int64_t ldb, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(256), 0, s, out, (int64_t)k, 0.0);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || n == 0) return err;
+  const int64_t blocks = (n + kDotRows - 1) / kDotRows;
+  hipLaunchKernelGGL(col_dots_kernel, dim3((unsigned)blocks), dim3(256), 0, s, n, k, A, lda, B, ldb,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(int64_t n, int k, double a, const double* X, int64_t ldx, double b,
+                        double* Y, int64_t ldy, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n * k, 256)), dim3(256), 0, s, n, k, a, X, ldx, b,
+                     Y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi(int64_t n, int k, const double* diag, const double* R, int64_t ldr,
+                         double* Z, int64_t ldz, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_kernel, dim3(grid_for(n * k, 256)), dim3(256), 0, s, n, k, diag, R,
+                     ldr, Z, ldz);
+  return hipGetLastError();
+}
+
+int spd_max_k() { return kSpdMaxK; }
+
+hipError_t launch_spd_solve(int k, int m, const double* G, const double* S, double* X, int* status,
+                            hipStream_t s) {
+  const size_t lds = (size_t)k * k * sizeof(double);
+  if (lds > 64 * 1024) {
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(spd_solve_kernel),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+  }
+  hipLaunchKernelGGL(spd_solve_kernel, dim3(1), dim3(kSpdThreads), lds, s, k, m, G, S, X, status);
+  return hipGetLastError();
+}
+
+}  // namespace mf

@@ -28,7 +28,13 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_apply_add", "mf_zero", "mf_set_launch", "mf_set_launch_mixed", "mf_timing",
            "mf_timing_read", "mf_batch_create", "mf_batch_destroy", "mf_batch_set_launch",
            "mf_batch_apply", "mf_batch_capture", "mf_batch_replay", "mf_batch_info",
-           "mf_last_error")
+           "mf_last_error",
+           # include/mfsolve.h
+           "mf_diagonal", "mf_block_gram", "mf_block_update", "mf_col_dots", "mf_axpby",
+           "mf_jacobi", "mf_spd_solve",
+           # include/mfmlp.h
+           "mf_mlp_gemm", "mf_cell_gather", "mf_cell_scatter", "mf_mse_grad", "mf_row_sums",
+           "mf_adam", "mf_to_bf16", "mf_fill_f32")
 
 
 class MfError(RuntimeError):
@@ -52,6 +58,7 @@ def lib() -> ctypes.CDLL:
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2208_07129_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        F32 = ctypes.c_float
         MP = ctypes.POINTER(MeshC)
         sig = {
             "mf_num_dofs": (I, [MP, I, ctypes.POINTER(I64)]),
@@ -78,6 +85,22 @@ def lib() -> ctypes.CDLL:
             "mf_batch_capture": (I, [P, P, P, P, P, P]),
             "mf_batch_replay": (I, [P, P]),
             "mf_batch_info": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(I), ctypes.POINTER(I)]),
+            "mf_diagonal": (I, [P, P, P]),
+            "mf_block_gram": (I, [I64, I, P, I64, P, I64, D, D, P, I, P]),
+            "mf_block_update": (I, [I64, I, I, D, P, I64, P, I, D, P, I64, P]),
+            "mf_col_dots": (I, [I64, I, P, I64, P, I64, P, P]),
+            "mf_axpby": (I, [I64, I, D, P, I64, D, P, I64, P]),
+            "mf_jacobi": (I, [I64, I, P, P, I64, P, I64, P]),
+            "mf_spd_solve": (I, [I, I, P, P, P, P, P]),
+            "mf_mlp_gemm": (I, [I, I, I, I, I, P, I64, P, I64, I, P, I, P, I64, P, I64, I, P, I64,
+                                P]),
+            "mf_cell_gather": (I, [P, I, P, I64, P, I64, I, P, P, I64, P, P]),
+            "mf_cell_scatter": (I, [P, I, P, I64, P, P, P, I64, P, I64, P]),
+            "mf_mse_grad": (I, [I, I, I64, P, P, I64, P, P, P]),
+            "mf_row_sums": (I, [I, I64, P, I64, P, I, P]),
+            "mf_adam": (I, [I64, P, P, P, P, P, F32, F32, F32, F32, I, P]),
+            "mf_to_bf16": (I, [I64, P, P, P]),
+            "mf_fill_f32": (I, [I64, P, F32, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -228,6 +251,112 @@ class Operator:
 
 def zero_ptr(Y_ptr: int, nrows: int, ncols: int, ld: int, stream=None):
     _check(lib().mf_zero(Y_ptr, nrows, ncols, ld, _stream_ptr(stream)))
+
+
+# ------------------------------------------------------------ include/mfsolve.h
+def _mv(V, name):
+    """(pointer, rows, cols, ld) of a float64 device matrix with unit column stride."""
+    import torch
+    if V.dtype != torch.float64 or not V.is_cuda or V.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D float64 device tensor")
+    n, k = V.shape
+    if n > 0 and k > 1 and V.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+    ld = V.stride(0) if n > 1 else k
+    return V.data_ptr(), n, k, max(ld, k)
+
+
+def diagonal(op: Operator, out=None, stream=None):
+    """Operator diagonal (constrained rows 1) as a float64 device vector."""
+    import torch
+    if out is None:
+        out = torch.empty(op.ndofs, dtype=torch.float64, device="cuda")
+    _check(lib().mf_diagonal(op._h, out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def block_gram(A, B, C=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
+    """C := alpha A^T B + beta C (k x k)."""
+    import torch
+    pa, n, k, lda = _mv(A, "A")
+    pb, nb, kb, ldb = _mv(B, "B")
+    if (nb, kb) != (n, k):
+        raise ValueError("A and B must have the same shape")
+    if C is None:
+        C = torch.empty(k, k, dtype=torch.float64, device=A.device)
+    pc, kc, kc2, ldc = _mv(C, "C")
+    if (kc, kc2) != (k, k):
+        raise ValueError("C must be k x k")
+    _check(lib().mf_block_gram(n, k, pa, lda, pb, ldb, float(alpha), float(beta), pc, ldc,
+                               _stream_ptr(stream)))
+    return C
+
+
+def block_update(P, M, Y, alpha: float = 1.0, beta: float = 1.0, stream=None):
+    """Y := beta Y + alpha P M."""
+    pp, n, kp, ldp = _mv(P, "P")
+    pm, km, k, ldm = _mv(M, "M")
+    py, ny, ky, ldy = _mv(Y, "Y")
+    if km != kp or ny != n or ky != k:
+        raise ValueError("shape mismatch in block_update")
+    _check(lib().mf_block_update(n, k, kp, float(alpha), pp, ldp, pm, ldm, float(beta), py, ldy,
+                                 _stream_ptr(stream)))
+    return Y
+
+
+def col_dots(A, B, out=None, stream=None):
+    """out[j] = sum_i A[i, j] B[i, j]."""
+    import torch
+    pa, n, k, lda = _mv(A, "A")
+    pb, nb, kb, ldb = _mv(B, "B")
+    if (nb, kb) != (n, k):
+        raise ValueError("A and B must have the same shape")
+    if out is None:
+        out = torch.empty(k, dtype=torch.float64, device=A.device)
+    _check(lib().mf_col_dots(n, k, pa, lda, pb, ldb, out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def col_norms2(V, out=None, stream=None):
+    return col_dots(V, V, out, stream)
+
+
+def axpby(a: float, X, b: float, Y, stream=None):
+    """Y := a X + b Y (b = 0: Y only written)."""
+    px, n, k, ldx = _mv(X, "X")
+    py, ny, ky, ldy = _mv(Y, "Y")
+    if (ny, ky) != (n, k):
+        raise ValueError("X and Y must have the same shape")
+    _check(lib().mf_axpby(n, k, float(a), px, ldx, float(b), py, ldy, _stream_ptr(stream)))
+    return Y
+
+
+def jacobi(diag, R, Z=None, stream=None):
+    """Z := R / diag row-wise."""
+    import torch
+    pr, n, k, ldr = _mv(R, "R")
+    if Z is None:
+        Z = torch.empty_like(R)
+    pz, nz, kz, ldz = _mv(Z, "Z")
+    if (nz, kz) != (n, k) or diag.numel() != n:
+        raise ValueError("shape mismatch in jacobi")
+    _check(lib().mf_jacobi(n, k, diag.data_ptr(), pr, ldr, pz, ldz, _stream_ptr(stream)))
+    return Z
+
+
+def spd_solve(G, S, X=None, status=None, stream=None):
+    """X := G^{-1} S (Cholesky); returns (X, status) with status a device int32 (0 = ok)."""
+    import torch
+    pg, k, k2, ldg = _mv(G, "G")
+    ps, ks, m, lds = _mv(S, "S")
+    if k2 != k or ks != k or ldg != k or lds != m:
+        raise ValueError("G must be k x k and S k x m, both contiguous")
+    if X is None:
+        X = torch.empty_like(S)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=G.device)
+    _check(lib().mf_spd_solve(k, m, pg, ps, X.data_ptr(), status.data_ptr(), _stream_ptr(stream)))
+    return X, status
 
 
 class Batch:

@@ -1,0 +1,185 @@
+"""GPU tests of the learned-preconditioner kernels (include/mfmlp.h) against
+the numpy FP64 oracle (oracle/mlp_oracle.py):
+
+- the BF16 matrix-core GEMM in its three operand forms with every epilogue and
+  the split batch dimension, against FP64 products of the same BF16 values
+  (FP32 accumulation: 1e-5 relative);
+- the cell gather (network inputs, targets, scales) and the partition-of-unity
+  assembly (with and without the Jacobi term);
+- loss and gradients of the whole network against the oracle's backward pass
+  on the same BF16-rounded weights and inputs (BF16 activations: 2e-2);
+- Adam against the oracle's FP32 update;
+- training reduces the loss, and the trained step is judged against Jacobi.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp_oracle as mo
+from oracle.fe_oracle import constrained_mask
+from paper_2208_07129_amd import blockcg, mfmv, mlp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    assert torch.cuda.is_available(), "GPU test needs a HIP device"
+    return torch.device("cuda:0")
+
+
+def bf(a):
+    """(device BF16 bits, FP64 values of the rounded numbers)"""
+    bits = mlp._host_bf16(a)
+    return torch.from_numpy(bits).to(dev()), mo.bf16_round(a)
+
+
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True)])
+@pytest.mark.parametrize("M,N,K", [(8, 8, 8), (72, 136, 40), (256, 344, 352), (344, 200, 256)])
+def test_gemm_forms(ta, tb, M, N, K):
+    rng = np.random.default_rng(M * 7 + N + K)
+    A = rng.standard_normal((K, M) if ta else (M, K)).astype(np.float32)
+    B = rng.standard_normal((N, K) if tb else (K, N)).astype(np.float32)
+    Ad, Ar = bf(A)
+    Bd, Br = bf(B)
+    ref = (Ar.T if ta else Ar) @ (Br.T if tb else Br)
+    out = torch.full((M, N), float("nan"), dtype=torch.float32, device=dev())
+    mlp.CellMLP._gemm(M, N, K, ta, tb, Ad, A.shape[1], Bd, B.shape[1], out_f32=out, ld_f32=N)
+    scale = np.abs(Ar).max() * np.abs(Br).max() * K
+    np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=0, atol=1e-6 * scale)
+
+
+def test_gemm_epilogues_and_split():
+    rng = np.random.default_rng(5)
+    M, N, K = 64, 128, 96
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    B = rng.standard_normal((K, N)).astype(np.float32)
+    bias = rng.standard_normal(M).astype(np.float32)
+    mask = rng.standard_normal((M, N)).astype(np.float32)
+    Ad, Ar = bf(A)
+    Bd, Br = bf(B)
+    md, mr = bf(mask)
+    ref = Ar @ Br
+    tol = 1e-6 * np.abs(Ar).max() * np.abs(Br).max() * K
+    f32 = torch.empty(M, N, dtype=torch.float32, device=dev())
+    b16 = torch.empty(M, N, dtype=torch.int16, device=dev())
+    bt = torch.from_numpy(bias).to(dev())
+    mlp.CellMLP._gemm(M, N, K, False, False, Ad, K, Bd, N, bias=bt, relu=True, out_f32=f32,
+                      ld_f32=N, out_bf16=b16, ld_bf16=N)
+    want = np.maximum(ref + bias[:, None], 0)
+    np.testing.assert_allclose(f32.cpu().numpy(), want, rtol=0, atol=tol)
+    got16 = mo.bf16_round(f32.cpu().numpy())
+    np.testing.assert_array_equal(mlp._host_bf16(f32.cpu().numpy()), b16.cpu().numpy())
+    assert np.all(np.abs(got16 - want) <= np.abs(want) * 2 ** -8 + tol)
+    mlp.CellMLP._gemm(M, N, K, False, False, Ad, K, Bd, N, mask=md, ldmask=N, out_f32=f32, ld_f32=N)
+    np.testing.assert_allclose(f32.cpu().numpy(), ref * (mr > 0), rtol=0, atol=tol)
+    f32.zero_()
+    mlp.CellMLP._gemm(M, N, K, False, False, Ad, K, Bd, N, kchunk=32, out_f32=f32, ld_f32=N,
+                      atomic=True)
+    np.testing.assert_allclose(f32.cpu().numpy(), ref, rtol=0, atol=tol)
+    with pytest.raises(mfmv.MfError):
+        mlp.CellMLP._gemm(M, N, K, False, False, Ad, K, Bd, N, kchunk=32, bias=bt, out_f32=f32,
+                          ld_f32=N, atomic=True)
+
+
+def small_op(bc, p=3, n=(2, 3, 2), sigma=1.0):
+    mesh = W.BoxMesh(n=n, lo=(0.0, 0.0, 0.0), hi=(2.0, 2.0, 2.0), bc=bc)
+    V = W.gaussian_wells(11, L=2.0, k=3, width=0.5, depth=(-2.0, -0.5))
+    op = mfmv.Operator(mesh, p, p + 1, 0.5, V(mfmv.quad_points(mesh, p + 1)), sigma)
+    return mesh, op
+
+
+@pytest.mark.parametrize("bc", [W.BC_NONE, W.BC_DIRICHLET0, W.BC_PERIODIC])
+def test_cell_gather_and_scatter_match_oracle(bc):
+    mesh, op = small_op(bc)
+    p, k = op.p, 9
+    cons = constrained_mask(mesh, p)
+    rng = np.random.default_rng(3)
+    R = rng.uniform(-1, 1, (op.ndofs, k))
+    E = rng.uniform(-1, 1, (op.ndofs, k))
+    R[cons] = 0.0
+    net = mlp.CellMLP(op, hidden=16, seed=1)
+    b = net.gather(torch.from_numpy(R).to(dev()), torch.from_numpy(E).to(dev()))
+    X, T, rho = mo.cell_inputs(mesh, p, R, E)
+    F = net.F
+    x0 = b["X0"].cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    X0 = x0.view(np.float32).astype(np.float64)
+    rows = op.ncells * k
+    np.testing.assert_allclose(b["rho"].cpu().numpy()[:rows], rho, rtol=1e-6)
+    assert np.all(np.abs(X0[:F, :rows].T - X) <= np.abs(X) * 2 ** -8 + 1e-30)
+    assert np.all(X0[F:] == 0.0) and np.all(X0[:, rows:] == 0.0)
+    np.testing.assert_allclose(b["T"].cpu().numpy()[:F, :rows].T, T, rtol=1e-6,
+                               atol=1e-6 * np.abs(T).max())
+    # assembly of arbitrary outputs, with and without the Jacobi term
+    Y = rng.standard_normal((net.Fp, b["ld"])).astype(np.float32)
+    b["Y"].copy_(torch.from_numpy(Y))
+    diag = rng.uniform(1.0, 2.0, op.ndofs)
+    Rd, dd = torch.from_numpy(R).to(dev()), torch.from_numpy(diag).to(dev())
+    Z = torch.empty_like(Rd)
+    for with_j in (False, True):
+        mfmv._check(mfmv.lib().mf_cell_scatter(
+            op._h, k, b["Y"].data_ptr(), b["ld"], b["rho"].data_ptr(),
+            dd.data_ptr() if with_j else None, Rd.data_ptr() if with_j else None, k,
+            Z.data_ptr(), k, None))
+        rows = op.ncells * k
+        ref = mo.cell_assemble(mesh, p, Y[:F, :rows].T.astype(np.float64),
+                               b["rho"].cpu().numpy()[:rows].astype(np.float64), k,
+                               R if with_j else None, diag if with_j else None)
+        np.testing.assert_allclose(Z.cpu().numpy(), ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+
+
+def test_forward_backward_match_oracle():
+    mesh, op = small_op(W.BC_PERIODIC, p=2, n=(2, 2, 2))
+    k = 8
+    net = mlp.CellMLP(op, hidden=32, seed=4, out_scale=1.0)
+    rng = np.random.default_rng(9)
+    R = torch.from_numpy(rng.uniform(-1, 1, (op.ndofs, k))).to(dev())
+    E = torch.from_numpy(rng.uniform(-1, 1, (op.ndofs, k))).to(dev())
+    b = net.gather(R, E)
+    net.forward(b)
+    net._loss.zero_()
+    net.loss_grad(b)
+    net.backward(b, kchunk=32)
+    F, Fp = net.F, net.Fp
+    rows = op.ncells * k
+    x0 = (b["X0"].cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    X = x0.astype(np.float64)[:F, :rows].T
+    T = b["T"].cpu().numpy().astype(np.float64)[:F, :rows].T
+    W1, b1, W2, b2, W3, b3 = [p.cpu().numpy().astype(np.float64) for p in net.params]
+    params = [mo.bf16_round(W1[:, :F]), b1, mo.bf16_round(W2), b2, mo.bf16_round(W3[:F]), b3[:F]]
+    loss, grads = mo.loss_and_grads(params, X, T)
+    assert abs(net._loss.item() - loss) <= 2e-2 * loss
+    gW1, gb1, gW2, gb2, gW3, gb3 = [g.cpu().numpy().astype(np.float64) for g in net.grads]
+    got = [gW1[:, :F], gb1, gW2, gb2, gW3[:F], gb3[:F]]
+    for name, g, r in zip(["W1", "b1", "W2", "b2", "W3", "b3"], got, grads):
+        rel = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
+        assert rel <= 2e-2, (name, rel)
+    assert np.all(gW1[:, F:] == 0) and np.all(gW3[F:] == 0) and np.all(gb3[F:] == 0)
+
+
+def test_adam_matches_oracle():
+    mesh, op = small_op(W.BC_PERIODIC, p=2, n=(1, 1, 2))
+    net = mlp.CellMLP(op, hidden=16, seed=2, out_scale=1.0)
+    rng = np.random.default_rng(1)
+    w0 = [p.cpu().numpy().copy() for p in net.params]
+    g = [rng.standard_normal(p.shape).astype(np.float32) for p in net.params]
+    for gd, gh in zip(net.grads, g):
+        gd.copy_(torch.from_numpy(gh))
+    net.adam(1e-2)
+    for i, (w, gh) in enumerate(zip(w0, g)):
+        ref, _, _ = mo.adam_step(w, gh, np.zeros_like(w), np.zeros_like(w), 1e-2, 0.9, 0.999, 1e-8, 1)
+        np.testing.assert_allclose(net.params[i].cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
+    for i in (0, 2, 4):
+        np.testing.assert_array_equal(net.wbf[i].cpu().numpy(),
+                                      mlp._host_bf16(net.params[i].cpu().numpy()))
+
+
+def test_training_reduces_loss_and_is_judged():
+    mesh, op = small_op(W.BC_PERIODIC, p=3, n=(3, 3, 3))
+    diag = mfmv.diagonal(op)
+    net = mlp.CellMLP(op, hidden=64, seed=0)
+    losses = mlp.train(net, diag, steps=120, k=16, lr=2e-3, refresh=10)
+    first, last = np.mean(losses[:10]), np.mean(losses[-10:])
+    assert np.isfinite(last) and last < 0.7 * first, (first, last)
+    j = mlp.judge(net, diag, k=8)
+    assert np.isfinite(j["ratio"]) and j["jacobi"] > 0

@@ -1,0 +1,84 @@
+"""Pins of the learned-preconditioner oracle (CPU): the backward pass against
+central finite differences of the loss, the partition of unity, and the
+identity network reproducing its input through the cell extraction and
+weighted assembly."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp_oracle as mo
+from oracle.fe_oracle import constrained_mask
+
+
+def rand_params(rng, F, H):
+    return [rng.standard_normal((H, F)) / np.sqrt(F), 0.1 * rng.standard_normal(H),
+            rng.standard_normal((H, H)) / np.sqrt(H), 0.1 * rng.standard_normal(H),
+            rng.standard_normal((F, H)) / np.sqrt(H), 0.1 * rng.standard_normal(F)]
+
+
+def test_backward_matches_central_differences():
+    rng = np.random.default_rng(3)
+    F, H, n = 7, 6, 11
+    params = rand_params(rng, F, H)
+    X = rng.standard_normal((n, F))
+    T = rng.standard_normal((n, F))
+    loss, grads = mo.loss_and_grads(params, X, T)
+    h = 1e-6
+    for pi, P in enumerate(params):
+        flat = P.reshape(-1)
+        for idx in rng.choice(flat.size, size=min(flat.size, 12), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = mo.loss_and_grads(params, X, T)
+            flat[idx] = old - h
+            lm, _ = mo.loss_and_grads(params, X, T)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            g = grads[pi].reshape(-1)[idx]
+            assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (pi, idx, fd, g)
+
+
+@pytest.mark.parametrize("bc", [W.BC_NONE, W.BC_DIRICHLET0, W.BC_PERIODIC])
+@pytest.mark.parametrize("n", [(1, 2, 1), (2, 2, 3)])
+def test_partition_of_unity(bc, n):
+    mesh = W.BoxMesh(n=n, bc=bc)
+    p = 2
+    w = mo.pou_weights(mesh, p)
+    from oracle.fe_oracle import cell_dof_map
+    cmap = cell_dof_map(mesh, p)
+    tot = np.zeros(constrained_mask(mesh, p).size)
+    np.add.at(tot, cmap.ravel(), w.ravel())
+    cons = constrained_mask(mesh, p)
+    np.testing.assert_allclose(tot[~cons], 1.0, rtol=0, atol=1e-15)
+    assert np.all(tot[cons] == 0.0)
+
+
+@pytest.mark.parametrize("bc", [W.BC_NONE, W.BC_DIRICHLET0, W.BC_PERIODIC])
+def test_identity_network_reproduces_the_input(bc):
+    mesh = W.BoxMesh(n=(2, 1, 3), bc=bc)
+    p, k = 3, 4
+    cons = constrained_mask(mesh, p)
+    R = np.random.default_rng(1).uniform(-1, 1, (cons.size, k))
+    R[cons] = 0.0
+    X, _, rho = mo.cell_inputs(mesh, p, R)
+    np.testing.assert_allclose(np.sqrt((X * X).mean(axis=1)), 1.0, rtol=1e-12)
+    Z = mo.cell_assemble(mesh, p, X, rho, k)
+    np.testing.assert_allclose(Z, R, rtol=0, atol=1e-14)
+    d = np.random.default_rng(2).uniform(1, 2, cons.size)
+    Z2 = mo.cell_assemble(mesh, p, X, rho, k, R=R, diag=d)
+    np.testing.assert_allclose(Z2, R + R / d[:, None], rtol=0, atol=1e-14)
+
+
+def test_bf16_rounding_is_nearest_even():
+    # 1 + 2^-8 is halfway between 1 and the next BF16 value 1 + 2^-7: ties to even (1)
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5, 3.0e-3])
+    r = mo.bf16_round(vals)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -6
+    assert r[3] == -2.5
+    assert abs(r[4] - 3.0e-3) <= 3.0e-3 * 2 ** -8
+
+
+def test_adam_first_step_moves_by_lr():
+    w, g = np.array([1.0, -2.0]), np.array([0.5, -3.0])
+    w1, m1, m2 = mo.adam_step(w, g, np.zeros(2), np.zeros(2), 0.1, 0.9, 0.999, 1e-12, 1)
+    np.testing.assert_allclose(w1, w - 0.1 * np.sign(g), rtol=1e-6)
