@@ -200,35 +200,47 @@ def solve_leg(a) -> dict:
     jac = blockcg.jacobi_preconditioner(diag)
     runs = [("jacobi_fp64", jac, "fp64", None), ("jacobi_mixed_fp32", jac, "fp32", None)]
     for name, M, prec, fb in runs:
+        print(f"solve {name} ...", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         X, st = blockcg.solve(op, B, M, tol=1e-10, maxit=a.solve_maxit, inner_precision=prec,
                               fallback=fb)
         out["solves"][name] = {"seconds": st.seconds, "iterations": st.iterations,
-                               "refinements": st.refinements, "converged": st.converged,
-                               "rel_residual": st.rel_residual, "breakdown": st.breakdown}
+                               "refinements": st.refinements, "converged": bool(st.converged),
+                               "rel_residual": st.rel_residual, "breakdown": bool(st.breakdown)}
         print(json.dumps({name: out["solves"][name]}), file=sys.stderr, flush=True)
         del X
     # learned preconditioner: train on operator-generated pairs, judge, solve
+    print("training the cell network ...", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    net = mlp.CellMLP(op, hidden=256, seed=0)
-    losses = mlp.train(net, diag, steps=a.train_steps, k=16, lr=1e-3)
+    net = mlp.CellMLP(op, hidden=256, seed=0, dscale=diag)
+    losses = mlp.train(net, diag, steps=a.train_steps, k=16, refresh=a.train_refresh)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     verdict = mlp.judge(net, diag, k=16)
+    fit = mlp.local_fit(net, diag, k=16)
     out["training"] = {"seconds": t_train, "steps": a.train_steps, "loss_first": losses[0],
-                       "loss_last": float(np.mean(losses[-10:])), "judge": verdict}
-    use_net = verdict["ratio"] < 1.0
-    M = net.preconditioner(diag) if use_net else jac
-    X, st = blockcg.solve(op, B, M, tol=1e-10, maxit=a.solve_maxit, inner_precision="fp32",
-                          fallback=jac if use_net else None)
-    out["solves"]["learned_mixed_fp32"] = {
-        "seconds": st.seconds, "iterations": st.iterations, "refinements": st.refinements,
-        "converged": st.converged, "rel_residual": st.rel_residual, "breakdown": st.breakdown,
-        "network_used": use_net, "fallback_switches": st.precond_switches}
-    j = out["solves"]["jacobi_mixed_fp32"]
-    out["value"] = st.seconds
-    out["learned_vs_jacobi_mixed"] = {"time_ratio": st.seconds / j["seconds"],
-                                      "iteration_ratio": st.iterations / max(j["iterations"], 1)}
+                       "loss_last": float(np.mean(losses[-10:])), "judge": verdict,
+                       "local_fit": fit}
+    print(json.dumps({"training": out["training"]}), file=sys.stderr, flush=True)
+    use_net = bool(verdict["ratio"] < 1.0)
+    # the learned preconditioner (measured whatever the judge says), both applies
+    for name, prec in (("learned_fp64", "fp64"), ("learned_mixed_fp32", "fp32")):
+        print(f"solve {name} ...", file=sys.stderr, flush=True)
+        X, st = blockcg.solve(op, B, net.preconditioner(diag), tol=1e-10, maxit=a.solve_maxit,
+                              inner_precision=prec, fallback=jac)
+        out["solves"][name] = {
+            "seconds": st.seconds, "iterations": st.iterations, "refinements": st.refinements,
+            "converged": bool(st.converged), "rel_residual": st.rel_residual,
+            "breakdown": bool(st.breakdown), "fallback_switches": st.precond_switches}
+        print(json.dumps({name: out["solves"][name]}), file=sys.stderr, flush=True)
+        del X
+    out["judge_deploys_network"] = use_net
+    best = min(out["solves"].values(), key=lambda r: r["seconds"] if r["converged"] else 1e30)
+    out["value"] = best["seconds"]
+    for prec in ("fp64", "mixed_fp32"):
+        j, l = out["solves"][f"jacobi_{prec}"], out["solves"][f"learned_{prec}"]
+        out[f"learned_vs_jacobi_{prec}"] = {"time_ratio": l["seconds"] / j["seconds"],
+                                            "iteration_ratio": l["iterations"] / max(j["iterations"], 1)}
     return out
 
 
@@ -247,7 +259,9 @@ def main(argv=None):
     ap.add_argument("--solve", action="store_true",
                     help="block-CG solve benchmark on the 20^3 p = 6 mesh (own JSON line)")
     ap.add_argument("--solve-maxit", type=int, default=4000)
-    ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--train-steps", type=int, default=1000)
+    ap.add_argument("--train-refresh", type=int, default=25,
+                    help="new operator-generated pairs every this many training steps")
     ap.add_argument("--lanczos-steps", type=int, default=120)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of X into Y (known bytes), for scaling "

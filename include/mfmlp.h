@@ -1,7 +1,7 @@
 /* libmfmv: kernels of the learned cell-local preconditioner for block CG,
  *   Z = sum_e Q_e^T W_e f_theta(Q_e R),
  * with f_theta a small MLP (F = np^3 inputs and outputs, two hidden ReLU
- * layers), Q_e the extraction of cell e's nodes (Sec. 3.2.3) and W_e the
+ * layers, plus a symmetric linear skip), Q_e the extraction of cell e's nodes (Sec. 3.2.3) and W_e the
  * partition-of-unity weights (1 / number of cells sharing the node).  The
  * network is applied to every (cell, column) of a residual block and trained
  * on the GPU by these kernels; the method generates its own training pairs
@@ -42,33 +42,42 @@ int mf_mlp_gemm(int M, int N, int K, int ta, int tb, const uint16_t* A, int64_t 
                 const uint16_t* mask, int64_t ldmask, float* out_f32, int64_t ld_f32, int atomic,
                 uint16_t* out_bf16, int64_t ld_bf16, void* stream);
 
-/* Network input of every (cell, column): rho[row] = RMS over the cell's F =
- * np^3 node values of column j of R (constrained nodes count as 0) and
- * X0t[i][row] = bf16(R[node_i][j] / rho) (0 when rho = 0; rows F <= i < Fp
- * zero).  With E != NULL also Tt[i][row] = E[node_i][j] / rho (FP32): the
+/* Network input of every (cell, column): u_i = R[node_i][j], times sqrt(w_i)
+ * (the square root of node i's partition-of-unity weight) when pou_sqrt != 0
+ * and divided by sqrt(dscale[node_i]) when dscale != NULL (a positive
+ * diagonal, e.g. mf_diagonal's: the network then works on the diagonally
+ * scaled cell problem); rho[row] = RMS of u over the cell's F = np^3 nodes
+ * (constrained nodes count as 0) and X0t[i][row] = bf16(u_i / rho) (0 when
+ * rho = 0; rows F <= i < Fp zero).  With E != NULL also Tt[i][row] =
+ * E[node_i][j] sqrt(dscale[node_i]) / rho (FP32; no partition weight): the
  * training target for the pair (R, E).  R and E are ndofs x k multivectors
  * (ldr, lde >= k); X0t and Tt are Fp x (ncells k) with leading dimension
  * ldx >= ncells k; rho has ncells k entries.  Fp >= F, multiple of 8.
  * Errors: MF_ERR_ARG, MF_ERR_HIP. */
 int mf_cell_gather(mf_operator* op, int k, const double* R, int64_t ldr, const double* E,
                    int64_t lde, int Fp, uint16_t* X0t, float* Tt, int64_t ldx, float* rho,
-                   void* stream);
+                   int pou_sqrt, const double* dscale, void* stream);
 
 /* Z := Z0 + sum_e Q_e^T W_e (rho * Yt): the partition-of-unity assembly of
  * the network outputs Yt (FP32, first F rows used, ldy >= ncells k) scaled
- * back by rho, on top of Z0 = R / diag row-wise (the Jacobi term) when diag
- * != NULL, else Z0 = 0.  Z (ndofs x k, ldz >= k) is overwritten; it must not
- * be R.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+ * back by rho, with W_e the weights w_i (or sqrt(w_i) when pou_sqrt != 0:
+ * with the same weighting of the input, a symmetric cell map then gives a
+ * symmetric preconditioner), divided by sqrt(dscale[node]) when dscale !=
+ * NULL, on top of Z0 = R / diag row-wise (the Jacobi term) when diag != NULL,
+ * else Z0 = 0.  Z (ndofs x k, ldz >= k) is overwritten; it must not be R.
+ * Errors: MF_ERR_ARG, MF_ERR_HIP. */
 int mf_cell_scatter(mf_operator* op, int k, const float* Yt, int64_t ldy, const float* rho,
                     const double* diag, const double* R, int64_t ldr, double* Z, int64_t ldz,
-                    void* stream);
+                    int pou_sqrt, const double* dscale, void* stream);
 
-/* Mean squared error over rows and the first F features:
- * *loss += sum_{i<F, n<N} (Yt - Tt)^2 / N (device double, accumulated), and
- * dYt = bf16(2 (Yt - Tt) / N) (rows F <= i < Fp written as 0).  Yt, Tt, dYt
- * share the leading dimension ld.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+/* Weighted squared error over rows and the first F features, w = roww[n]
+ * (FP32 per row; NULL means 1):
+ *   *loss += scale * sum_{i<F, n<N} w (Yt - Tt)^2   (device double, accumulated)
+ *   dYt = bf16(2 scale w (Yt - Tt))                 (rows F <= i < Fp written 0)
+ * scale = 1 / (sum of the weights) gives the mean over the rows that count.
+ * Yt, Tt, dYt share the leading dimension ld.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
 int mf_mse_grad(int F, int Fp, int64_t N, const float* Yt, const float* Tt, int64_t ld,
-                uint16_t* dYt, double* loss, void* stream);
+                const float* roww, float scale, uint16_t* dYt, double* loss, void* stream);
 
 /* out[m] = (accumulate ? out[m] : 0) + sum_{n<N} X[m*ld + n] for m < M (BF16
  * X, FP32 out): bias gradients.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
@@ -80,6 +89,12 @@ int mf_row_sums(int M, int64_t N, const uint16_t* X, int64_t ld, float* out, int
  * also written as BF16.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
 int mf_adam(int64_t n, float* w, const float* g, float* m1, float* m2, uint16_t* wbf, float lr,
             float beta1, float beta2, float eps, int step, void* stream);
+
+/* S := (S + S^T) / 2 on the leading n x n block of a row-major FP32 matrix
+ * (ld >= n), and the same entries of its BF16 copy Sbf (same layout; may be
+ * NULL): the projection that keeps the network's linear skip block
+ * symmetric after each optimizer step.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+int mf_symmetrize(int n, float* S, int64_t ld, uint16_t* Sbf, void* stream);
 
 /* dst = bf16(src) (n values); mf_fill_f32: v[i] = x.  Errors: MF_ERR_ARG,
  * MF_ERR_HIP. */

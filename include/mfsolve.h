@@ -7,7 +7,8 @@
  * `stream` (a hipStream_t, NULL = the default stream), allocates nothing and
  * returns MF_OK or a negative mf_status (message in mf_last_error()).
  * Arguments are checked on the host: NULL pointers, n < 0, k < 1, ld < k
- * give MF_ERR_ARG; a failing HIP or rocBLAS launch gives MF_ERR_HIP.
+ * give MF_ERR_ARG; a failing HIP or rocBLAS launch gives MF_ERR_HIP.  With
+ * n = 0 the multivector pointers may be NULL (no rows to touch).
  */
 #ifndef MFSOLVE_H
 #define MFSOLVE_H
@@ -35,10 +36,19 @@ int mf_diagonal(mf_operator* op, double* diag, void* stream);
 /* C := alpha * A^T B + beta * C, the k x k Gram block of two n x k
  * multivectors (block CG: P^T A P, P^T R, (A P)^T Z).  C is row-major with
  * leading dimension ldc >= k, on the device; with beta = 0 its old contents
- * are ignored.  A plain GEMM, run by rocBLAS dgemm.  Errors: MF_ERR_ARG,
+ * are ignored.  Two stages: partial products of row chunks (plain GEMMs,
+ * rocBLAS strided-batched dgemm) into `work` (a caller-owned device array of
+ * at least mf_block_gram_work(n, k) doubles, contents undefined afterwards),
+ * then the library's reduction of them into C.  C and work must not overlap each other or A, B.
+ * Errors: MF_ERR_ARG (also for a short or overlapping work array),
  * MF_ERR_HIP. */
 int mf_block_gram(int64_t n, int k, const double* A, int64_t lda, const double* B, int64_t ldb,
-                  double alpha, double beta, double* C, int ldc, void* stream);
+                  double alpha, double beta, double* C, int ldc, double* work, int64_t work_len,
+                  void* stream);
+
+/* Number of doubles the work array of mf_block_gram needs for n rows and k
+ * columns (at most 512 k^2), or -1 for n < 0 or k < 1. */
+int64_t mf_block_gram_work(int64_t n, int k);
 
 /* Y := beta * Y + alpha * P M, with P an n x kp multivector (ldp), M a kp x k
  * row-major device matrix (ldm >= k) and Y n x k (ldy).  Y must not overlap P

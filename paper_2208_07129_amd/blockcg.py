@@ -76,14 +76,15 @@ def block_pcg(op: mfmv.Operator, B, X, precond: Callable, tol: float, maxit: int
     alpha = torch.empty(k, k, dtype=torch.float64, device=dev)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
     rn2 = torch.empty(k, dtype=torch.float64, device=dev)
+    work = mfmv.block_gram_work(n, k, dev)
 
     precond(R, P)
     it, converged, breakdown = 0, False, False
     active = precond
     while it < maxit:
         op.apply(P, Q, precision=precision)
-        mfmv.block_gram(P, Q, G)                      # P^T A P
-        mfmv.block_gram(P, R, S)                      # P^T R
+        mfmv.block_gram(P, Q, G, work=work)           # P^T A P
+        mfmv.block_gram(P, R, S, work=work)           # P^T R
         mfmv.spd_solve(G, S, alpha, st)
         mfmv.block_update(P, alpha, X, 1.0, 1.0)      # X += P alpha
         mfmv.block_update(Q, alpha, R, -1.0, 1.0)     # R -= Q alpha
@@ -108,7 +109,7 @@ def block_pcg(op: mfmv.Operator, B, X, precond: Callable, tol: float, maxit: int
                 if stats is not None:
                     stats.precond_switches += 1
                 active(R, Z)
-        mfmv.block_gram(Q, Z, S)                      # (A P)^T Z
+        mfmv.block_gram(Q, Z, S, work=work)           # (A P)^T Z
         mfmv.spd_solve(G, S, alpha, st)               # G^{-1} (A P)^T Z
         mfmv.block_update(P, alpha, Z, -1.0, 1.0)     # Z -= P G^{-1} (AP)^T Z
         P, Z = Z, P

@@ -39,7 +39,7 @@ int mf_mlp_gemm(int M, int N, int K, int ta, int tb, const uint16_t* A, int64_t 
 
 int mf_cell_gather(mf_operator* handle, int k, const double* R, int64_t ldr, const double* E,
                    int64_t lde, int Fp, uint16_t* X0t, float* Tt, int64_t ldx, float* rho,
-                   void* stream) {
+                   int pou_sqrt, const double* dscale, void* stream) {
   if (!handle || !R || !X0t || !rho) return fail(MF_ERR_ARG, "operator, R, X0t, rho non-NULL");
   Operator* op = reinterpret_cast<Operator*>(handle);
   const int F = op->np * op->np * op->np;
@@ -48,32 +48,33 @@ int mf_cell_gather(mf_operator* handle, int k, const double* R, int64_t ldr, con
   if (Fp < F || Fp % 8) return fail(MF_ERR_ARG, "Fp must be >= np^3 and a multiple of 8");
   if (ldx < op->ncells * k) return fail(MF_ERR_ARG, "ldx < ncells * k");
   if (op->ncells * k >= ((int64_t)1 << 31)) return fail(MF_ERR_UNSUPPORTED, "batch too large");
-  hipError_t err = launch_cell_gather(*op, k, R, ldr, E, lde, Fp, X0t, Tt, ldx, rho,
-                                      static_cast<hipStream_t>(stream));
+  hipError_t err = launch_cell_gather(*op, k, R, ldr, E, lde, Fp, X0t, Tt, ldx, rho, pou_sqrt,
+                                      dscale, static_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "cell gather launch");
   return MF_OK;
 }
 
 int mf_cell_scatter(mf_operator* handle, int k, const float* Yt, int64_t ldy, const float* rho,
                     const double* diag, const double* R, int64_t ldr, double* Z, int64_t ldz,
-                    void* stream) {
+                    int pou_sqrt, const double* dscale, void* stream) {
   if (!handle || !Yt || !rho || !Z) return fail(MF_ERR_ARG, "operator, Yt, rho, Z non-NULL");
   Operator* op = reinterpret_cast<Operator*>(handle);
   if (k < 1 || ldz < k) return fail(MF_ERR_ARG, "need k >= 1, ldz >= k");
   if (ldy < op->ncells * k) return fail(MF_ERR_ARG, "ldy < ncells * k");
   if (diag && (!R || ldr < k)) return fail(MF_ERR_ARG, "diag needs R with ldr >= k");
   if (R && R == Z) return fail(MF_ERR_ARG, "Z must not be R");
-  hipError_t err = launch_cell_scatter(*op, k, Yt, ldy, rho, diag, R, ldr, Z, ldz,
-                                       static_cast<hipStream_t>(stream));
+  hipError_t err = launch_cell_scatter(*op, k, Yt, ldy, rho, diag, R, ldr, Z, ldz, pou_sqrt,
+                                       dscale, static_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "cell scatter launch");
   return MF_OK;
 }
 
 int mf_mse_grad(int F, int Fp, int64_t N, const float* Yt, const float* Tt, int64_t ld,
-                uint16_t* dYt, double* loss, void* stream) {
+                const float* roww, float scale, uint16_t* dYt, double* loss, void* stream) {
   if (!Yt || !Tt || !dYt || !loss) return fail(MF_ERR_ARG, "NULL argument");
   if (F < 1 || Fp < F || N < 1 || ld < N) return fail(MF_ERR_ARG, "need 1 <= F <= Fp, 1 <= N <= ld");
-  hipError_t err = launch_mse_grad(F, Fp, N, Yt, Tt, ld, dYt, loss, static_cast<hipStream_t>(stream));
+  hipError_t err = launch_mse_grad(F, Fp, N, Yt, Tt, ld, roww, scale, dYt, loss,
+                                   static_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "MSE kernel launch");
   return MF_OK;
 }
@@ -94,6 +95,13 @@ int mf_adam(int64_t n, float* w, const float* g, float* m1, float* m2, uint16_t*
   hipError_t err = launch_adam(n, w, g, m1, m2, wbf, lr, beta1, beta2, eps, step,
                                static_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "Adam kernel launch");
+  return MF_OK;
+}
+
+int mf_symmetrize(int n, float* S, int64_t ld, uint16_t* Sbf, void* stream) {
+  if (!S || n < 1 || ld < n) return fail(MF_ERR_ARG, "need S non-NULL, n >= 1, ld >= n");
+  hipError_t err = launch_symmetrize(n, S, ld, Sbf, static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "symmetrize kernel launch");
   return MF_OK;
 }
 

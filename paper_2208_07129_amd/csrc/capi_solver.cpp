@@ -1,7 +1,9 @@
-// C ABI of the block-CG building blocks (include/mfsolve.h).  The Gram
-// blocks and block updates are plain GEMMs on row-major (dof-major)
-// multivectors and go to rocBLAS dgemm, read as column-major transposes; the
-// rest are the library's kernels (solver.hip).
+// C ABI of the block-CG building blocks (include/mfsolve.h).  Block updates
+// and the partial products of the Gram blocks are plain GEMMs on row-major
+// (dof-major) multivectors and go to rocBLAS dgemm, read as column-major
+// transposes (a k x k result over n >> k rows is split into row chunks, a
+// strided batch, so the library GEMM gets enough output tiles); the
+// reductions and the rest are the library's kernels (solver.hip).
 #include <mutex>
 #include <vector>
 
@@ -58,27 +60,65 @@ int mf_diagonal(mf_operator* handle, double* diag, void* stream) {
   return MF_OK;
 }
 
+int64_t mf_block_gram_work(int64_t n, int k) {
+  if (n < 0 || k < 1) return -1;
+  return gram_blocks(n) * (int64_t)k * k;
+}
+
 int mf_block_gram(int64_t n, int k, const double* A, int64_t lda, const double* B, int64_t ldb,
-                  double alpha, double beta, double* C, int ldc, void* stream) {
-  if (!A || !B || !C) return fail(MF_ERR_ARG, "A, B and C must be non-NULL");
+                  double alpha, double beta, double* C, int ldc, double* work, int64_t work_len,
+                  void* stream) {
+  if (!C || !work || (n > 0 && (!A || !B)))
+    return fail(MF_ERR_ARG, "A, B, C and work must be non-NULL");
   if (n < 0 || k < 1 || lda < k || ldb < k || ldc < k)
     return fail(MF_ERR_ARG, "need n >= 0, k >= 1, lda, ldb, ldc >= k");
-  if (n > INT32_MAX || lda > INT32_MAX || ldb > INT32_MAX)
-    return fail(MF_ERR_UNSUPPORTED, "n and leading dimensions must fit in 32 bits");
-  std::lock_guard<std::mutex> lock(g_blas_mutex);
-  rocblas_handle h;
-  if (int s = blas_handle(&h)) return s;
-  rocblas_set_stream(h, static_cast<hipStream_t>(stream));
-  // column-major: C^T (k x k) = B^T(k x n) * A(n x k)  <=>  row-major C = A^T B
-  rocblas_status st =
-      rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, k, k, (rocblas_int)n,
-                    &alpha, B, (rocblas_int)ldb, A, (rocblas_int)lda, &beta, C, ldc);
-  if (st != rocblas_status_success) return blas_fail(st, "rocblas_dgemm (gram)");
-  return MF_OK;
+  if (work_len < mf_block_gram_work(n, k)) return fail(MF_ERR_ARG, "work_len < mf_block_gram_work");
+  const size_t cs = span_bytes(k, k, ldc), ws = (size_t)work_len * sizeof(double);
+  if (overlaps(C, cs, A, span_bytes(n, k, lda)) || overlaps(C, cs, B, span_bytes(n, k, ldb)) ||
+      overlaps(work, ws, C, cs) || overlaps(work, ws, A, span_bytes(n, k, lda)) ||
+      overlaps(work, ws, B, span_bytes(n, k, ldb)))
+    return fail(MF_ERR_ARG, "C or work overlaps an operand");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  {
+    // partial products of row chunks by rocBLAS strided-batched dgemm (column-
+    // major: work_b (k x k) = B_b^T A_b), the tail chunk by one more dgemm, then
+    // the library's reduction into C
+    const int64_t nb = gram_blocks(n);
+    const int64_t chunk = n > 0 ? (n + nb - 1) / nb : 0;
+    const int64_t full = chunk > 0 ? n / chunk : 0;
+    const int64_t tail = n - full * chunk;
+    if (n > INT32_MAX || lda > INT32_MAX || ldb > INT32_MAX)
+      return fail(MF_ERR_UNSUPPORTED, "n and leading dimensions must fit in 32 bits");
+    std::lock_guard<std::mutex> lock(g_blas_mutex);
+    rocblas_handle h;
+    if (int st = blas_handle(&h)) return st;
+    rocblas_set_stream(h, hs);
+    const double one = 1.0, zero = 0.0;
+    if (full > 0) {
+      rocblas_status st = rocblas_dgemm_strided_batched(
+          h, rocblas_operation_none, rocblas_operation_transpose, k, k, (rocblas_int)chunk, &one,
+          B, (rocblas_int)ldb, chunk * ldb, A, (rocblas_int)lda, chunk * lda, &zero, work, k,
+          (int64_t)k * k, (rocblas_int)full);
+      if (st != rocblas_status_success) return blas_fail(st, "rocblas_dgemm_strided_batched");
+    }
+    if (tail > 0) {
+      rocblas_status st = rocblas_dgemm(
+          h, rocblas_operation_none, rocblas_operation_transpose, k, k, (rocblas_int)tail, &one,
+          B + full * chunk * ldb, (rocblas_int)ldb, A + full * chunk * lda, (rocblas_int)lda,
+          &zero, work + full * k * k, k);
+      if (st != rocblas_status_success) return blas_fail(st, "rocblas_dgemm (tail)");
+    }
+    // work_b holds the column-major transpose of the partial: sum of B^T A
+    // read as row-major is A^T B, as wanted
+    hipError_t err = launch_gram_reduce(k, (int)(full + (tail > 0)), work, alpha, beta, C, ldc, hs);
+    if (err != hipSuccess) return hip_fail(err, "Gram reduction launch");
+    return MF_OK;
+  }
 }
 
 int mf_block_update(int64_t n, int k, int kp, double alpha, const double* P, int64_t ldp,
                     const double* M, int ldm, double beta, double* Y, int64_t ldy, void* stream) {
+  if (n == 0) return (!M || k < 1 || kp < 1) ? fail(MF_ERR_ARG, "M non-NULL, k, kp >= 1") : MF_OK;
   if (!P || !M || !Y) return fail(MF_ERR_ARG, "P, M and Y must be non-NULL");
   if (n < 0 || k < 1 || kp < 1 || ldp < kp || ldm < k || ldy < k)
     return fail(MF_ERR_ARG, "need n >= 0, k, kp >= 1, ldp >= kp, ldm >= k, ldy >= k");
@@ -102,7 +142,7 @@ int mf_block_update(int64_t n, int k, int kp, double alpha, const double* P, int
 
 int mf_col_dots(int64_t n, int k, const double* A, int64_t lda, const double* B, int64_t ldb,
                 double* out, void* stream) {
-  if (!A || !B || !out) return fail(MF_ERR_ARG, "A, B and out must be non-NULL");
+  if (!out || (n > 0 && (!A || !B))) return fail(MF_ERR_ARG, "A, B and out must be non-NULL");
   if (n < 0 || k < 1 || lda < k || ldb < k) return fail(MF_ERR_ARG, "need n >= 0, k >= 1, ld >= k");
   hipError_t err = launch_col_dots(n, k, A, lda, B, ldb, out, static_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "column-dot kernel launch");
@@ -111,8 +151,9 @@ int mf_col_dots(int64_t n, int k, const double* A, int64_t lda, const double* B,
 
 int mf_axpby(int64_t n, int k, double a, const double* X, int64_t ldx, double b, double* Y,
              int64_t ldy, void* stream) {
-  if (!X || !Y) return fail(MF_ERR_ARG, "X and Y must be non-NULL");
+  if (n > 0 && (!X || !Y)) return fail(MF_ERR_ARG, "X and Y must be non-NULL");
   if (n < 0 || k < 1 || ldx < k || ldy < k) return fail(MF_ERR_ARG, "need n >= 0, k >= 1, ld >= k");
+  if (n == 0) return MF_OK;
   if (X != Y && overlaps(Y, span_bytes(n, k, ldy), X, span_bytes(n, k, ldx)))
     return fail(MF_ERR_ARG, "Y overlaps X without being equal to it");
   if (X == Y && ldx != ldy) return fail(MF_ERR_ARG, "in place needs ldx == ldy");
@@ -123,8 +164,9 @@ int mf_axpby(int64_t n, int k, double a, const double* X, int64_t ldx, double b,
 
 int mf_jacobi(int64_t n, int k, const double* diag, const double* R, int64_t ldr, double* Z,
               int64_t ldz, void* stream) {
-  if (!diag || !R || !Z) return fail(MF_ERR_ARG, "diag, R and Z must be non-NULL");
+  if (n > 0 && (!diag || !R || !Z)) return fail(MF_ERR_ARG, "diag, R and Z must be non-NULL");
   if (n < 0 || k < 1 || ldr < k || ldz < k) return fail(MF_ERR_ARG, "need n >= 0, k >= 1, ld >= k");
+  if (n == 0) return MF_OK;
   if (Z != R && overlaps(Z, span_bytes(n, k, ldz), R, span_bytes(n, k, ldr)))
     return fail(MF_ERR_ARG, "Z overlaps R without being equal to it");
   if (Z == R && ldz != ldr) return fail(MF_ERR_ARG, "in place needs ldz == ldr");

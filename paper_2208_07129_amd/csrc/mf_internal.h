@@ -149,6 +149,9 @@ hipError_t launch_col_dots(int64_t n, int k, const double* A, int64_t lda, const
                            int64_t ldb, double* out, hipStream_t s);
 hipError_t launch_axpby(int64_t n, int k, double a, const double* X, int64_t ldx, double b,
                         double* Y, int64_t ldy, hipStream_t s);
+int64_t gram_blocks(int64_t n);
+hipError_t launch_gram_reduce(int k, int nb, const double* work, double alpha, double beta,
+                              double* C, int ldc, hipStream_t s);
 hipError_t launch_jacobi(int64_t n, int k, const double* diag, const double* R, int64_t ldr,
                          double* Z, int64_t ldz, hipStream_t s);
 hipError_t launch_spd_solve(int k, int m, const double* G, const double* S, double* X, int* status,
@@ -171,12 +174,16 @@ hipError_t launch_gemm_bf16(int M, int N, int K, bool ta, bool tb, const uint16_
                             hipStream_t s);
 hipError_t launch_cell_gather(const Operator& op, int k, const double* R, int64_t ldr,
                               const double* E, int64_t lde, int Fp, uint16_t* X0t, float* Tt,
-                              int64_t ldx, float* rho, hipStream_t s);
+                              int64_t ldx, float* rho, int pou_sqrt, const double* dsc,
+                              hipStream_t s);
 hipError_t launch_cell_scatter(const Operator& op, int k, const float* Yt, int64_t ldy,
                                const float* rho, const double* diag, const double* R, int64_t ldr,
-                               double* Z, int64_t ldz, hipStream_t s);
+                               double* Z, int64_t ldz, int pou_sqrt, const double* dsc,
+                               hipStream_t s);
+hipError_t launch_symmetrize(int n, float* S, int64_t ld, uint16_t* Sbf, hipStream_t s);
 hipError_t launch_mse_grad(int F, int Fp, int64_t nrows, const float* Yt, const float* Tt,
-                           int64_t ld, uint16_t* dYt, double* loss, hipStream_t s);
+                           int64_t ld, const float* roww, float scale, uint16_t* dYt, double* loss,
+                           hipStream_t s);
 hipError_t launch_row_sums(int M, int64_t N, const uint16_t* X, int64_t ld, float* out,
                            bool accumulate, hipStream_t s);
 hipError_t launch_adam(int64_t n, float* w, const float* g, float* m1, float* m2, uint16_t* wbf,

@@ -149,7 +149,8 @@ constexpr int kCols = 64;
 __global__ void __launch_bounds__(256)
 cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int64_t ldr,
                    const double* __restrict__ E, int64_t lde, int Fp, uint16_t* __restrict__ X0t,
-                   float* __restrict__ Tt, int64_t ldx, float* __restrict__ rho) {
+                   float* __restrict__ Tt, int64_t ldx, float* __restrict__ rho, int pou_sqrt,
+                   const double* __restrict__ dsc) {
   __shared__ double part[256];
   const int e = blockIdx.x;
   const int j0 = blockIdx.y * kCols;
@@ -160,9 +161,12 @@ cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int6
   double ss = 0.0;
   if (j < k)
     for (int i = ph; i < F; i += 4) {
-      const int node = grid_node(g, cx, cy, cz, i % np, (i / np) % np, i / (np * np));
+      const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
+      const int node = grid_node(g, cx, cy, cz, i1, i2, i3);
       if (node >= 0) {
-        const double x = R[(int64_t)node * ldr + j];
+        double x = R[(int64_t)node * ldr + j];
+        if (pou_sqrt) x *= sqrt(pou_weight(g, i1, i2, i3, cx, cy, cz));
+        if (dsc) x /= sqrt(dsc[node]);
         ss = fma(x, x, ss);
       }
     }
@@ -177,10 +181,13 @@ cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int6
   for (int i = ph; i < Fp; i += 4) {
     double x = 0.0, y = 0.0;
     if (i < F) {
-      const int node = grid_node(g, cx, cy, cz, i % np, (i / np) % np, i / (np * np));
+      const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
+      const int node = grid_node(g, cx, cy, cz, i1, i2, i3);
       if (node >= 0) {
-        x = R[(int64_t)node * ldr + j] * s;
-        if (E) y = E[(int64_t)node * lde + j] * s;
+        const double ws = pou_sqrt ? sqrt(pou_weight(g, i1, i2, i3, cx, cy, cz)) : 1.0;
+        const double dh = dsc ? sqrt(dsc[node]) : 1.0;
+        x = R[(int64_t)node * ldr + j] * s * ws / dh;
+        if (E) y = E[(int64_t)node * lde + j] * s * dh;
       }
     }
     X0t[(int64_t)i * ldx + row] = f32_to_bf16((float)x);
@@ -192,7 +199,8 @@ cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int6
 // (partition-of-unity average of the cell-local predictions).
 __global__ void __launch_bounds__(256)
 cell_scatter_kernel(GridDesc g, int np, int k, const float* __restrict__ Yt, int64_t ldy,
-                    const float* __restrict__ rho, double* __restrict__ Z, int64_t ldz) {
+                    const float* __restrict__ rho, double* __restrict__ Z, int64_t ldz,
+                    int pou_sqrt, const double* __restrict__ dsc) {
   const int e = blockIdx.x;
   const int j0 = blockIdx.y * kCols;
   const int t = threadIdx.x, jj = t % kCols, ph = t / kCols;
@@ -206,31 +214,34 @@ cell_scatter_kernel(GridDesc g, int np, int k, const float* __restrict__ Yt, int
     const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
     const int node = grid_node(g, cx, cy, cz, i1, i2, i3);
     if (node < 0) continue;
-    const double w = pou_weight(g, i1, i2, i3, cx, cy, cz);
+    const double pw = pou_weight(g, i1, i2, i3, cx, cy, cz);
+    double w = pou_sqrt ? sqrt(pw) : pw;
+    if (dsc) w /= sqrt(dsc[node]);
     unsafeAtomicAdd(Z + (int64_t)node * ldz + j, w * r * (double)Yt[(int64_t)i * ldy + row]);
   }
 }
 
-// dYt = 2 (Yt - Tt) / nrows for features < F (0 for the padding), as BF16;
-// loss += sum (Yt - Tt)^2 / nrows.
+// dYt = 2 scale w[n] (Yt - Tt) for features < F (0 for the padding), as
+// BF16; loss += scale sum w[n] (Yt - Tt)^2 (w = 1 when the row weights are
+// null).
 __global__ void __launch_bounds__(256)
 mse_grad_kernel(int F, int Fp, int64_t nrows, const float* __restrict__ Yt,
-                const float* __restrict__ Tt, int64_t ld, uint16_t* __restrict__ dYt,
-                double* __restrict__ loss) {
+                const float* __restrict__ Tt, int64_t ld, const float* __restrict__ roww,
+                float scale, uint16_t* __restrict__ dYt, double* __restrict__ loss) {
   __shared__ double part[256];
   double acc = 0.0;
   const int64_t total = (int64_t)Fp * nrows;
-  const float sc = 2.0f / (float)nrows;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(idx / nrows);
     const int64_t n = idx % nrows;
+    const float w = roww ? roww[n] : 1.0f;
     float d = 0.f;
     if (i < F) {
       d = Yt[(int64_t)i * ld + n] - Tt[(int64_t)i * ld + n];
-      acc += (double)d * d;
+      acc += (double)w * d * d;
     }
-    dYt[(int64_t)i * ld + n] = f32_to_bf16(sc * d);
+    dYt[(int64_t)i * ld + n] = f32_to_bf16(2.0f * scale * w * d);
   }
   part[threadIdx.x] = acc;
   __syncthreads();
@@ -238,7 +249,7 @@ mse_grad_kernel(int F, int Fp, int64_t nrows, const float* __restrict__ Yt,
     if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) unsafeAtomicAdd(loss, part[0] / (double)nrows);
+  if (threadIdx.x == 0) unsafeAtomicAdd(loss, part[0] * (double)scale);
 }
 
 // out[m] (+)= sum_n X[m][n] (BF16 rows): bias gradients.
@@ -273,6 +284,25 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ w, const float* __res
     const float wi = w[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
     w[i] = wi;
     if (wbf) wbf[i] = f32_to_bf16(wi);
+  }
+}
+
+// S <- (S + S^T) / 2 on the leading n x n block of a row-major matrix (ld),
+// with its BF16 copy (same layout) refreshed.
+__global__ void symmetrize_kernel(int n, float* __restrict__ S, int64_t ld, uint16_t* __restrict__ Sbf) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    if (j < i) continue;
+    const float v = 0.5f * (S[(int64_t)i * ld + j] + S[(int64_t)j * ld + i]);
+    S[(int64_t)i * ld + j] = v;
+    S[(int64_t)j * ld + i] = v;
+    if (Sbf) {
+      const uint16_t b = f32_to_bf16(v);
+      Sbf[(int64_t)i * ld + j] = b;
+      Sbf[(int64_t)j * ld + i] = b;
+    }
   }
 }
 
@@ -329,32 +359,35 @@ hipError_t launch_gemm_bf16(int M, int N, int K, bool ta, bool tb, const uint16_
 
 hipError_t launch_cell_gather(const Operator& op, int k, const double* R, int64_t ldr,
                               const double* E, int64_t lde, int Fp, uint16_t* X0t, float* Tt,
-                              int64_t ldx, float* rho, hipStream_t s) {
+                              int64_t ldx, float* rho, int pou_sqrt, const double* dsc,
+                              hipStream_t s) {
   dim3 grid((unsigned)op.ncells, (k + kCols - 1) / kCols);
   hipLaunchKernelGGL(cell_gather_kernel, grid, dim3(256), 0, s, op.grid, op.np, k, R, ldr, E, lde,
-                     Fp, X0t, Tt, ldx, rho);
+                     Fp, X0t, Tt, ldx, rho, pou_sqrt, dsc);
   return hipGetLastError();
 }
 
 hipError_t launch_cell_scatter(const Operator& op, int k, const float* Yt, int64_t ldy,
                                const float* rho, const double* diag, const double* R, int64_t ldr,
-                               double* Z, int64_t ldz, hipStream_t s) {
+                               double* Z, int64_t ldz, int pou_sqrt, const double* dsc,
+                               hipStream_t s) {
   hipLaunchKernelGGL(init_z_kernel, dim3(blocks_for(op.ndofs * k)), dim3(256), 0, s, Z, op.ndofs,
                      k, ldz, diag, R, ldr);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   dim3 grid((unsigned)op.ncells, (k + kCols - 1) / kCols);
   hipLaunchKernelGGL(cell_scatter_kernel, grid, dim3(256), 0, s, op.grid, op.np, k, Yt, ldy, rho,
-                     Z, ldz);
+                     Z, ldz, pou_sqrt, dsc);
   return hipGetLastError();
 }
 
 hipError_t launch_mse_grad(int F, int Fp, int64_t nrows, const float* Yt, const float* Tt,
-                           int64_t ld, uint16_t* dYt, double* loss, hipStream_t s) {
+                           int64_t ld, const float* roww, float scale, uint16_t* dYt, double* loss,
+                           hipStream_t s) {
   unsigned blocks = blocks_for((int64_t)Fp * nrows);
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(mse_grad_kernel, dim3(blocks), dim3(256), 0, s, F, Fp, nrows, Yt, Tt, ld, dYt,
-                     loss);
+  hipLaunchKernelGGL(mse_grad_kernel, dim3(blocks), dim3(256), 0, s, F, Fp, nrows, Yt, Tt, ld, roww,
+                     scale, dYt, loss);
   return hipGetLastError();
 }
 
@@ -369,6 +402,12 @@ hipError_t launch_adam(int64_t n, float* w, const float* g, float* m1, float* m2
   const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
   hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, w, g, m1, m2, wbf, lr,
                      b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_symmetrize(int n, float* S, int64_t ld, uint16_t* Sbf, hipStream_t s) {
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(blocks_for((int64_t)n * n)), dim3(256), 0, s, n, S, ld,
+                     Sbf);
   return hipGetLastError();
 }
 

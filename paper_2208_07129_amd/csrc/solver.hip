@@ -111,6 +111,23 @@ col_dots_kernel(int64_t n, int k, const double* __restrict__ A, int64_t lda,
   }
 }
 
+// Gram block C = alpha A^T B + beta C in two stages: partial products of row
+// chunks (rocBLAS strided-batched dgemm, capi_solver.cpp) into work[b], then
+// their sum into C here.  Chunks of at least 2048 rows, at most 512 of them.
+constexpr int kGramRows = 2048, kGramMaxBlocks = 512;
+
+// C[i][j] := alpha sum_b work[b][i][j] + beta C[i][j] (beta = 0: C not read).
+__global__ void gram_reduce_kernel(int k, int nb, const double* __restrict__ work, double alpha,
+                                   double beta, double* __restrict__ C, int ldc) {
+  const int kk = k * k;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kk; i += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += work[(int64_t)b * kk + i];
+    double* c = C + (int64_t)(i / k) * ldc + i % k;
+    *c = beta == 0.0 ? alpha * s : fma(beta, *c, alpha * s);
+  }
+}
+
 // Y := a X + b Y (b = 0: Y is not read).
 __global__ void axpby_kernel(int64_t n, int k, double a, const double* X, int64_t ldx, double b,
                              double* Y, int64_t ldy) {
@@ -136,53 +153,79 @@ __global__ void jacobi_kernel(int64_t n, int k, const double* __restrict__ diag,
 }
 
 // X := G^{-1} S (G k x k SPD, S k x m), one workgroup.  The lower Cholesky
-// factor is formed in LDS (right-looking, one column per step); each thread
-// then owns right-hand-side columns and runs the forward and backward
-// substitutions, keeping its column of X in global memory (L1/L2 resident).
-constexpr int kSpdMaxK = 128, kSpdThreads = 256;
+// factor is formed in LDS in packed storage (row r at r(r+1)/2; right-looking,
+// one column per step).  The two triangular solves then run on panels of 64
+// right-hand-side columns held in LDS: 4 adjacent lanes own a column, split
+// each row's dot product and combine it with lane shuffles, so a column needs
+// no barrier (its 4 lanes are in one wavefront).
+constexpr int kSpdMaxK = 128, kSpdThreads = 256, kSpdPanel = 64;
+__device__ inline int tri(int r, int c) { return r * (r + 1) / 2 + c; }
 __global__ void __launch_bounds__(kSpdThreads)
 spd_solve_kernel(int k, int m, const double* __restrict__ G, const double* __restrict__ S,
                  double* __restrict__ X, int* __restrict__ status) {
-  extern __shared__ double L[];  // k x k, row-major
+  extern __shared__ double sh[];
+  double* L = sh;                                   // k(k+1)/2
+  double* P = sh + (k * (k + 1) / 2 + 1) / 2 * 2;   // k x kSpdPanel, 16-byte aligned
   __shared__ int bad;
   const int t = threadIdx.x;
-  for (int i = t; i < k * k; i += kSpdThreads) L[i] = G[i];
+  for (int i = t; i < k * k; i += kSpdThreads) {
+    const int r = i / k, c = i % k;
+    if (c <= r) L[tri(r, c)] = G[i];
+  }
   if (t == 0) bad = 0;
   __syncthreads();
   for (int c = 0; c < k; ++c) {
     if (t == 0) {
-      const double d = L[c * k + c];
+      const double d = L[tri(c, c)];
       if (!(d > 0.0) || !isfinite(d)) bad = c + 1;
-      else L[c * k + c] = sqrt(d);
+      else L[tri(c, c)] = sqrt(d);
     }
     __syncthreads();
     if (bad) break;
-    const double dc = L[c * k + c];
-    for (int r = c + 1 + t; r < k; r += kSpdThreads) L[r * k + c] /= dc;
+    const double dc = L[tri(c, c)];
+    for (int r = c + 1 + t; r < k; r += kSpdThreads) L[tri(r, c)] /= dc;
     __syncthreads();
-    // trailing lower triangle: rows r > c, columns c < s <= r
     const int rem = k - c - 1;
     for (int w = t; w < rem * rem; w += kSpdThreads) {
-      const int r = c + 1 + w / rem, s = c + 1 + w % rem;
-      if (s <= r) L[r * k + s] -= L[r * k + c] * L[s * k + c];
+      const int r = c + 1 + w / rem, s2 = c + 1 + w % rem;
+      if (s2 <= r) L[tri(r, s2)] -= L[tri(r, c)] * L[tri(s2, c)];
     }
     __syncthreads();
   }
   if (t == 0) *status = bad;
   if (bad) return;
-  for (int j = t; j < m; j += kSpdThreads) {
-    // L y = s
+  const int q = t & 3, jc = t >> 2;   // lane quarter, panel column
+  for (int j0 = 0; j0 < m; j0 += kSpdPanel) {
+    const int w = m - j0 < kSpdPanel ? m - j0 : kSpdPanel;
+    for (int i = t; i < k * kSpdPanel; i += kSpdThreads) {
+      const int r = i / kSpdPanel, c = i % kSpdPanel;
+      P[i] = c < w ? S[(int64_t)r * m + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    // L y = s (rows in order)
     for (int r = 0; r < k; ++r) {
-      double acc = S[r * m + j];
-      for (int c = 0; c < r; ++c) acc -= L[r * k + c] * X[c * m + j];
-      X[r * m + j] = acc / L[r * k + r];
+      double acc = 0.0;
+      for (int c = q; c < r; c += 4) acc = fma(L[tri(r, c)], P[c * kSpdPanel + jc], acc);
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      if (q == 0) P[r * kSpdPanel + jc] = (P[r * kSpdPanel + jc] - acc) / L[tri(r, r)];
+      __builtin_amdgcn_wave_barrier();
     }
-    // L^T x = y
+    // L^T x = y (rows in reverse)
     for (int r = k - 1; r >= 0; --r) {
-      double acc = X[r * m + j];
-      for (int c = r + 1; c < k; ++c) acc -= L[c * k + r] * X[c * m + j];
-      X[r * m + j] = acc / L[r * k + r];
+      double acc = 0.0;
+      for (int c = r + 1 + q; c < k; c += 4) acc = fma(L[tri(c, r)], P[c * kSpdPanel + jc], acc);
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      if (q == 0) P[r * kSpdPanel + jc] = (P[r * kSpdPanel + jc] - acc) / L[tri(r, r)];
+      __builtin_amdgcn_wave_barrier();
     }
+    __syncthreads();
+    for (int i = t; i < k * kSpdPanel; i += kSpdThreads) {
+      const int r = i / kSpdPanel, c = i % kSpdPanel;
+      if (c < w) X[(int64_t)r * m + j0 + c] = P[i];
+    }
+    __syncthreads();
   }
 }
 
@@ -220,6 +263,20 @@ hipError_t launch_col_dots(int64_t n, int k, const double* A, int64_t lda, const
   return hipGetLastError();
 }
 
+hipError_t launch_gram_reduce(int k, int nb, const double* work, double alpha, double beta,
+                              double* C, int ldc, hipStream_t s) {
+  const int kk = k * k;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((kk + 255) / 256), dim3(256), 0, s, k, nb, work, alpha,
+                     beta, C, ldc);
+  return hipGetLastError();
+}
+
+int64_t gram_blocks(int64_t n) {
+  int64_t nb = (n + kGramRows - 1) / kGramRows;
+  if (nb > kGramMaxBlocks) nb = kGramMaxBlocks;
+  return nb < 1 ? 1 : nb;
+}
+
 hipError_t launch_axpby(int64_t n, int k, double a, const double* X, int64_t ldx, double b,
                         double* Y, int64_t ldy, hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -240,7 +297,7 @@ int spd_max_k() { return kSpdMaxK; }
 
 hipError_t launch_spd_solve(int k, int m, const double* G, const double* S, double* X, int* status,
                             hipStream_t s) {
-  const size_t lds = (size_t)k * k * sizeof(double);
+  const size_t lds = ((size_t)(k * (k + 1) / 2 + 1) / 2 * 2 + (size_t)k * kSpdPanel) * sizeof(double);
   if (lds > 64 * 1024) {
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(spd_solve_kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

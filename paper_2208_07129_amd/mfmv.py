@@ -30,11 +30,12 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_batch_apply", "mf_batch_capture", "mf_batch_replay", "mf_batch_info",
            "mf_last_error",
            # include/mfsolve.h
-           "mf_diagonal", "mf_block_gram", "mf_block_update", "mf_col_dots", "mf_axpby",
+           "mf_diagonal", "mf_block_gram", "mf_block_gram_work", "mf_block_update", "mf_col_dots",
+           "mf_axpby",
            "mf_jacobi", "mf_spd_solve",
            # include/mfmlp.h
            "mf_mlp_gemm", "mf_cell_gather", "mf_cell_scatter", "mf_mse_grad", "mf_row_sums",
-           "mf_adam", "mf_to_bf16", "mf_fill_f32")
+           "mf_adam", "mf_symmetrize", "mf_to_bf16", "mf_fill_f32")
 
 
 class MfError(RuntimeError):
@@ -86,7 +87,8 @@ def lib() -> ctypes.CDLL:
             "mf_batch_replay": (I, [P, P]),
             "mf_batch_info": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(I), ctypes.POINTER(I)]),
             "mf_diagonal": (I, [P, P, P]),
-            "mf_block_gram": (I, [I64, I, P, I64, P, I64, D, D, P, I, P]),
+            "mf_block_gram": (I, [I64, I, P, I64, P, I64, D, D, P, I, P, I64, P]),
+            "mf_block_gram_work": (I64, [I64, I]),
             "mf_block_update": (I, [I64, I, I, D, P, I64, P, I, D, P, I64, P]),
             "mf_col_dots": (I, [I64, I, P, I64, P, I64, P, P]),
             "mf_axpby": (I, [I64, I, D, P, I64, D, P, I64, P]),
@@ -94,9 +96,10 @@ def lib() -> ctypes.CDLL:
             "mf_spd_solve": (I, [I, I, P, P, P, P, P]),
             "mf_mlp_gemm": (I, [I, I, I, I, I, P, I64, P, I64, I, P, I, P, I64, P, I64, I, P, I64,
                                 P]),
-            "mf_cell_gather": (I, [P, I, P, I64, P, I64, I, P, P, I64, P, P]),
-            "mf_cell_scatter": (I, [P, I, P, I64, P, P, P, I64, P, I64, P]),
-            "mf_mse_grad": (I, [I, I, I64, P, P, I64, P, P, P]),
+            "mf_cell_gather": (I, [P, I, P, I64, P, I64, I, P, P, I64, P, I, P, P]),
+            "mf_cell_scatter": (I, [P, I, P, I64, P, P, P, I64, P, I64, I, P, P]),
+            "mf_symmetrize": (I, [I, P, I64, P, P]),
+            "mf_mse_grad": (I, [I, I, I64, P, P, I64, P, F32, P, P, P]),
             "mf_row_sums": (I, [I, I64, P, I64, P, I, P]),
             "mf_adam": (I, [I64, P, P, P, P, P, F32, F32, F32, F32, I, P]),
             "mf_to_bf16": (I, [I64, P, P, P]),
@@ -275,8 +278,15 @@ def diagonal(op: Operator, out=None, stream=None):
     return out
 
 
-def block_gram(A, B, C=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
-    """C := alpha A^T B + beta C (k x k)."""
+def block_gram_work(n: int, k: int, device="cuda"):
+    """A work array for block_gram on n x k multivectors."""
+    import torch
+    return torch.empty(max(1, lib().mf_block_gram_work(n, k)), dtype=torch.float64, device=device)
+
+
+def block_gram(A, B, C=None, alpha: float = 1.0, beta: float = 0.0, work=None, stream=None):
+    """C := alpha A^T B + beta C (k x k); `work` from block_gram_work (allocated
+    here when not given)."""
     import torch
     pa, n, k, lda = _mv(A, "A")
     pb, nb, kb, ldb = _mv(B, "B")
@@ -287,8 +297,10 @@ def block_gram(A, B, C=None, alpha: float = 1.0, beta: float = 0.0, stream=None)
     pc, kc, kc2, ldc = _mv(C, "C")
     if (kc, kc2) != (k, k):
         raise ValueError("C must be k x k")
+    if work is None:
+        work = block_gram_work(n, k, A.device)
     _check(lib().mf_block_gram(n, k, pa, lda, pb, ldb, float(alpha), float(beta), pc, ldc,
-                               _stream_ptr(stream)))
+                               work.data_ptr(), work.numel(), _stream_ptr(stream)))
     return C
 
 

@@ -99,7 +99,14 @@ def test_cell_gather_and_scatter_match_oracle(bc):
     E = rng.uniform(-1, 1, (op.ndofs, k))
     R[cons] = 0.0
     net = mlp.CellMLP(op, hidden=16, seed=1)
-    b = net.gather(torch.from_numpy(R).to(dev()), torch.from_numpy(E).to(dev()))
+    Rt, Et = torch.from_numpy(R).to(dev()), torch.from_numpy(E).to(dev())
+    bs = net.gather(Rt, pou_sqrt=True)
+    Xs, _, rhos = mo.cell_inputs(mesh, p, R, pou_sqrt=True)
+    rows = op.ncells * k
+    np.testing.assert_allclose(bs["rho"].cpu().numpy()[:rows], rhos, rtol=1e-6)
+    xs = (bs["X0"].cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    assert np.all(np.abs(xs.astype(np.float64)[:net.F, :rows].T - Xs) <= np.abs(Xs) * 2 ** -8 + 1e-30)
+    b = net.gather(Rt, Et)
     X, T, rho = mo.cell_inputs(mesh, p, R, E)
     F = net.F
     x0 = b["X0"].cpu().numpy().view(np.uint16).astype(np.uint32) << 16
@@ -117,15 +124,27 @@ def test_cell_gather_and_scatter_match_oracle(bc):
     Rd, dd = torch.from_numpy(R).to(dev()), torch.from_numpy(diag).to(dev())
     Z = torch.empty_like(Rd)
     for with_j in (False, True):
-        mfmv._check(mfmv.lib().mf_cell_scatter(
-            op._h, k, b["Y"].data_ptr(), b["ld"], b["rho"].data_ptr(),
-            dd.data_ptr() if with_j else None, Rd.data_ptr() if with_j else None, k,
-            Z.data_ptr(), k, None))
-        rows = op.ncells * k
-        ref = mo.cell_assemble(mesh, p, Y[:F, :rows].T.astype(np.float64),
-                               b["rho"].cpu().numpy()[:rows].astype(np.float64), k,
-                               R if with_j else None, diag if with_j else None)
-        np.testing.assert_allclose(Z.cpu().numpy(), ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+        for sq in (0, 1):
+            for ds in (None, dd):
+                mfmv._check(mfmv.lib().mf_cell_scatter(
+                    op._h, k, b["Y"].data_ptr(), b["ld"], b["rho"].data_ptr(),
+                    dd.data_ptr() if with_j else None, Rd.data_ptr() if with_j else None, k,
+                    Z.data_ptr(), k, sq, None if ds is None else ds.data_ptr(), None))
+                ref = mo.cell_assemble(mesh, p, Y[:F, :rows].T.astype(np.float64),
+                                       b["rho"].cpu().numpy()[:rows].astype(np.float64), k,
+                                       R if with_j else None, diag if with_j else None,
+                                       pou_sqrt=bool(sq), dscale=None if ds is None else diag)
+                np.testing.assert_allclose(Z.cpu().numpy(), ref, rtol=0,
+                                           atol=1e-10 * np.abs(ref).max())
+    # diagonally scaled network inputs and targets
+    net.dscale = dd
+    bd = net.gather(Rt, Et, pou_sqrt=True)
+    Xd, Td, rhod = mo.cell_inputs(mesh, p, R, E, pou_sqrt=True, dscale=diag)
+    np.testing.assert_allclose(bd["rho"].cpu().numpy()[:rows], rhod, rtol=1e-6)
+    xd = (bd["X0"].cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    assert np.all(np.abs(xd.astype(np.float64)[:F, :rows].T - Xd) <= np.abs(Xd) * 2 ** -8 + 1e-30)
+    np.testing.assert_allclose(bd["T"].cpu().numpy()[:F, :rows].T, Td, rtol=1e-6,
+                               atol=1e-6 * np.abs(Td).max())
 
 
 def test_forward_backward_match_oracle():
@@ -145,16 +164,34 @@ def test_forward_backward_match_oracle():
     x0 = (b["X0"].cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
     X = x0.astype(np.float64)[:F, :rows].T
     T = b["T"].cpu().numpy().astype(np.float64)[:F, :rows].T
-    W1, b1, W2, b2, W3, b3 = [p.cpu().numpy().astype(np.float64) for p in net.params]
-    params = [mo.bf16_round(W1[:, :F]), b1, mo.bf16_round(W2), b2, mo.bf16_round(W3[:F]), b3[:F]]
+    H = net.H
+    W1, b1, W2, b2, W3S, b3 = [p.cpu().numpy().astype(np.float64) for p in net.params]
+    params = [mo.bf16_round(W1[:, :F]), b1, mo.bf16_round(W2), b2, mo.bf16_round(W3S[:F, :H]),
+              b3[:F], mo.bf16_round(W3S[:F, H:H + F])]
     loss, grads = mo.loss_and_grads(params, X, T)
     assert abs(net._loss.item() - loss) <= 2e-2 * loss
-    gW1, gb1, gW2, gb2, gW3, gb3 = [g.cpu().numpy().astype(np.float64) for g in net.grads]
-    got = [gW1[:, :F], gb1, gW2, gb2, gW3[:F], gb3[:F]]
-    for name, g, r in zip(["W1", "b1", "W2", "b2", "W3", "b3"], got, grads):
+    gW1, gb1, gW2, gb2, gW3S, gb3 = [g.cpu().numpy().astype(np.float64) for g in net.grads]
+    got = [gW1[:, :F], gb1, gW2, gb2, gW3S[:F, :H], gb3[:F], gW3S[:F, H:H + F]]
+    for name, g, r in zip(["W1", "b1", "W2", "b2", "W3", "b3", "S"], got, grads):
         rel = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
         assert rel <= 2e-2, (name, rel)
-    assert np.all(gW1[:, F:] == 0) and np.all(gW3[F:] == 0) and np.all(gb3[F:] == 0)
+    assert np.all(gW1[:, F:] == 0) and np.all(gW3S[F:] == 0) and np.all(gb3[F:] == 0)
+    assert np.all(gW3S[:, H + F:] == 0)
+
+
+def test_symmetric_projection():
+    mesh, op = small_op(W.BC_PERIODIC, p=2, n=(1, 1, 2))
+    net = mlp.CellMLP(op, hidden=16, seed=2)
+    rng = np.random.default_rng(8)
+    H, F = net.H, net.F
+    Wh = rng.standard_normal(net.params[4].shape).astype(np.float32)
+    net.params[4].copy_(torch.from_numpy(Wh))
+    net.project()
+    got = net.params[4].cpu().numpy()
+    Sref = 0.5 * (Wh[:F, H:H + F] + Wh[:F, H:H + F].T)
+    np.testing.assert_allclose(got[:F, H:H + F], Sref, rtol=1e-6)
+    np.testing.assert_array_equal(got[:, :H], Wh[:, :H])
+    np.testing.assert_array_equal(net.wbf[4].cpu().numpy()[:F, H:H + F], mlp._host_bf16(Sref))
 
 
 def test_adam_matches_oracle():
@@ -166,20 +203,49 @@ def test_adam_matches_oracle():
     for gd, gh in zip(net.grads, g):
         gd.copy_(torch.from_numpy(gh))
     net.adam(1e-2)
+    H, F = net.H, net.F
     for i, (w, gh) in enumerate(zip(w0, g)):
         ref, _, _ = mo.adam_step(w, gh, np.zeros_like(w), np.zeros_like(w), 1e-2, 0.9, 0.999, 1e-8, 1)
+        if i == 4:  # the skip block is projected onto symmetric matrices after the step
+            S = ref[:F, H:H + F]
+            ref[:F, H:H + F] = 0.5 * (S + S.T)
         np.testing.assert_allclose(net.params[i].cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
     for i in (0, 2, 4):
         np.testing.assert_array_equal(net.wbf[i].cpu().numpy(),
                                       mlp._host_bf16(net.params[i].cpu().numpy()))
 
 
-def test_training_reduces_loss_and_is_judged():
-    mesh, op = small_op(W.BC_PERIODIC, p=3, n=(3, 3, 3))
+def test_training_reduces_loss_and_fits_the_cell_blocks():
+    mesh, op = small_op(W.BC_PERIODIC, p=3, n=(4, 4, 4))
     diag = mfmv.diagonal(op)
-    net = mlp.CellMLP(op, hidden=64, seed=0)
-    losses = mlp.train(net, diag, steps=120, k=16, lr=2e-3, refresh=10)
-    first, last = np.mean(losses[:10]), np.mean(losses[-10:])
-    assert np.isfinite(last) and last < 0.7 * first, (first, last)
-    j = mlp.judge(net, diag, k=8)
-    assert np.isfinite(j["ratio"]) and j["jacobi"] > 0
+    net = mlp.CellMLP(op, hidden=128, seed=0)
+    losses = mlp.train(net, diag, steps=300, k=16)
+    first, last = np.mean(losses[:5]), np.mean(losses[-10:])
+    assert np.isfinite(last) and last < 0.3 * first, (first, last)
+    fit = mlp.local_fit(net, diag, k=16)
+    assert fit < 0.3, fit           # held out: close to the cell-block inverse
+    for linear in (True, False):
+        j = mlp.judge(net, diag, k=8, linear=linear)
+        assert np.isfinite(j["ratio"]) and j["jacobi"] > 0
+
+
+def test_learned_preconditioner_gain_over_jacobi():
+    """The trained network against Jacobi in block PCG on the same problem (FP64
+    apply): both reach 1e-10; the judge prefers the learned step on held-out pairs
+    and the learned preconditioner needs fewer iterations (the gain the network
+    brings).  The whole nonlinear network also converges (flexible iteration)."""
+    mesh, op = small_op(W.BC_PERIODIC, p=3, n=(4, 4, 4))
+    diag = mfmv.diagonal(op)
+    net = mlp.CellMLP(op, hidden=128, seed=0, dscale=diag)
+    mlp.train(net, diag, steps=1000, k=16)
+    B = torch.from_numpy(np.random.default_rng(4).uniform(-1, 1, (op.ndofs, 8))).to(dev())
+    jac = blockcg.jacobi_preconditioner(diag)
+    _, sj = blockcg.solve(op, B, jac, tol=1e-10, maxit=3000)
+    _, sl = blockcg.solve(op, B, net.preconditioner(diag), tol=1e-10, maxit=3000, fallback=jac)
+    _, sf = blockcg.solve(op, B, net.preconditioner(diag, linear=False), tol=1e-10, maxit=3000,
+                          fallback=jac)
+    jd = mlp.judge(net, diag, k=8)
+    print("jacobi", sj.iterations, "learned", sl.iterations, "full", sf.iterations, "judge", jd)
+    assert sj.converged and sl.converged and sf.converged
+    assert jd["ratio"] < 1.0
+    assert sl.iterations < sj.iterations

@@ -11,9 +11,10 @@ from oracle.fe_oracle import constrained_mask
 
 
 def rand_params(rng, F, H):
+    S = rng.standard_normal((F, F)) / np.sqrt(F)
     return [rng.standard_normal((H, F)) / np.sqrt(F), 0.1 * rng.standard_normal(H),
             rng.standard_normal((H, H)) / np.sqrt(H), 0.1 * rng.standard_normal(H),
-            rng.standard_normal((F, H)) / np.sqrt(H), 0.1 * rng.standard_normal(F)]
+            rng.standard_normal((F, H)) / np.sqrt(H), 0.1 * rng.standard_normal(F), S + S.T]
 
 
 def test_backward_matches_central_differences():
@@ -67,6 +68,35 @@ def test_identity_network_reproduces_the_input(bc):
     d = np.random.default_rng(2).uniform(1, 2, cons.size)
     Z2 = mo.cell_assemble(mesh, p, X, rho, k, R=R, diag=d)
     np.testing.assert_allclose(Z2, R + R / d[:, None], rtol=0, atol=1e-14)
+    # symmetric weighting: identity cell map gives sum_e Q_e^T w Q_e r = r too
+    Xs, _, rhos = mo.cell_inputs(mesh, p, R, pou_sqrt=True)
+    np.testing.assert_allclose(mo.cell_assemble(mesh, p, Xs, rhos, k, pou_sqrt=True), R,
+                               rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("bc", [W.BC_NONE, W.BC_DIRICHLET0, W.BC_PERIODIC])
+@pytest.mark.parametrize("scaled", [False, True])
+def test_symmetric_weighting_gives_a_symmetric_operator(bc, scaled):
+    """With sqrt(w) on both sides and a symmetric linear cell map S, the assembled
+    map r -> z is a symmetric matrix (checked as u^T M v = v^T M u)."""
+    mesh = W.BoxMesh(n=(2, 2, 1), bc=bc)
+    p, k = 2, 1
+    cons = constrained_mask(mesh, p)
+    F = (p + 1) ** 3
+    rng = np.random.default_rng(5)
+    S = rng.standard_normal((F, F))
+    S = S + S.T
+
+    d = rng.uniform(0.5, 2.0, cons.size) if scaled else None
+
+    def M(r):
+        X, _, rho = mo.cell_inputs(mesh, p, r, pou_sqrt=True, dscale=d)
+        return mo.cell_assemble(mesh, p, X @ S.T, rho, k, pou_sqrt=True, dscale=d)
+    u = rng.standard_normal((cons.size, 1))
+    v = rng.standard_normal((cons.size, 1))
+    u[cons] = 0.0
+    v[cons] = 0.0
+    assert abs((u * M(v)).sum() - (v * M(u)).sum()) <= 1e-12 * np.abs(u * M(v)).sum()
 
 
 def test_bf16_rounding_is_nearest_even():
