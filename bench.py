@@ -30,7 +30,8 @@ METRIC = "A·X GDoF·vec/s, FP64 vs mixed precision at ≤1e-6 rel err; %rooflin
 UNIT = "GDoF·vec/s"
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (= FP64 matrix) peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_f64_traffic.json")
-KERNEL_SOURCES = ["paper_2208_07129_amd/csrc/apply_box.hip", "paper_2208_07129_amd/csrc/sf_common.h",
+KERNEL_SOURCES = ["paper_2208_07129_amd/csrc/apply_box.hip", "paper_2208_07129_amd/csrc/box_body.h",
+                  "paper_2208_07129_amd/csrc/sf_common.h",
                   "paper_2208_07129_amd/csrc/sf_tables.h"]
 
 
