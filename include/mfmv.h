@@ -195,9 +195,10 @@ int mf_timing_read(mf_operator* op, int* count, double* zero_ms, double* kernel_
 
 /* A batch applies a list of operators, each to its own multivector,
  *     Y_i := A_i X_i,  i = 0 .. nops-1,
- * in one persistent launch: the (cell, column-tile) work items of all
- * operators form one list (heaviest degree first) that a grid sized to the
- * device's resident capacity drains through a global counter.  This is the
+ * in one launch (or one per degree): the (cell, column-tile) work items of all
+ * operators form one list (heaviest degree first), cut into one contiguous
+ * range per XCD of equal estimated cost that the XCD's workgroups take in an
+ * interleaved order; a byte table maps each item to its operator.  This is the
  * single launch over every (cell, batch) pair of eq. basempigpu widened to
  * several meshes, degrees and column counts.  Supported operators: axis-aligned
  * cells, q = p + 1, p in [2, 8] (MF_ERR_UNSUPPORTED otherwise); at most 64 per
@@ -205,21 +206,34 @@ int mf_timing_read(mf_operator* op, int* count, double* zero_ms, double* kernel_
 typedef struct mf_batch mf_batch;
 
 /* nvec[i]: columns of X_i / Y_i; prec: as mf_apply.  Allocates the work table
- * and counter on the current device.  Errors: MF_ERR_ARG, MF_ERR_UNSUPPORTED,
- * MF_ERR_HIP. */
+ * and the per-XCD item ranges on the current device.  Errors: MF_ERR_ARG,
+ * MF_ERR_UNSUPPORTED, MF_ERR_HIP. */
 int mf_batch_create(int nops, mf_operator* const* ops, const int* nvec, int prec, mf_batch** out);
 void mf_batch_destroy(mf_batch* b);
 
-/* Launch shape of the persistent kernel, 0..2 (see the tuner): 0 = 512 threads
- * with the largest column tile per degree within 80 KiB of LDS, 1 = 512
- * threads with FP64 tiles of 8 (mixed 16), 2 = 256 threads with FP64 tiles of 4
- * (mixed 8).  Rebuilds the work table (synchronous copy). */
+/* Launch shape, 0..5 (see the tuner).  0..2: one persistent kernel for every
+ * degree of the batch: 0 = 512 threads, FP64 tiles filling the workgroup
+ * (16 columns up to 5 points per direction, else 8 within 80 KiB of LDS, else
+ * 4; mixed: the largest of 16 / 8 within 80 KiB), 1 = 512 threads with FP64
+ * tiles of 8 (mixed 16), 2 = 256 threads with FP64 tiles of 4 (mixed 8).
+ * 3..5: one kernel per degree present, each with that degree's own tile and
+ * workgroup size: 3 = resident (persistent) grids and 4 = one workgroup per
+ * item, the degrees one after another with the zero fills of the later
+ * degrees overlapped on a side stream; 5 = one workgroup per item, every
+ * degree (its zero fill, then its kernel) on its own side stream so that the
+ * degrees run concurrently.  The items of each launch are cut into one
+ * contiguous range per XCD of equal estimated cost.  Side streams are the
+ * batch's own (default priority), forked from and joined back into the
+ * caller's stream by events, so a call is ordered on that stream as a whole
+ * (also under graph capture).
+ * Rebuilds the work tables (synchronous copies; may reallocate them) and drops
+ * a graph captured with the previous shape (capture again before replaying). */
 int mf_batch_set_launch(mf_batch* b, int cfg);
 
 /* Y_i := A_i X_i for every operator (arrays of nops device pointers in the
- * caller's operator order; ldx / ldy may be NULL for ld = nvec).  Enqueues a
- * counter reset, the zero fill of every Y_i's cell-face rows and the
- * persistent kernel on `stream`; allocates nothing.  Outputs must not overlap
+ * caller's operator order; ldx / ldy may be NULL for ld = nvec).  Enqueues the
+ * zero fill of every Y_i's cell-face rows (a kernel) and the apply kernel(s)
+ * on `stream`; allocates nothing.  Outputs must not overlap
  * each other or any input.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
 int mf_batch_apply(mf_batch* b, const double* const* X, double* const* Y, const int64_t* ldx,
                    const int64_t* ldy, void* stream);

@@ -1,6 +1,9 @@
 // C ABI of the batched apply: a list of operators (uneven meshes, degrees and
-// column counts) applied in one persistent launch, optionally captured once in
-// a HIP graph and replayed.
+// column counts) applied in one persistent launch over cost-balanced per-XCD
+// item ranges, or in one launch per degree, optionally captured once in a HIP
+// graph and replayed.  The per-degree shapes fork work onto the batch's own
+// side streams (default priority) and join it back before returning, so every
+// call is ordered on the caller's stream as a whole.
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -20,9 +23,24 @@ struct Batch {
   std::vector<int> nvec;
   std::vector<int> perm;       // work-list position -> caller index
   BatchOp* d_ops = nullptr;    // in work-list order
-  int* d_counter = nullptr;
-  int64_t total_items = 0, total_lines = 0;
-  int grid[kBatchCfgs] = {0, 0, 0};
+  int64_t* d_bounds = nullptr; // kXcds + 1 item indices: the range of each XCD
+  uint8_t* d_item_op = nullptr;  // operator (work-list index) of every item
+  int64_t item_cap = 0;          // capacity of d_item_op
+  uint8_t* d_plane_op = nullptr;  // operator of every zero-fill node plane
+  // shape 3 (one launch per kind): kinds in work-list order, their per-XCD
+  // bounds (kXcds + 1 each) and grids
+  std::vector<int> kinds;
+  std::vector<int> kone;     // shape 4: one-shot grid of each kind (8 x its longest XCD range)
+  std::vector<int64_t> kplane0, kplanes;  // each kind's zero-fill node planes
+  int64_t* d_kbounds = nullptr;
+  // side streams and events of the per-degree shapes (one per degree that can
+  // occur after the first)
+  hipStream_t side[kBatchMaxP - kBatchMinP + 1] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t joined[kBatchMaxP - kBatchMinP + 1] = {};
+  int kgrid[kBatchMaxP + 1] = {};
+  int64_t total_items = 0, total_planes = 0;
+  int grid[kBatchCfgs] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -32,14 +50,15 @@ static int batch_tile_rt(int prec, int cfg, int p) {
   switch (cfg) {
     case 0: return batch_tile(prec, 0, p + 1, p + 1);
     case 1: return batch_tile(prec, 1, p + 1, p + 1);
-    default: return batch_tile(prec, 2, p + 1, p + 1);
+    case 2: return batch_tile(prec, 2, p + 1, p + 1);
+    default: return batch_tile(prec, 3, p + 1, p + 1);  // shapes 3..5
   }
 }
 
 // Build the device op table for launch shape `cfg` (tiles depend on it).
 static int build_table(Batch* b, int cfg) {
   std::vector<BatchOp> host(b->nops);
-  int64_t items = 0, lines = 0;
+  int64_t items = 0, planes = 0;
   for (int k = 0; k < b->nops; ++k) {
     const int i = b->perm[k];
     const Operator* op = b->ops[i];
@@ -54,17 +73,109 @@ static int build_table(Batch* b, int cfg) {
     d.p = op->p;
     for (int j = 0; j < 3; ++j) d.nodes[j] = (int)op->nodes[j];
     d.item_begin = items;
-    d.line_begin = lines;
+    d.plane_begin = planes;
     d.grid = op->grid;
     items += op->ncells * d.ntiles;
-    lines += op->nodes[1] * op->nodes[2];
+    planes += op->nodes[2];
   }
   if (items >= ((int64_t)1 << 31)) return fail(MF_ERR_UNSUPPORTED, "more than 2^31 work items");
+  // a captured graph holds the previous shape's launches and tables
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  std::vector<uint8_t> item_op(items), plane_op(planes);
+  for (int k = 0; k < b->nops; ++k) {
+    const int64_t n = host[k].ncells * host[k].ntiles;
+    std::fill(item_op.begin() + host[k].item_begin, item_op.begin() + host[k].item_begin + n,
+              (uint8_t)k);
+    const Operator* op = b->ops[b->perm[k]];
+    std::fill(plane_op.begin() + host[k].plane_begin,
+              plane_op.begin() + host[k].plane_begin + op->nodes[2], (uint8_t)k);
+  }
+  if (items > b->item_cap) {
+    if (b->d_item_op) (void)hipFree(b->d_item_op);
+    b->d_item_op = nullptr;
+    b->item_cap = 0;
+    hipError_t e = hipMalloc(&b->d_item_op, items);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (batch item table)");
+    b->item_cap = items;
+  }
+  if (!b->d_plane_op && planes > 0) {
+    hipError_t e = hipMalloc(&b->d_plane_op, planes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (batch plane table)");
+  }
+  // one contiguous item range per XCD, of equal estimated cost (flops of the
+  // sum-factorised cell operator per column times the tile width)
+  std::vector<double> cost(b->nops);
+  double total = 0.0;
+  for (int k = 0; k < b->nops; ++k) {
+    const int n = host[k].p + 1, m = n;  // q = p + 1
+    const double f = 4.0 * (double)(n * n * n * m + n * n * m * m + n * m * m * m) +
+                     12.0 * m * m * m * m + 18.0 * m * m * m;
+    cost[k] = f * batch_tile_rt(b->prec, cfg, host[k].p);
+    total += cost[k] * (double)(host[k].ncells * host[k].ntiles);
+  }
+  int64_t bounds[kXcds + 1];
+  bounds[0] = 0;
+  bounds[kXcds] = items;
+  {
+    int k = 0;
+    double before = 0.0;  // cost of the operators before k
+    for (int x = 1; x < kXcds; ++x) {
+      const double target = total * x / kXcds;
+      while (k < b->nops - 1 &&
+             before + cost[k] * (double)(host[k].ncells * host[k].ntiles) < target) {
+        before += cost[k] * (double)(host[k].ncells * host[k].ntiles);
+        ++k;
+      }
+      int64_t it = host[k].item_begin + (int64_t)((target - before) / cost[k] + 0.5);
+      const int64_t lim = host[k].item_begin + host[k].ncells * host[k].ntiles;
+      if (it > lim) it = lim;
+      if (it < bounds[x - 1]) it = bounds[x - 1];
+      bounds[x] = it;
+    }
+  }
+  // shape 3: each kind's contiguous item range split evenly over the XCDs
+  b->kinds.clear();
+  b->kone.clear();
+  b->kplane0.clear();
+  b->kplanes.clear();
+  std::vector<int64_t> kb;
+  for (int k = 0; k < b->nops;) {
+    const int p = host[k].p;
+    const int64_t beg = host[k].item_begin;
+    int k2 = k;
+    while (k2 < b->nops && host[k2].p == p) ++k2;
+    const int64_t fin = k2 < b->nops ? host[k2].item_begin : items;
+    b->kinds.push_back(p);
+    b->kplane0.push_back(host[k].plane_begin);
+    b->kplanes.push_back((k2 < b->nops ? host[k2].plane_begin : planes) - host[k].plane_begin);
+    int64_t longest = 0;
+    for (int x = 0; x <= kXcds; ++x) {
+      kb.push_back(beg + (fin - beg) * x / kXcds);
+      if (x > 0) longest = std::max(longest, kb.back() - kb[kb.size() - 2]);
+    }
+    b->kone.push_back((int)std::max<int64_t>(kXcds, longest * kXcds));
+    k = k2;
+  }
   hipError_t err = hipMemcpy(b->d_ops, host.data(), host.size() * sizeof(BatchOp),
                              hipMemcpyHostToDevice);
+  if (err == hipSuccess)
+    err = hipMemcpy(b->d_bounds, bounds, sizeof(bounds), hipMemcpyHostToDevice);
+  if (err == hipSuccess && !kb.empty())
+    err = hipMemcpy(b->d_kbounds, kb.data(), kb.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (err == hipSuccess && items > 0)
+    err = hipMemcpy(b->d_item_op, item_op.data(), items, hipMemcpyHostToDevice);
+  if (err == hipSuccess && planes > 0)
+    err = hipMemcpy(b->d_plane_op, plane_op.data(), planes, hipMemcpyHostToDevice);
   if (err != hipSuccess) return hip_fail(err, "hipMemcpy");
   b->total_items = items;
-  b->total_lines = lines;
+  b->total_planes = planes;
   b->cfg = cfg;
   return MF_OK;
 }
@@ -104,12 +215,57 @@ static int fill_ptrs(const Batch* b, const double* const* X, double* const* Y, c
   return MF_OK;
 }
 
+static hipError_t launch_kind(Batch* b, size_t i, const BatchPtrs& p, hipStream_t s) {
+  const bool resident = b->cfg == 3;
+  return launch_batched_kind_any(b->prec, b->kinds[i], resident, b->d_ops, b->d_item_op,
+                                 b->d_kbounds + i * (kXcds + 1), p,
+                                 resident ? b->kgrid[b->kinds[i]] : b->kone[i], s);
+}
+
+static hipError_t zero_kind(Batch* b, size_t i, const BatchPtrs& p, hipStream_t s) {
+  return launch_batch_zero(b->d_ops, b->d_plane_op, p, b->kplane0[i], b->kplanes[i], s);
+}
+
 static int enqueue(Batch* b, const BatchPtrs& p, hipStream_t s) {
-  hipError_t err = launch_reset_counter(b->d_counter, s);
-  if (err == hipSuccess) err = launch_batch_zero(b->d_ops, b->nops, p, b->total_lines, s);
-  if (err == hipSuccess)
-    err = launch_batched(b->prec, b->cfg, b->d_ops, b->nops, b->total_items, b->d_counter, p,
-                         b->grid[b->cfg], s);
+  hipError_t err = hipSuccess;
+  if (b->cfg < 3) {
+    err = launch_batch_zero(b->d_ops, b->d_plane_op, p, 0, b->total_planes, s);
+    if (err == hipSuccess)
+      err = launch_batched(b->prec, b->cfg, b->d_ops, b->d_item_op, b->d_bounds, p,
+                           b->grid[b->cfg], s);
+    if (err != hipSuccess) return hip_fail(err, "batched launch");
+    return MF_OK;
+  }
+  const size_t nk = b->kinds.size();
+  err = hipEventRecord(b->fork, s);
+  if (b->cfg == 5) {
+    // every degree on its own stream: its zero fill, then its kernel; the
+    // degrees run concurrently and fill each other's tails
+    for (size_t i = 1; i < nk && err == hipSuccess; ++i) {
+      err = hipStreamWaitEvent(b->side[i], b->fork, 0);
+      if (err == hipSuccess) err = zero_kind(b, i, p, b->side[i]);
+      if (err == hipSuccess) err = launch_kind(b, i, p, b->side[i]);
+      if (err == hipSuccess) err = hipEventRecord(b->joined[i], b->side[i]);
+    }
+    if (err == hipSuccess) err = zero_kind(b, 0, p, s);
+    if (err == hipSuccess) err = launch_kind(b, 0, p, s);
+  } else {
+    // 3, 4: the degrees one after another on s; the zero fills of the later
+    // degrees run on a side stream while the first degree computes
+    if (err == hipSuccess && nk > 1) err = hipStreamWaitEvent(b->side[0], b->fork, 0);
+    for (size_t i = 1; i < nk && err == hipSuccess; ++i) {
+      err = zero_kind(b, i, p, b->side[0]);
+      if (err == hipSuccess) err = hipEventRecord(b->joined[i], b->side[0]);
+    }
+    if (err == hipSuccess) err = zero_kind(b, 0, p, s);
+    for (size_t i = 0; i < nk && err == hipSuccess; ++i) {
+      if (i > 0) err = hipStreamWaitEvent(s, b->joined[i], 0);
+      if (err == hipSuccess) err = launch_kind(b, i, p, s);
+    }
+  }
+  // join every side stream back into s
+  for (size_t i = 1; i < nk && err == hipSuccess; ++i)
+    err = hipStreamWaitEvent(s, b->joined[i], 0);
   if (err != hipSuccess) return hip_fail(err, "batched launch");
   return MF_OK;
 }
@@ -160,14 +316,31 @@ int mf_batch_create(int nops, mf_operator* const* ops, const int* nvec, int prec
   int cus = 0;
   if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
   if (err == hipSuccess) err = hipMalloc(&b->d_ops, nops * sizeof(BatchOp));
-  if (err == hipSuccess) err = hipMalloc(&b->d_counter, sizeof(int));
+  if (err == hipSuccess) err = hipMalloc(&b->d_bounds, (kXcds + 1) * sizeof(int64_t));
+  if (err == hipSuccess)
+    err = hipMalloc(&b->d_kbounds, (kBatchMaxP - kBatchMinP + 1) * (kXcds + 1) * sizeof(int64_t));
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int i = 0; i <= kBatchMaxP - kBatchMinP && err == hipSuccess; ++i) {
+    err = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&b->joined[i], hipEventDisableTiming);
+  }
   if (err != hipSuccess) {
     mf_batch_destroy(reinterpret_cast<mf_batch*>(b));
     return hip_fail(err, "batch setup");
   }
   for (int c = 0; c < kBatchCfgs; ++c) {
-    const int per_cu = batched_blocks_per_cu(prec, c);
-    b->grid[c] = std::max(1, per_cu) * cus;
+    const int per_cu = c >= 3 ? 1 : batched_blocks_per_cu(prec, c);  // 3..5: per kind, below
+    int g = std::max(1, per_cu) * cus;
+    g -= g % kXcds;
+    b->grid[c] = std::max(g, kXcds);
+  }
+  for (int p = kBatchMinP; p <= kBatchMaxP; ++p) {
+    bool used = false;
+    for (const Operator* op : b->ops) used |= op->p == p;
+    if (!used) continue;
+    int g = std::max(1, batched_kind_blocks_per_cu(prec, p)) * cus;
+    g -= g % kXcds;
+    b->kgrid[p] = std::max(g, kXcds);
   }
   if (int s = build_table(b, 0)) {
     mf_batch_destroy(reinterpret_cast<mf_batch*>(b));
@@ -183,7 +356,15 @@ void mf_batch_destroy(mf_batch* handle) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_ops) (void)hipFree(b->d_ops);
-  if (b->d_counter) (void)hipFree(b->d_counter);
+  if (b->d_bounds) (void)hipFree(b->d_bounds);
+  if (b->d_kbounds) (void)hipFree(b->d_kbounds);
+  if (b->d_item_op) (void)hipFree(b->d_item_op);
+  if (b->d_plane_op) (void)hipFree(b->d_plane_op);
+  for (int i = 0; i <= kBatchMaxP - kBatchMinP; ++i) {
+    if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+    if (b->joined[i]) (void)hipEventDestroy(b->joined[i]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   delete b;
 }
 

@@ -37,52 +37,92 @@ __global__ void zero_shared_rows_kernel(double* __restrict__ Y, int Nx, int Ny, 
   }
 }
 
-// Batched form: one workgroup per node line of any operator of the batch.
-__global__ void batch_zero_kernel(const BatchOp* __restrict__ ops, int nops, BatchPtrs ptrs) {
-  const int64_t g = blockIdx.x;
-  int o = 0;
-  while (o + 1 < nops && ops[o + 1].line_begin <= g) ++o;
+// Batched form: kBatchZeroSplit workgroups per node plane gz of any operator of
+// the batch, each taking a contiguous share of the plane's face rows
+// (per-line workgroups are too small for the batch's small meshes and column
+// counts).  A plane on a cell face (gz a multiple of p) is zeroed whole;
+// otherwise its face rows are enumerated as k = 0 .. n-1: first the lines
+// gy = 0, p, 2p, ... whole, then the rows gx = 0, p, 2p, ... of the other
+// lines.  Lanes take columns in groups of the next power of two >= ncols (up
+// to 64), so a wavefront stores 64 / group rows at a time.
+constexpr int kBatchZeroSplit = 16;
+
+__global__ void batch_zero_kernel(const BatchOp* __restrict__ ops,
+                                  const uint8_t* __restrict__ plane_op, BatchPtrs ptrs,
+                                  int64_t first) {
+  const int64_t g = first + blockIdx.x;
+  const int o = plane_op[g];
   const BatchOp& op = ops[o];
-  const int line = (int)(g - op.line_begin);
+  const int gz = (int)(g - op.plane_begin);
   const int Nx = op.nodes[0], Ny = op.nodes[1], p = op.p;
-  const int gy = line % Ny, gz = line / Ny;
-  const bool full = (gy % p == 0) || (gz % p == 0);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t ld = ptrs.ldy[o];
   const int ncols = ptrs.nvec[o];
-  double* base = ptrs.Y[o] + (int64_t)line * Nx * ld;
-  const int step = full ? 1 : p;
-  for (int gx = wave * step; gx < Nx; gx += nw * step) {
-    double* row = base + (int64_t)gx * ld;
-    for (int c = lane; c < ncols; c += 64) row[c] = 0.0;
+  double* base = ptrs.Y[o] + (int64_t)gz * Nx * Ny * ld;
+  const bool full = p == 1 || gz % p == 0;
+  const int nyf = (Ny + p - 1) / p, nxf = (Nx + p - 1) / p;
+  const int64_t nrows = full ? (int64_t)Nx * Ny : (int64_t)nyf * Nx + (int64_t)(Ny - nyf) * nxf;
+  int lpr = 1;
+  while (lpr < ncols && lpr < 64) lpr *= 2;
+  const int rpw = 64 / lpr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int sub = lane / lpr, c0 = lane % lpr;
+  const int64_t k0 = nrows * blockIdx.y / gridDim.y, k1 = nrows * (blockIdx.y + 1) / gridDim.y;
+  for (int64_t k = k0 + (int64_t)wave * rpw + sub; k < k1; k += (int64_t)nw * rpw) {
+    int64_t row;
+    if (full) {
+      row = k;
+    } else if (k < (int64_t)nyf * Nx) {
+      row = (k / Nx) * p * (int64_t)Nx + k % Nx;
+    } else {
+      const int64_t kk = k - (int64_t)nyf * Nx;
+      const int64_t j = kk / nxf;
+      row = (j + j / (p - 1) + 1) * (int64_t)Nx + (kk % nxf) * p;
+    }
+    double* dst = base + row * ld;
+    for (int c = c0; c < ncols; c += lpr) dst[c] = 0.0;
   }
 }
 
-__global__ void reset_counter_kernel(int* counter) { *counter = 0; }
-
 }  // namespace
 
-hipError_t launch_batch_zero(const BatchOp* ops, int nops, const BatchPtrs& ptrs, int64_t lines,
-                             hipStream_t s) {
-  if (lines < 1) return hipSuccess;
-  hipLaunchKernelGGL(batch_zero_kernel, dim3((unsigned)lines), dim3(256), 0, s, ops, nops, ptrs);
+hipError_t launch_batch_zero(const BatchOp* ops, const uint8_t* plane_op, const BatchPtrs& ptrs,
+                             int64_t first, int64_t planes, hipStream_t s) {
+  if (planes < 1) return hipSuccess;
+  hipLaunchKernelGGL(batch_zero_kernel, dim3((unsigned)planes, kBatchZeroSplit), dim3(256), 0, s,
+                     ops, plane_op, ptrs, first);
   return hipGetLastError();
 }
 
-hipError_t launch_reset_counter(int* counter, hipStream_t s) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
-  return hipGetLastError();
-}
-
-hipError_t launch_batched(int prec, int bcfg, const BatchOp* ops, int nops, int64_t total,
-                          int* counter, const BatchPtrs& ptrs, int grid, hipStream_t s) {
-#define MF_BATCH_CASE(P, C) \
-  if (prec == P && bcfg == C) return launch_batched_kernel<P, C>(ops, nops, total, counter, ptrs, grid, s);
+hipError_t launch_batched(int prec, int bcfg, const BatchOp* ops, const uint8_t* item_op,
+                          const int64_t* bounds, const BatchPtrs& ptrs, int grid, hipStream_t s) {
+#define MF_BATCH_CASE(P, C)                                                                  \
+  if (prec == P && bcfg == C)                                                                \
+    return launch_batched_kernel<P, C>(ops, item_op, bounds, ptrs, grid, s);
   MF_BATCH_CASE(MF_FP64, 0) MF_BATCH_CASE(MF_FP64, 1) MF_BATCH_CASE(MF_FP64, 2)
   MF_BATCH_CASE(MF_FP32_MFMA, 0) MF_BATCH_CASE(MF_FP32_MFMA, 1) MF_BATCH_CASE(MF_FP32_MFMA, 2)
   MF_BATCH_CASE(MF_BF16_MFMA, 0) MF_BATCH_CASE(MF_BF16_MFMA, 1) MF_BATCH_CASE(MF_BF16_MFMA, 2)
 #undef MF_BATCH_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_batched_kind_any(int prec, int p, bool loop, const BatchOp* ops,
+                                   const uint8_t* item_op,
+                                   const int64_t* bounds, const BatchPtrs& ptrs, int grid,
+                                   hipStream_t s) {
+  if (prec == MF_FP64)
+    return launch_batched_kind<MF_FP64>(p, loop, ops, item_op, bounds, ptrs, grid, s);
+  if (prec == MF_FP32_MFMA)
+    return launch_batched_kind<MF_FP32_MFMA>(p, loop, ops, item_op, bounds, ptrs, grid, s);
+  if (prec == MF_BF16_MFMA)
+    return launch_batched_kind<MF_BF16_MFMA>(p, loop, ops, item_op, bounds, ptrs, grid, s);
+  return hipErrorInvalidValue;
+}
+
+int batched_kind_blocks_per_cu(int prec, int p) {
+  if (prec == MF_FP64) return batched_kind_occupancy<MF_FP64>(p);
+  if (prec == MF_FP32_MFMA) return batched_kind_occupancy<MF_FP32_MFMA>(p);
+  if (prec == MF_BF16_MFMA) return batched_kind_occupancy<MF_BF16_MFMA>(p);
+  return 0;
 }
 
 int batched_blocks_per_cu(int prec, int bcfg) {

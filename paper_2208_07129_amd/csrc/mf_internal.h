@@ -15,8 +15,8 @@ constexpr int kMaxP = 10;
 constexpr int kMaxQExtra = 3;  // q in [p+1, p+3]
 constexpr int kBoxCfgs = 10;   // launch shapes of the box-cell kernel
 constexpr int kMixedCfgs = 4;  // launch shapes of the mixed-precision kernel
-constexpr int kBatchCfgs = 3;  // launch shapes of the persistent batched kernel
-constexpr int kMaxBatch = 64;  // operators per batch
+constexpr int kBatchCfgs = 6;  // launch shapes of the batched apply (3..5: one launch per kind)
+constexpr int kMaxBatch = 64;  // operators per batch (operator indices fit in a byte)
 
 // Error reporting: every entry point returns a status and stores a message.
 int fail(int status, const std::string& msg);
@@ -106,7 +106,7 @@ struct BatchOp {
   int64_t item_begin;  // first work item of this operator in the batch's list
   int64_t ncells;
   int ntiles;          // column tiles
-  int64_t line_begin;  // first node line (gy, gz) of this operator in the batch's zero fill
+  int64_t plane_begin;  // first node plane gz of this operator in the batch's zero fill
   GridDesc grid;
   int p;
   int nodes[3];
@@ -119,13 +119,21 @@ struct BatchPtrs {
   int64_t ldy[kMaxBatch];
   int nvec[kMaxBatch];
 };
-hipError_t launch_batched(int prec, int bcfg, const BatchOp* ops, int nops, int64_t total,
-                          int* counter, const BatchPtrs& ptrs, int grid, hipStream_t s);
+// bounds: kXcds + 1 item indices; XCD x runs the items [bounds[x], bounds[x+1]).
+// item_op[item]: index into ops of the operator that owns work item `item`.
+hipError_t launch_batched(int prec, int bcfg, const BatchOp* ops, const uint8_t* item_op,
+                          const int64_t* bounds, const BatchPtrs& ptrs, int grid, hipStream_t s);
 int batched_blocks_per_cu(int prec, int bcfg);
-// Batched shared-row zero fill and counter reset (kernels, graph-capturable).
-hipError_t launch_batch_zero(const BatchOp* ops, int nops, const BatchPtrs& ptrs, int64_t lines,
-                             hipStream_t s);
-hipError_t launch_reset_counter(int* counter, hipStream_t s);
+hipError_t launch_batched_kind_any(int prec, int p, bool loop, const BatchOp* ops,
+                                   const uint8_t* item_op,
+                                   const int64_t* bounds, const BatchPtrs& ptrs, int grid,
+                                   hipStream_t s);
+int batched_kind_blocks_per_cu(int prec, int p);
+// Batched shared-row zero fill (a kernel, graph-capturable) of the node
+// planes [first, first + planes) of the concatenated gz planes of the batch;
+// plane_op[plane]: the operator that owns that plane.
+hipError_t launch_batch_zero(const BatchOp* ops, const uint8_t* plane_op, const BatchPtrs& ptrs,
+                             int64_t first, int64_t planes, hipStream_t s);
 
 // FP64 fused apply; returns hipSuccess or the launch error.
 hipError_t launch_apply_f64(const Operator& op, const ApplyLaunch& a, hipStream_t s);

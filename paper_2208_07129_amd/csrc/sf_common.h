@@ -424,16 +424,36 @@ constexpr BoxCfg mixed_cfg(int np, int nq, int idx) {
 
 // ---------------------------------------------------------------- batches
 // Launch shapes of the persistent batched kernel (kinds q = p + 1, p = 2..8):
-// 0: 512 threads, the largest tile per kind within 80 KiB (FP64 8 or 4,
-//    mixed 16 or 8);  1: 512 threads, FP64 B = 8 / mixed B = 16 for every kind;
+// 0: 512 threads; FP64 tile per kind filling the workgroup's pencil tasks
+//    (nq^2 B up to 512: B = 16 for nq <= 5, 8 up to 80 KiB of LDS, else 4),
+//    mixed the largest of 16 / 8 within 80 KiB;
+// 1: 512 threads, FP64 B = 8 / mixed B = 16 for every kind;
 // 2: 256 threads, FP64 B = 4 / mixed B = 8.
 constexpr int kBatchMinP = 2, kBatchMaxP = 8;
 constexpr int batch_threads(int bcfg) { return bcfg == 2 ? 256 : 512; }
+// Per-kind launches (shape 3): the kind's own default tile and the fewest
+// whole wavefronts covering its pencil tasks (FP64, one column per thread), or
+// the mixed kernel's default shape.
+constexpr BoxCfg batch_kind_shape(int prec, int np, int nq) {
+  if (prec == MF_FP64) {
+    BoxCfg c = box_cfg(np, nq, 0);
+    c.C = 1;
+    c.pers = false;
+    c.NT = (nq * nq * c.B + 63) / 64 * 64;
+    if (c.NT > 1024) c.NT = 1024;
+    return c;
+  }
+  return mixed_cfg(np, nq, 0);
+}
 constexpr int batch_tile(int prec, int bcfg, int np, int nq) {
   const bool f64 = prec == MF_FP64;
+  if (bcfg >= 3) return batch_kind_shape(prec, np, nq).B;
   if (bcfg == 1) return f64 ? 8 : 16;
   if (bcfg == 2) return f64 ? 4 : 8;
-  if (f64) return box_lds_bytes(np, nq, 8) <= 80 * 1024 ? 8 : 4;
+  if (f64) {
+    if (nq * nq * 16 <= 512 && box_lds_bytes(np, nq, 16) <= 80 * 1024) return 16;
+    return box_lds_bytes(np, nq, 8) <= 80 * 1024 ? 8 : 4;
+  }
   return mixed_lds_bytes(np, nq, 16) <= 80 * 1024 ? 16 : 8;
 }
 constexpr size_t batch_lds_bytes(int prec, int bcfg) {
@@ -446,10 +466,18 @@ constexpr size_t batch_lds_bytes(int prec, int bcfg) {
   return m;
 }
 template <int PREC, int BCFG>
-hipError_t launch_batched_kernel(const BatchOp* ops, int nops, int64_t total, int* counter,
+hipError_t launch_batched_kernel(const BatchOp* ops, const uint8_t* item_op, const int64_t* bounds,
                                  const BatchPtrs& ptrs, int grid, hipStream_t s);
 template <int PREC, int BCFG>
 int batched_occupancy();
+// per-kind kernels, p = 2 .. 8: loop = resident grid (shape 3), else one
+// item per workgroup (shape 4)
+template <int PREC>
+hipError_t launch_batched_kind(int p, bool loop, const BatchOp* ops, const uint8_t* item_op,
+                               const int64_t* bounds, const BatchPtrs& ptrs, int grid,
+                               hipStream_t s);
+template <int PREC>
+int batched_kind_occupancy(int p);
 
 template <int P>
 hipError_t launch_apply_f64_p(const Operator& op, const ApplyLaunch& a, hipStream_t s);

@@ -1,4 +1,5 @@
-"""GPU tests of the batched persistent apply and its graph replay.
+"""GPU tests of the batched apply (persistent and per-degree launch shapes, the
+latter forking onto side streams) and its graph replay.
 
 Each batched result must equal the single-operator apply of the same mesh
 (FP64: per-column relative difference <= 1e-12), for every launch shape; a
@@ -48,7 +49,7 @@ def test_batch_equals_single_applies_every_shape(prec, tol):
     Xs = [torch.from_numpy(w.X()).to(dev()) for w in ws]
     ref = [op.apply(X, precision="fp64") for op, X in zip(ops, Xs)]
     b = mfmv.Batch(ops, [w.nvec for w in ws], prec)
-    for cfg in range(3):
+    for cfg in range(mfmv.BATCH_CFGS):
         b.set_launch(cfg)
         Ys = [torch.full_like(X, float("nan")) for X in Xs]
         b.apply(Xs, Ys)
@@ -63,12 +64,16 @@ def test_batch_equals_single_applies_every_shape(prec, tol):
     assert err.max() <= tol
 
 
-def test_batch_graph_replays():
+@pytest.mark.parametrize("prec,tol,cfg", [("fp64", 1e-12, 0), ("fp64", 1e-12, 3),
+                                          ("fp64", 1e-12, 4), ("fp64", 1e-12, 5),
+                                          ("fp32", 1e-6, 5)])
+def test_batch_graph_replays(prec, tol, cfg):
     ws = small_batch(seed=9, count=5)
     ops = [mfmv.Operator.from_workload(w) for w in ws]
     Xs = [torch.from_numpy(w.X()).to(dev()) for w in ws]
     ref = [op.apply(X) for op, X in zip(ops, Xs)]
-    b = mfmv.Batch(ops, [w.nvec for w in ws], "fp64")
+    b = mfmv.Batch(ops, [w.nvec for w in ws], prec)
+    b.set_launch(cfg)
     Ys = [torch.full_like(X, float("nan")) for X in Xs]
     s = torch.cuda.Stream()
     torch.cuda.synchronize()
@@ -80,7 +85,12 @@ def test_batch_graph_replays():
         b.replay(s)
         s.synchronize()
         for Y, R in zip(Ys, ref):
-            assert colrel(Y, R) <= 1e-12, rep
+            assert colrel(Y, R) <= tol, rep
+    # a new launch shape drops the graph captured with the old one
+    b.set_launch((cfg + 1) % mfmv.BATCH_CFGS)
+    with pytest.raises(mfmv.MfError) as e:
+        b.replay(s)
+    assert e.value.status == mfmv.MF_ERR_ARG
 
 
 def test_batch_rejects_unsupported():

@@ -161,6 +161,22 @@ def config4_meshes(count: int = 32) -> List[Workload]:
     return out
 
 
+def small_meshes(count: int = 64) -> List[Workload]:
+    """Batch of small uneven periodic [0,10]^3 meshes (the regime where one launch per
+    operator leaves the GPU mostly idle): n ~ U{2..6}, p ~ U{4,6,8}, q = p+1,
+    nvec ~ U{4,8,16}."""
+    rng = np.random.default_rng(1014)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(2, 7))
+        p = int(rng.choice([4, 6, 8]))
+        nvec = int(rng.choice([4, 8, 16]))
+        m = BoxMesh(n=(n, n, n), lo=(0, 0, 0), hi=(10, 10, 10), bc=BC_PERIODIC)
+        out.append(Workload(f"small{i}-{n}^3-p{p}", m, p, p + 1, 0.5,
+                            gaussian_wells((1014, i)), 0.0, nvec, (1014, 1000 + i)))
+    return out
+
+
 def config5() -> Workload:
     """Periodic [0,10]^3, 20^3 cells, p=6, q=7 (1,728,000 dofs), sigma=0.5, 128 right-hand sides."""
     m = BoxMesh(n=(20, 20, 20), lo=(0, 0, 0), hi=(10, 10, 10), bc=BC_PERIODIC)
