@@ -11,7 +11,8 @@
 //   T  <- det J (V + sigma) o T + sum_s g_s Lf_s T  (eq. helmholtz, eq. mjacobian)
 //   V_e = (N x N x N)^T T;  Y += Q_e^T V_e         (Sec. 3.2.3)
 // Every 1D contraction runs in even-odd form (eo_matvec).  Only two cell
-// buffers live in LDS (the general kernel needs three).
+// buffers live in LDS (the general kernel needs three), and seven stages
+// separated by six barriers cover the whole chain (box_mid).
 //
 // Work split: a tile of B columns is cut into G = B / C groups of C adjacent
 // columns; a task is one (pencil, column group), so a thread applies every
@@ -179,9 +180,19 @@ __device__ __forceinline__ void box_p1(double* __restrict__ bA, BoxGather<NP, B,
   }
 }
 
-// P2 .. P7 (barrier-separated; starts after the barrier that follows P1):
-// N along 1 and 2, the collapsed derivative terms, the mass term and N^T along
-// 2 and 1.  Leaves (NQ,NP,NP) in B.
+// P2 .. P6 (barrier-separated; starts after the barrier that follows P1).
+// The directions of the last forward and the first backward stages are
+// chosen so that each pencil owner applies every operator of its direction at
+// once, one barrier fewer than a stage per operator:
+//   P2  y: N                      A (NQ,NP,NP) -> B (NQ,NQ,NP)
+//   P3  z: T = N t; U = vq o T + g2 Lf_2 T   B -> T in A, U in B (in place)
+//   P4  x: U += g0 Lf_0 T                   A, B -> B (in place)
+//   P5  y: U += g1 Lf_1 T, then N^T         A, B -> B (in place, y extent NP)
+//   P6  z: N^T                              B -> B (in place, z extent NP)
+// B keeps the (NQ,NQ,NQ) strides throughout, so the result is left in B at
+// (q, j, k) -> q + NQ j + NQ^2 k (q < NQ; j, k < NP).  In-place stages are
+// safe because every pencil of a stage has a single owner that reads it whole
+// before writing it.
 template <int NP, int NQ, int B, int C, int NT>
 __device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restrict__ bB,
                                         const double* __restrict__ svq, double g0, double g1,
@@ -192,21 +203,64 @@ __device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restr
   using TK = Tasks<NQ2, G, NT>;
   constexpr int R = TK::R;
 
-  // P2, P3: N along directions 1 and 2 -> T in A (NQ,NQ,NQ).
+  // P2: N along direction 1.
   box_stage<Nf, false, NP, 1, NQ, NP, NP, NQ, B, C, NT>(bA, bB, tid);
   __syncthreads();
-  box_stage<Nf, false, NP, 2, NQ, NQ, NP, NQ, B, C, NT>(bB, bA, tid);
-  __syncthreads();
 
-  // P4: B = g0 Lf_0 T (direction-0 pencils).
+  // P3: direction-2 pencils (a, b): T = N along 2; U = vq o T + g2 Lf_2 T.
+  // (eo_matvec folds its input in place: T is stored and the mass term taken
+  // before Lf_2 consumes it.)
   {
-    double t[R * C][NQ], o[R * C][NQ];
+    double in[R * C][NP], t[R * C][NQ], m[R * C][NQ], l[R * C][NQ];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int w = TK::clamp(tid + k * NT);
       const int g = w % G, pen = w / G;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) lds_get<C>(bA + (pen * NQ + q) * B + g * C, t, k * C, q);
+      for (int i = 0; i < NP; ++i) lds_get<C>(bB + (pen + i * NQ2) * B + g * C, in, k * C, i);
+    }
+    eo_matvec<Nf, NQ, NP, false, NP, R * C>(in, t);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int w = TK::clamp(tid + k * NT);
+      const int g = w % G, pen = w / G;
+      const bool live = TK::live(k, tid + k * NT);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const double sv = svq[pen + q * NQ2];
+#pragma unroll
+        for (int c = 0; c < C; ++c) m[k * C + c][q] = sv * t[k * C + c][q];
+        if (live) lds_put<C>(bA + (pen + q * NQ2) * B + g * C, t, k * C, q);
+      }
+    }
+    eo_matvec<Lf, NQ, NQ, false, NQ, R * C>(t, l);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int w = tid + k * NT;
+      if (!TK::live(k, w)) continue;
+      const int g = w % G, pen = w / G;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) l[k * C + c][q] = fma(g2, l[k * C + c][q], m[k * C + c][q]);
+        lds_put<C>(bB + (pen + q * NQ2) * B + g * C, l, k * C, q);
+      }
+    }
+  }
+  __syncthreads();
+
+  // P4: direction-0 pencils (b, c): U += g0 Lf_0 T.
+  {
+    double t[R * C][NQ], u[R * C][NQ], o[R * C][NQ];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int w = TK::clamp(tid + k * NT);
+      const int g = w % G, pen = w / G;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        lds_get<C>(bA + (pen * NQ + q) * B + g * C, t, k * C, q);
+        lds_get<C>(bB + (pen * NQ + q) * B + g * C, u, k * C, q);
+      }
     }
     eo_matvec<Lf, NQ, NQ, false, NQ, R * C>(t, o);
 #pragma unroll
@@ -217,16 +271,16 @@ __device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restr
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) o[k * C + c][q] *= g0;
+        for (int c = 0; c < C; ++c) o[k * C + c][q] = fma(g0, o[k * C + c][q], u[k * C + c][q]);
         lds_put<C>(bB + (pen * NQ + q) * B + g * C, o, k * C, q);
       }
     }
   }
   __syncthreads();
 
-  // P5: B += g1 Lf_1 T (direction-1 pencils).
+  // P5: direction-1 pencils (a, c): u = U + g1 Lf_1 T, then N^T along 1.
   {
-    double t[R * C][NQ], b[R * C][NQ], o[R * C][NQ];
+    double t[R * C][NQ], u[R * C][NQ], o[R * C][NQ], v[R * C][NP];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int w = TK::clamp(tid + k * NT);
@@ -235,10 +289,15 @@ __device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restr
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         lds_get<C>(bA + (base + q * NQ) * B + g * C, t, k * C, q);
-        lds_get<C>(bB + (base + q * NQ) * B + g * C, b, k * C, q);
+        lds_get<C>(bB + (base + q * NQ) * B + g * C, u, k * C, q);
       }
     }
     eo_matvec<Lf, NQ, NQ, false, NQ, R * C>(t, o);
+#pragma unroll
+    for (int r = 0; r < R * C; ++r)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) u[r][q] = fma(g1, o[r][q], u[r][q]);
+    eo_matvec<Nf, NP, NQ, true, NP, R * C>(u, v);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int w = tid + k * NT;
@@ -246,58 +305,37 @@ __device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restr
       const int g = w % G, pen = w / G;
       const int base = (pen / NQ) * NQ2 + (pen % NQ);
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) o[k * C + c][q] = fma(g1, o[k * C + c][q], b[k * C + c][q]);
-        lds_put<C>(bB + (base + q * NQ) * B + g * C, o, k * C, q);
-      }
+      for (int j = 0; j < NP; ++j) lds_put<C>(bB + (base + j * NQ) * B + g * C, v, k * C, j);
     }
   }
   __syncthreads();
 
-  // P6: direction-2 pencils: u = vq o T + B + g2 Lf_2 T, then N^T along 2;
-  // written into A in place as (NQ,NQ,NP) (each pencil has a single owner).
+  // P6: direction-2 pencils (a, j), a < NQ, j < NP: N^T along 2, in place.
   {
-    double t[R * C][NQ], acc[R * C][NQ], l[R * C][NQ], o[R * C][NP];
+    using TK6 = Tasks<NQ * NP, G, NT>;
+    constexpr int R6 = TK6::R;
+    double u[R6 * C][NQ], v[R6 * C][NP];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int w = TK::clamp(tid + k * NT);
-      const int g = w % G, pen = w / G;
+    for (int k = 0; k < R6; ++k) {
+      const int w = TK6::clamp(tid + k * NT);
+      const int g = w % G, pen = w / G;  // pen = a + NQ j
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        lds_get<C>(bA + (pen + q * NQ2) * B + g * C, t, k * C, q);
-        lds_get<C>(bB + (pen + q * NQ2) * B + g * C, acc, k * C, q);
-      }
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const double sv = svq[pen + q * NQ2];
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc[k * C + c][q] = fma(sv, t[k * C + c][q], acc[k * C + c][q]);
-      }
+      for (int c = 0; c < NQ; ++c) lds_get<C>(bB + (pen + c * NQ2) * B + g * C, u, k * C, c);
     }
-    eo_matvec<Lf, NQ, NQ, false, NQ, R * C>(t, l);
+    eo_matvec<Nf, NP, NQ, true, NP, R6 * C>(u, v);
 #pragma unroll
-    for (int r = 0; r < R * C; ++r)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) acc[r][q] = fma(g2, l[r][q], acc[r][q]);
-    eo_matvec<Nf, NP, NQ, true, NP, R * C>(acc, o);
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
+    for (int k = 0; k < R6; ++k) {
       const int w = tid + k * NT;
-      if (!TK::live(k, w)) continue;
+      if (!TK6::live(k, w)) continue;
       const int g = w % G, pen = w / G;
 #pragma unroll
-      for (int i = 0; i < NP; ++i) lds_put<C>(bA + (pen + i * NQ2) * B + g * C, o, k * C, i);
+      for (int i = 0; i < NP; ++i) lds_put<C>(bB + (pen + i * NQ2) * B + g * C, v, k * C, i);
     }
   }
-  __syncthreads();
-
-  // P7: N^T along direction 1: A (NQ,NQ,NP) -> B (NQ,NP,NP).
-  box_stage<Nf, true, NP, 1, NQ, NQ, NP, NP, B, C, NT>(bA, bB, tid);
   __syncthreads();
 }
 
-// P8: N^T along direction 0 and the assembly of this thread's pencils.
+// P7: N^T along direction 0 and the assembly of this thread's pencils.
 template <int NP, int NQ, int B, int C, int NT, bool ACCUM>
 __device__ __forceinline__ void box_p8(const double* __restrict__ bB,
                                        const BoxGather<NP, B, C, NT>& Gt, double* __restrict__ Y,
@@ -309,8 +347,9 @@ __device__ __forceinline__ void box_p8(const double* __restrict__ bB,
   for (int k = 0; k < R1; ++k) {
     const int w = GT::TK::clamp(tid + k * NT);
     const int g = w % G, pen = w / G;
+    const int base = ((pen % NP) + NQ * (pen / NP)) * NQ;  // (j, k) in the NQ-strided layout
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) lds_get<C>(bB + (pen * NQ + q) * B + g * C, t, k * C, q);
+    for (int q = 0; q < NQ; ++q) lds_get<C>(bB + (base + q) * B + g * C, t, k * C, q);
   }
   eo_matvec<MatN<NP, NQ>, NP, NQ, true, NP, R1 * C>(t, o);
 #pragma unroll
@@ -407,9 +446,9 @@ __device__ __forceinline__ void box_items(double* __restrict__ lds, const GridDe
     }
     if (nx >= end) break;
     it = nx;
-    // no barrier here: the next P1 writes A and svq, whose last readers (P6,
-    // P7) are behind barriers; B is rewritten only after the barrier that
-    // follows the next P1, when every thread has finished this P8.
+    // no barrier here: the next P1 writes A and svq, whose last readers (P5,
+    // P3) are behind barriers; B is rewritten only after the barrier that
+    // follows the next P1, when every thread has finished this P7.
   }
 }
 
