@@ -139,11 +139,12 @@ int mf_operator_info(const mf_operator* op, int64_t* ndofs, int64_t* ncells, int
  *   Y: device, ndofs rows, row stride ldy >= nvec; constrained rows are
  *      written as zero (the action of C^T).  Y must not overlap X.
  *   prec: MF_FP64 evaluates every step in FP64 (FP64 atomic assembly).
- *         MF_FP32_MFMA / MF_BF16_MFMA: the sum-factorised contractions run on
- *         the matrix cores (FP32 operands, or BF16 operands; FP32
- *         accumulation), cell arrays are FP32, and each (cell, column) is
- *         scaled by a power of two before the conversion and unscaled before
- *         the FP64 assembly.  Built for axis-aligned cells only.
+ *         MF_FP32_MFMA / MF_BF16_MFMA: cell arrays are FP32 and each (cell,
+ *         column) is scaled by a power of two before the conversion and
+ *         unscaled before the FP64 assembly; the sum-factorised contractions
+ *         run on the matrix cores (FP32 or BF16 operands, FP32 accumulation)
+ *         or, for FP32 by default, as FP32 vector even-odd contractions (see
+ *         mf_set_launch_mixed).  Built for axis-aligned cells only.
  * Stream-ordered on `stream`; allocates nothing, does not synchronise.
  * Errors: MF_ERR_ARG (null, nvec < 1, ld < nvec, overlap), MF_ERR_UNSUPPORTED
  * (precision not available for this p, q), MF_ERR_HIP (launch failure). */
@@ -176,8 +177,18 @@ int mf_zero(double* Y, int64_t nrows, int ncols, int64_t ld, void* stream);
  * not fit the LDS for this p, q). */
 int mf_set_launch(mf_operator* op, int general, int cfg);
 
-/* Launch shape of the mixed-precision kernel, 0..3, or -1 for the built-in
- * choice by column count.  Errors as mf_set_launch. */
+/* Launch shape of the mixed-precision apply, 0..6, or -1 for the built-in
+ * choice (by precision and column count).  0..3: matrix-core kernels (FP32 or
+ * BF16 operands by the call's precision): 0 = 16 columns and 512 threads (8
+ * columns if 16 exceed 80 KiB of LDS), 1 = 16 / 256, 2 = 8 / 256, 3 = 8 / 512.
+ * 4..6: FP32 vector kernels (the even-odd contractions of the FP64 box kernel
+ * on FP32 cell arrays, the same per-(cell, column) power-of-two scaling):
+ * 4 = 16 columns, two per thread (16-byte accesses; odd nvec, odd ldx or ldy
+ * or unaligned X or Y run shape 5 instead), 5 = 8 columns, 6 = 16 columns,
+ * each with the fewest whole wavefronts covering the pencil tasks.  A BF16
+ * call with a shape of 4..6 runs matrix-core shape 0.  The built-in choice for
+ * FP32 is shape 6 (nvec > 8, where it fits 1024 threads) or 5.  Errors as
+ * mf_set_launch. */
 int mf_set_launch_mixed(mf_operator* op, int cfg);
 
 /* Per-launch timing for diagnostics and benchmarks.  mf_timing(op, slots)

@@ -96,11 +96,17 @@ template <int NP, int PREC>
 struct KindShape {
   static constexpr BoxCfg c = batch_kind_shape(PREC, NP, NP);
   static constexpr int B = c.B, NT = c.NT;
-  static constexpr size_t LDS = PREC == MF_FP64 ? box_lds_bytes(NP, NP, B) : mixed_lds_bytes(NP, NP, B);
+  // FP64 and FP32 run the box body (double / float cell arrays), BF16 the
+  // matrix-core body
+  static constexpr bool BOX = PREC != MF_BF16_MFMA;
+  static constexpr size_t LDS = PREC == MF_FP64        ? box_lds_bytes(NP, NP, B)
+                                : PREC == MF_FP32_MFMA ? box_lds_bytes_t<float>(NP, NP, B)
+                                                       : mixed_lds_bytes(NP, NP, B);
   static constexpr int WG = (int)(kLdsMax / LDS) < 1 ? 1 : (int)(kLdsMax / LDS);
   static constexpr int W0 = (WG * (NT / 64) + 3) / 4;
-  // FP64: the LDS-limited occupancy; mixed: no budget (see batch_waves_per_eu)
-  static constexpr int WAVES = PREC != MF_FP64 ? 1 : (W0 < 1 ? 1 : (W0 > 8 ? 8 : W0));
+  // box bodies: the LDS-limited occupancy; matrix-core body: no budget (see
+  // batch_waves_per_eu)
+  static constexpr int WAVES = !BOX ? 1 : (W0 < 1 ? 1 : (W0 > 8 ? 8 : W0));
 };
 
 template <int NP, int PREC>
@@ -112,6 +118,10 @@ __device__ __forceinline__ void kind_item(double* lds, const BatchOp& op, const 
   if constexpr (PREC == MF_FP64)
     box_cell_tile<NP, NP, B, 1, NT, false>(lds, op.grid, op.geo, op.vq, ptrs.X[o], ptrs.Y[o],
                                            ptrs.ldx[o], ptrs.ldy[o], ptrs.nvec[o], e, v0);
+  else if constexpr (PREC == MF_FP32_MFMA)
+    box_cell_tile<NP, NP, B, 1, NT, false, float>(reinterpret_cast<float*>(lds), op.grid, op.geo,
+                                                  op.vq, ptrs.X[o], ptrs.Y[o], ptrs.ldx[o],
+                                                  ptrs.ldy[o], ptrs.nvec[o], e, v0);
   else
     mixed_cell_tile<NP, NP, B, NT, false, PREC>(lds, op.map, op.geo, op.vq, ptrs.X[o], ptrs.Y[o],
                                                 ptrs.ldx[o], ptrs.ldy[o], ptrs.nvec[o], e, v0);

@@ -24,6 +24,8 @@
 // (their rows are zeroed beforehand).
 #pragma once
 
+#include <type_traits>
+
 #include "mf_internal.h"
 #include "sf_common.h"
 #include "sf_tables.h"
@@ -32,25 +34,39 @@ namespace mf {
 
 // C adjacent columns of one LDS point <-> rows row .. row+C-1 of a register
 // block d[RN][N] at entry i.
-template <int C, int RN, int N>
-__device__ __forceinline__ void lds_get(const double* __restrict__ p, double (&d)[RN][N], int row,
-                                        int i) {
+// T is the arithmetic type of the cell arrays: double (the FP64 apply) or
+// float (the FP32 vector apply; X and Y stay FP64 in HBM).
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+
+template <int C, int RN, int N, typename T>
+__device__ __forceinline__ void lds_get(const T* __restrict__ p, T (&d)[RN][N], int row, int i) {
   if constexpr (C == 1) {
     d[row][i] = p[0];
   } else {
     static_assert(C == 2, "C is 1 or 2");
-    const double2 v = *reinterpret_cast<const double2*>(p);
+    const auto v = *reinterpret_cast<const typename Pair<T>::type*>(p);
     d[row][i] = v.x;
     d[row + 1][i] = v.y;
   }
 }
-template <int C, int RN, int N>
-__device__ __forceinline__ void lds_put(double* __restrict__ p, const double (&s)[RN][N], int row,
-                                        int i) {
+template <int C, int RN, int N, typename T>
+__device__ __forceinline__ void lds_put(T* __restrict__ p, const T (&s)[RN][N], int row, int i) {
   if constexpr (C == 1) {
     p[0] = s[row][i];
   } else {
-    *reinterpret_cast<double2*>(p) = make_double2(s[row][i], s[row + 1][i]);
+    typename Pair<T>::type v;
+    v.x = s[row][i];
+    v.y = s[row + 1][i];
+    *reinterpret_cast<typename Pair<T>::type*>(p) = v;
   }
 }
 
@@ -70,14 +86,14 @@ struct Tasks {
 // (extents S0, S1, S2), in place allowed when src and dst are one buffer and
 // every pencil keeps its positions (each pencil has a single owner).
 template <class Mat, bool TR, int LD, int DIR, int S0, int S1, int S2, int NOUT, int B, int C,
-          int NT>
-__device__ __forceinline__ void box_stage(const double* src, double* dst, int tid) {
+          int NT, typename T>
+__device__ __forceinline__ void box_stage(const T* src, T* dst, int tid) {
   using PI = Pencils<DIR, S0, S1, S2>;
   using PO = Pencils<DIR, DIR == 0 ? NOUT : S0, DIR == 1 ? NOUT : S1, DIR == 2 ? NOUT : S2>;
   constexpr int NIN = PI::L, G = B / C;
   using TK = Tasks<PI::COUNT, G, NT>;
   constexpr int R = TK::R;
-  double in[R * C][NIN], out[R * C][NOUT];
+  T in[R * C][NIN], out[R * C][NOUT];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int w = TK::clamp(tid + k * NT);
@@ -101,14 +117,23 @@ __device__ __forceinline__ void box_stage(const double* src, double* dst, int ti
 // node numbers of the pencil (-1 for a constrained node) and the gathered X
 // values of its C columns.  The same thread owns the same tasks in the last
 // phase, so the node numbers also drive the assembly.
-template <int NP, int B, int C, int NT>
+//
+// With FP32 cell arrays (T = float) every (cell, column) is scaled by a power
+// of two 2^-e before the conversion, e the exponent of the column's largest
+// gathered magnitude, and the assembly multiplies by 2^e again: the FP32
+// stages then see values below 1 whatever the magnitude of X (scaling by a
+// power of two is exact).
+template <int NP, int B, int C, int NT, typename T = double>
 struct BoxGather {
   static constexpr int G = B / C;
   using TK = Tasks<NP * NP, G, NT>;
   static constexpr int T1 = TK::T;
   static constexpr int R1 = TK::R;
+  static constexpr bool F32 = std::is_same<T, float>::value;
   int node[R1][NP];
-  double x[R1 * C][NP];
+  double x[R1 * C][NP];                 // gathered FP64 values
+  T xs[F32 ? R1 * C : 1][NP];           // scaled FP32 values (T = float)
+  int ex[F32 ? R1 * C : 1];             // column exponents e (T = float)
 
   // Node numbers from the structured-grid arithmetic: cell e at (cx, cy, cz),
   // local node (i1, i2, i3) -> grid node (cx p + i1, ...) with the periodic
@@ -160,16 +185,54 @@ struct BoxGather {
       }
     }
   }
+  // T = float: the column exponents (a max-reduction over the lanes of equal
+  // column group, then over the wavefronts through `scratch`, NT / 64 * B
+  // ints of LDS not otherwise in use before the next barrier) and the scaled
+  // FP32 values.  Every thread of the workgroup must call it (one barrier).
+  __device__ __forceinline__ void scale(int* __restrict__ scratch, int tid) {
+    static_assert(F32 && R1 == 1 && 64 % G == 0, "one task per thread, G divides 64");
+    constexpr int kNone = -100000;
+    int e[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      double m = 0.0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) m = fmax(m, fabs(x[c][i]));
+      int em = kNone;
+      if (m > 0.0) (void)frexp(m, &em);
+#pragma unroll
+      for (int off = G; off < 64; off *= 2) em = max(em, __shfl_xor(em, off));
+      e[c] = em;
+    }
+    const int lane = tid & 63, wave = tid >> 6, g = tid % G;
+    if (lane < G) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) scratch[wave * B + g * C + c] = e[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      int em = kNone;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) em = max(em, scratch[w * B + g * C + c]);
+      ex[c] = em == kNone ? 0 : em;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) xs[c][i] = (T)ldexp(x[c][i], -ex[c]);
+    }
+  }
 };
 
 // P1: N along direction 0 from the gathered registers (consumed) -> A (NQ,NP,NP).
-template <int NP, int NQ, int B, int C, int NT>
-__device__ __forceinline__ void box_p1(double* __restrict__ bA, BoxGather<NP, B, C, NT>& Gt,
+template <int NP, int NQ, int B, int C, int NT, typename T = double>
+__device__ __forceinline__ void box_p1(T* __restrict__ bA, BoxGather<NP, B, C, NT, T>& Gt,
                                        int tid) {
-  using GT = BoxGather<NP, B, C, NT>;
+  using GT = BoxGather<NP, B, C, NT, T>;
   constexpr int R1 = GT::R1, G = GT::G;
-  double o[R1 * C][NQ];
-  eo_matvec<MatN<NP, NQ>, NQ, NP, false, NP, R1 * C>(Gt.x, o);
+  T o[R1 * C][NQ];
+  if constexpr (GT::F32)
+    eo_matvec<MatN<NP, NQ>, NQ, NP, false, NP, R1 * C>(Gt.xs, o);
+  else
+    eo_matvec<MatN<NP, NQ>, NQ, NP, false, NP, R1 * C>(Gt.x, o);
 #pragma unroll
   for (int k = 0; k < R1; ++k) {
     const int w = tid + k * NT;
@@ -193,10 +256,9 @@ __device__ __forceinline__ void box_p1(double* __restrict__ bA, BoxGather<NP, B,
 // (q, j, k) -> q + NQ j + NQ^2 k (q < NQ; j, k < NP).  In-place stages are
 // safe because every pencil of a stage has a single owner that reads it whole
 // before writing it.
-template <int NP, int NQ, int B, int C, int NT>
-__device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restrict__ bB,
-                                        const double* __restrict__ svq, double g0, double g1,
-                                        double g2, int tid) {
+template <int NP, int NQ, int B, int C, int NT, typename T = double>
+__device__ __forceinline__ void box_mid(T* __restrict__ bA, T* __restrict__ bB,
+                                        const T* __restrict__ svq, T g0, T g1, T g2, int tid) {
   constexpr int NQ2 = NQ * NQ, G = B / C;
   using Nf = MatN<NP, NQ>;
   using Lf = MatL<NP, NQ>;
@@ -204,14 +266,14 @@ __device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restr
   constexpr int R = TK::R;
 
   // P2: N along direction 1.
-  box_stage<Nf, false, NP, 1, NQ, NP, NP, NQ, B, C, NT>(bA, bB, tid);
+  box_stage<Nf, false, NP, 1, NQ, NP, NP, NQ, B, C, NT, T>(bA, bB, tid);
   __syncthreads();
 
   // P3: direction-2 pencils (a, b): T = N along 2; U = vq o T + g2 Lf_2 T.
   // (eo_matvec folds its input in place: T is stored and the mass term taken
   // before Lf_2 consumes it.)
   {
-    double in[R * C][NP], t[R * C][NQ], m[R * C][NQ], l[R * C][NQ];
+    T in[R * C][NP], t[R * C][NQ], m[R * C][NQ], l[R * C][NQ];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int w = TK::clamp(tid + k * NT);
@@ -227,7 +289,7 @@ __device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restr
       const bool live = TK::live(k, tid + k * NT);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const double sv = svq[pen + q * NQ2];
+        const T sv = svq[pen + q * NQ2];
 #pragma unroll
         for (int c = 0; c < C; ++c) m[k * C + c][q] = sv * t[k * C + c][q];
         if (live) lds_put<C>(bA + (pen + q * NQ2) * B + g * C, t, k * C, q);
@@ -251,7 +313,7 @@ __device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restr
 
   // P4: direction-0 pencils (b, c): U += g0 Lf_0 T.
   {
-    double t[R * C][NQ], u[R * C][NQ], o[R * C][NQ];
+    T t[R * C][NQ], u[R * C][NQ], o[R * C][NQ];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int w = TK::clamp(tid + k * NT);
@@ -280,7 +342,7 @@ __device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restr
 
   // P5: direction-1 pencils (a, c): u = U + g1 Lf_1 T, then N^T along 1.
   {
-    double t[R * C][NQ], u[R * C][NQ], o[R * C][NQ], v[R * C][NP];
+    T t[R * C][NQ], u[R * C][NQ], o[R * C][NQ], v[R * C][NP];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int w = TK::clamp(tid + k * NT);
@@ -314,7 +376,7 @@ __device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restr
   {
     using TK6 = Tasks<NQ * NP, G, NT>;
     constexpr int R6 = TK6::R;
-    double u[R6 * C][NQ], v[R6 * C][NP];
+    T u[R6 * C][NQ], v[R6 * C][NP];
 #pragma unroll
     for (int k = 0; k < R6; ++k) {
       const int w = TK6::clamp(tid + k * NT);
@@ -336,13 +398,13 @@ __device__ __forceinline__ void box_mid(double* __restrict__ bA, double* __restr
 }
 
 // P7: N^T along direction 0 and the assembly of this thread's pencils.
-template <int NP, int NQ, int B, int C, int NT, bool ACCUM>
-__device__ __forceinline__ void box_p8(const double* __restrict__ bB,
-                                       const BoxGather<NP, B, C, NT>& Gt, double* __restrict__ Y,
+template <int NP, int NQ, int B, int C, int NT, bool ACCUM, typename T = double>
+__device__ __forceinline__ void box_p8(const T* __restrict__ bB,
+                                       const BoxGather<NP, B, C, NT, T>& Gt, double* __restrict__ Y,
                                        int64_t ldy, int nvec, int v0, int tid) {
-  using GT = BoxGather<NP, B, C, NT>;
+  using GT = BoxGather<NP, B, C, NT, T>;
   constexpr int R1 = GT::R1, G = GT::G;
-  double t[R1 * C][NQ], o[R1 * C][NP];
+  T t[R1 * C][NQ], o[R1 * C][NP];
 #pragma unroll
   for (int k = 0; k < R1; ++k) {
     const int w = GT::TK::clamp(tid + k * NT);
@@ -359,6 +421,12 @@ __device__ __forceinline__ void box_p8(const double* __restrict__ bB,
     if (w >= GT::T1 || v >= nvec) continue;
     const int i2 = pen % NP, i3 = pen / NP;
     const bool inner_pen = i2 > 0 && i2 < NP - 1 && i3 > 0 && i3 < NP - 1;
+    double sc[C];  // undoes the column scaling of FP32 cell arrays
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if constexpr (GT::F32) sc[c] = ldexp(1.0, Gt.ex[c]);
+      else sc[c] = 1.0;
+    }
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
       const int node = Gt.node[k][i];
@@ -366,11 +434,11 @@ __device__ __forceinline__ void box_p8(const double* __restrict__ bB,
       double* dst = Y + (int64_t)node * ldy + v;
       if (i > 0 && i < NP - 1 && inner_pen) {
         if constexpr (C == 1) {
-          if (ACCUM) *dst += o[k][i];
-          else *dst = o[k][i];
+          if (ACCUM) *dst += (double)o[k][i] * sc[0];
+          else *dst = (double)o[k][i] * sc[0];
         } else {
           double2* d2 = reinterpret_cast<double2*>(dst);
-          double2 val = make_double2(o[2 * k][i], o[2 * k + 1][i]);
+          double2 val = make_double2((double)o[2 * k][i] * sc[0], (double)o[2 * k + 1][i] * sc[1]);
           if (ACCUM) {
             const double2 old = *d2;
             val.x += old.x;
@@ -380,7 +448,7 @@ __device__ __forceinline__ void box_p8(const double* __restrict__ bB,
         }
       } else {
 #pragma unroll
-        for (int c = 0; c < C; ++c) unsafeAtomicAdd(dst + c, o[k * C + c][i]);
+        for (int c = 0; c < C; ++c) unsafeAtomicAdd(dst + c, (double)o[k * C + c][i] * sc[c]);
       }
     }
   }
@@ -392,30 +460,31 @@ __device__ __forceinline__ void box_p8(const double* __restrict__ bB,
 // item i runs its contractions, so the extraction latency hides behind
 // arithmetic instead of idling the workgroup; node numbers are recomputed from
 // the grid for the assembly rather than held through the contractions.
-template <int NP, int NQ, int B, int C, int NT, bool ACCUM>
-__device__ __forceinline__ void box_items(double* __restrict__ lds, const GridDesc& grid,
+template <int NP, int NQ, int B, int C, int NT, bool ACCUM, typename T = double>
+__device__ __forceinline__ void box_items(T* __restrict__ lds, const GridDesc& grid,
                                           const int32_t* __restrict__ order,
                                           const double* __restrict__ geo,
                                           const double* __restrict__ vq,
                                           const double* __restrict__ X, double* __restrict__ Y,
                                           int64_t ldx, int64_t ldy, int nvec, int ntiles,
                                           int64_t it, int64_t end, int64_t W) {
+  static_assert(std::is_same<T, double>::value, "the persistent form is built for FP64 only");
   constexpr int NQ3 = NQ * NQ * NQ;
   constexpr int RV = (NQ3 + NT - 1) / NT;
-  double* bA = lds;
-  double* bB = bA + NQ3 * B;
-  double* svq = bB + NQ3 * B;
+  T* bA = lds;
+  T* bB = bA + NQ3 * B;
+  T* svq = bB + NQ3 * B;
   const int tid = threadIdx.x;
   if (it >= end) return;
-  auto load_vq = [&](int64_t e, double (&r)[RV]) {
+  auto load_vq = [&](int64_t e, T (&r)[RV]) {
 #pragma unroll
     for (int k = 0; k < RV; ++k) {
       const int i = tid + k * NT;
-      r[k] = vq[e * NQ3 + (i < NQ3 ? i : 0)];
+      r[k] = (T)vq[e * NQ3 + (i < NQ3 ? i : 0)];
     }
   };
-  BoxGather<NP, B, C, NT> cur;
-  double vqc[RV];
+  BoxGather<NP, B, C, NT, T> cur;
+  T vqc[RV];
   {
     const int64_t e = order[it / ntiles];
     cur.load_grid(grid, e, tid);
@@ -425,11 +494,11 @@ __device__ __forceinline__ void box_items(double* __restrict__ lds, const GridDe
   for (;;) {
     const int64_t e = order[it / ntiles];
     const int v0 = (int)(it % ntiles) * B;
-    const double g0 = geo[e * 6 + 0], g1 = geo[e * 6 + 3], g2 = geo[e * 6 + 5];
+    const T g0 = (T)geo[e * 6 + 0], g1 = (T)geo[e * 6 + 3], g2 = (T)geo[e * 6 + 5];
 #pragma unroll
     for (int k = 0; k < RV; ++k)
       if (RV * NT == NQ3 || tid + k * NT < NQ3) svq[tid + k * NT] = vqc[k];
-    box_p1<NP, NQ, B, C, NT>(bA, cur, tid);
+    box_p1<NP, NQ, B, C, NT, T>(bA, cur, tid);
     const int64_t nx = it + W;
     if (nx < end) {  // prefetch the next item into the registers P1 just freed
       const int64_t en = order[nx / ntiles];
@@ -438,11 +507,11 @@ __device__ __forceinline__ void box_items(double* __restrict__ lds, const GridDe
       load_vq(en, vqc);
     }
     __syncthreads();
-    box_mid<NP, NQ, B, C, NT>(bA, bB, svq, g0, g1, g2, tid);
+    box_mid<NP, NQ, B, C, NT, T>(bA, bB, svq, g0, g1, g2, tid);
     {
-      BoxGather<NP, B, C, NT> here;  // node numbers only (x unused)
+      BoxGather<NP, B, C, NT, T> here;  // node numbers only (x unused)
       here.load_grid(grid, e, tid);
-      box_p8<NP, NQ, B, C, NT, ACCUM>(bB, here, Y, ldy, nvec, v0, tid);
+      box_p8<NP, NQ, B, C, NT, ACCUM, T>(bB, here, Y, ldy, nvec, v0, tid);
     }
     if (nx >= end) break;
     it = nx;
@@ -453,29 +522,31 @@ __device__ __forceinline__ void box_items(double* __restrict__ lds, const GridDe
 }
 
 // One (cell e, columns v0 .. v0+B-1) work item.  `lds` holds
-// box_lds_bytes(NP, NQ, B) bytes; the caller synchronises the workgroup
+// box_lds_bytes_t<T>(NP, NQ, B) bytes; the caller synchronises the workgroup
 // before reusing it for another item.
-template <int NP, int NQ, int B, int C, int NT, bool ACCUM>
-__device__ __forceinline__ void box_cell_tile(double* __restrict__ lds, const GridDesc& grid,
+template <int NP, int NQ, int B, int C, int NT, bool ACCUM, typename T = double>
+__device__ __forceinline__ void box_cell_tile(T* __restrict__ lds, const GridDesc& grid,
                                               const double* __restrict__ geo,
                                               const double* __restrict__ vq,
                                               const double* __restrict__ X, double* __restrict__ Y,
                                               int64_t ldx, int64_t ldy, int nvec, int64_t e,
                                               int v0) {
   constexpr int NQ3 = NQ * NQ * NQ;
-  double* bA = lds;
-  double* bB = bA + NQ3 * B;
-  double* svq = bB + NQ3 * B;
+  T* bA = lds;
+  T* bB = bA + NQ3 * B;
+  T* svq = bB + NQ3 * B;
   const int tid = threadIdx.x;
-  BoxGather<NP, B, C, NT> Gt;
+  BoxGather<NP, B, C, NT, T> Gt;
   Gt.load_grid(grid, e, tid);
-  for (int i = tid; i < NQ3; i += NT) svq[i] = vq[e * NQ3 + i];
-  const double g0 = geo[e * 6 + 0], g1 = geo[e * 6 + 3], g2 = geo[e * 6 + 5];
+  for (int i = tid; i < NQ3; i += NT) svq[i] = (T)vq[e * NQ3 + i];
+  const T g0 = (T)geo[e * 6 + 0], g1 = (T)geo[e * 6 + 3], g2 = (T)geo[e * 6 + 5];
   Gt.load_x(X, ldx, nvec, v0, tid);
-  box_p1<NP, NQ, B, C, NT>(bA, Gt, tid);
+  if constexpr (std::is_same<T, float>::value)
+    Gt.scale(reinterpret_cast<int*>(bB), tid);  // B is first written in P2
+  box_p1<NP, NQ, B, C, NT, T>(bA, Gt, tid);
   __syncthreads();
-  box_mid<NP, NQ, B, C, NT>(bA, bB, svq, g0, g1, g2, tid);
-  box_p8<NP, NQ, B, C, NT, ACCUM>(bB, Gt, Y, ldy, nvec, v0, tid);
+  box_mid<NP, NQ, B, C, NT, T>(bA, bB, svq, g0, g1, g2, tid);
+  box_p8<NP, NQ, B, C, NT, ACCUM, T>(bB, Gt, Y, ldy, nvec, v0, tid);
 }
 
 }  // namespace mf

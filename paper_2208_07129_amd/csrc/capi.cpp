@@ -329,9 +329,11 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
   a.threads = 256;
   a.vtile = choose_vtile_f64(op->np, op->nq, nvec);
   if (mixed)
-    a.cfg = op->mcfg >= 0 ? op->mcfg : choose_cfg_mixed(op->np, op->nq, nvec);
+    a.cfg = op->mcfg >= 0 ? op->mcfg : choose_cfg_mixed(op->np, op->nq, nvec, prec);
   else
     a.cfg = op->cfg >= 0 ? op->cfg : choose_cfg_box(op->np, op->nq, nvec);
+  if (mixed && a.cfg >= kMixedMfmaCfgs && !box_pairs_ok(X, Y, nvec, ldx, ldy))
+    a.cfg = vec32_cfg_single(a.cfg);
   if (!mixed && op->box && !box_pairs_ok(X, Y, nvec, ldx, ldy))
     a.cfg = box_cfg_single(op->np, op->nq, a.cfg);
   a.accumulate = accumulate;

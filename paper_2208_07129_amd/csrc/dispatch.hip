@@ -168,14 +168,22 @@ int choose_cfg_box(int np, int nq, int nvec) {
 bool apply_mixed_supported(int p, int q, int cfg) {
   if (p < 1 || p > kMaxP || q < p + 1 || q > p + kMaxQExtra || cfg < 0 || cfg >= kMixedCfgs)
     return false;
+  if (cfg >= kMixedMfmaCfgs) return vec32_cfg(p + 1, q, cfg).B > 0;
   return mixed_cfg(p + 1, q, cfg).B > 0;
 }
 
-int choose_cfg_mixed(int np, int nq, int nvec) {
+int choose_cfg_mixed(int np, int nq, int nvec, int prec) {
+  if (prec == MF_FP32_MFMA) {
+    // FP32: the vector shapes measured fastest (p = 6: 0.42 vs 0.50 ms for the
+    // matrix-core shape at nvec 64; p = 8: 0.42 vs 0.61 ms): 16 columns, one per
+    // thread, where the workgroup fits, else 8; 8 for narrow multivectors.
+    if (nvec > 8 && vec32_cfg(np, nq, 6).B > 0) return 6;
+    if (vec32_cfg(np, nq, 5).B > 0) return 5;
+  }
   const int b0 = mixed_cfg(np, nq, 0).B;
   if (nvec >= b0) return 0;
   int best = 0, bestB = b0;
-  for (int c = 1; c < kMixedCfgs; ++c) {
+  for (int c = 1; c < kMixedMfmaCfgs; ++c) {
     const int b = mixed_cfg(np, nq, c).B;
     if (b >= nvec && b < bestB) {
       best = c;

@@ -14,7 +14,7 @@ namespace mf {
 constexpr int kMaxP = 10;
 constexpr int kMaxQExtra = 3;  // q in [p+1, p+3]
 constexpr int kBoxCfgs = 10;   // launch shapes of the box-cell kernel
-constexpr int kMixedCfgs = 4;  // launch shapes of the mixed-precision kernel
+constexpr int kMixedCfgs = 7;  // launch shapes of the mixed-precision apply (4..6: FP32 vector)
 constexpr int kBatchCfgs = 6;  // launch shapes of the batched apply (3..5: one launch per kind)
 constexpr int kMaxBatch = 64;  // operators per batch (operator indices fit in a byte)
 
@@ -149,7 +149,7 @@ bool apply_box_supported(int p, int q, int cfg);
 // Mixed-precision (FP32 / BF16 matrix-core) apply for box cells.
 hipError_t launch_apply_mixed(const Operator& op, const ApplyLaunch& a, int prec, hipStream_t s);
 bool apply_mixed_supported(int p, int q, int cfg);
-int choose_cfg_mixed(int np, int nq, int nvec);
+int choose_cfg_mixed(int np, int nq, int nvec, int prec);
 int choose_cfg_box(int np, int nq, int nvec);
 // block-CG building blocks (solver.hip)
 hipError_t launch_diagonal(const Operator& op, const double* d_tab, double* diag, hipStream_t s);

@@ -127,33 +127,33 @@ struct EoMat {
 // place (x[r][i] <- x_i + x_{n-1-i}, x[r][n-1-i] <- x_i - x_{n-1-i}) and is
 // not usable afterwards.  Every coefficient is a literal used RN times back to
 // back; exact zeros are skipped.
-template <class M, int NOUT, int NIN, bool TR, int LD, int RN>
-__device__ __forceinline__ void eo_matvec(double (&x)[RN][NIN], double (&y)[RN][NOUT]) {
+template <class M, int NOUT, int NIN, bool TR, int LD, int RN, typename T>
+__device__ __forceinline__ void eo_matvec(T (&x)[RN][NIN], T (&y)[RN][NOUT]) {
   using E = EoMat<M, NOUT, NIN, TR, LD>;
   static_assert(centrosymmetric<M, NOUT, NIN, TR, LD>(), "matrix is not centrosymmetric");
 #pragma unroll
   for (int r = 0; r < RN; ++r)
 #pragma unroll
     for (int i = 0; i < E::HI; ++i) {
-      const double a = x[r][i], b = x[r][NIN - 1 - i];
+      const T a = x[r][i], b = x[r][NIN - 1 - i];
       x[r][i] = a + b;
       x[r][NIN - 1 - i] = a - b;
     }
   sfor<E::HO + E::MO>([&](auto O) {
     constexpr int o = decltype(O)::value;
-    double ev[RN], od[RN];
+    T ev[RN], od[RN];
     constexpr int fe = E::first_e(o);
     if constexpr (fe < 0) {
 #pragma unroll
-      for (int r = 0; r < RN; ++r) ev[r] = 0.0;
+      for (int r = 0; r < RN; ++r) ev[r] = T(0);
     } else {
       sfor<E::HI + E::MI>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        constexpr double c = E::e(o, i);
+        constexpr T c = (T)E::e(o, i);
         if constexpr (i == fe) {
 #pragma unroll
           for (int r = 0; r < RN; ++r) ev[r] = c * x[r][i];
-        } else if constexpr (i > fe && c != 0.0) {
+        } else if constexpr (i > fe && c != T(0)) {
 #pragma unroll
           for (int r = 0; r < RN; ++r) ev[r] = fma(c, x[r][i], ev[r]);
         }
@@ -173,11 +173,11 @@ __device__ __forceinline__ void eo_matvec(double (&x)[RN][NIN], double (&y)[RN][
       } else {
         sfor<E::HI>([&](auto I) {
           constexpr int i = decltype(I)::value;
-          constexpr double c = E::d(o, i);
+          constexpr T c = (T)E::d(o, i);
           if constexpr (i == fd) {
 #pragma unroll
             for (int r = 0; r < RN; ++r) od[r] = c * x[r][NIN - 1 - i];
-          } else if constexpr (i > fd && c != 0.0) {
+          } else if constexpr (i > fd && c != T(0)) {
 #pragma unroll
             for (int r = 0; r < RN; ++r) od[r] = fma(c, x[r][NIN - 1 - i], od[r]);
           }
@@ -329,6 +329,11 @@ constexpr size_t kLdsMax = 160 * 1024;     // LDS per workgroup on gfx950
 constexpr size_t box_lds_bytes(int np, int nq, int vtile) {
   return (2 * (size_t)nq * nq * nq * vtile + (size_t)nq * nq * nq) * sizeof(double) + 0 * np;
 }
+// The same for cell arrays of type T (the FP32 vector apply keeps them in float).
+template <typename T>
+constexpr size_t box_lds_bytes_t(int np, int nq, int vtile) {
+  return (2 * (size_t)nq * nq * nq * vtile + (size_t)nq * nq * nq) * sizeof(T) + 0 * np;
+}
 
 // Launch shapes of the box-cell kernel: vector tile B, threads NT (0: the
 // fewest whole wavefronts that cover the largest phase, nq^2 B / C tasks),
@@ -422,6 +427,32 @@ constexpr BoxCfg mixed_cfg(int np, int nq, int idx) {
   return c;
 }
 
+// FP32 vector shapes of the mixed-precision apply (shapes 4 .. 6): the box
+// kernel's even-odd contractions on FP32 cell arrays (FP64 X and Y, FP64
+// assembly), half the LDS per column of the FP64 kernel.  4: B = 16 with two
+// columns per thread; 5: B = 8; 6: B = 16, one column per thread; each with
+// the fewest whole wavefronts covering the nq^2 B / C pencil tasks.
+constexpr int kMixedMfmaCfgs = 4;
+constexpr BoxCfg vec32_cfg(int np, int nq, int idx) {
+  BoxCfg c{0, 0, 1, false};
+  if (idx == 4) c = BoxCfg{16, 0, 2, false};
+  if (idx == 5) c = BoxCfg{8, 0, 1, false};
+  if (idx == 6) c = BoxCfg{16, 0, 1, false};
+  if (c.B == 0) return c;
+  c.NT = (nq * nq * c.B / c.C + 63) / 64 * 64;
+  if (c.NT > 1024 || box_lds_bytes_t<float>(np, nq, c.B) > kLdsMax) c.B = 0;
+  return c;
+}
+// shape with one column per thread for calls that cannot take column pairs
+constexpr int vec32_cfg_single(int idx) { return idx == 4 ? 5 : idx; }
+constexpr int vec32_waves_per_eu(int np, int nq, int B, int NT) {
+  const size_t l = box_lds_bytes_t<float>(np, nq, B);
+  int wg = (int)(kLdsMax / (l > 0 ? l : 1));
+  wg = wg < 1 ? 1 : (wg > 8 ? 8 : wg);
+  const int w = (wg * (NT / 64) + 3) / 4;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 // ---------------------------------------------------------------- batches
 // Launch shapes of the persistent batched kernel (kinds q = p + 1, p = 2..8):
 // 0: 512 threads; FP64 tile per kind filling the workgroup's pencil tasks
@@ -431,9 +462,9 @@ constexpr BoxCfg mixed_cfg(int np, int nq, int idx) {
 // 2: 256 threads, FP64 B = 4 / mixed B = 8.
 constexpr int kBatchMinP = 2, kBatchMaxP = 8;
 constexpr int batch_threads(int bcfg) { return bcfg == 2 ? 256 : 512; }
-// Per-kind launches (shape 3): the kind's own default tile and the fewest
-// whole wavefronts covering its pencil tasks (FP64, one column per thread), or
-// the mixed kernel's default shape.
+// Per-kind launches (shapes 3..5): the kind's own default tile and the fewest
+// whole wavefronts covering its pencil tasks (FP64, one column per thread),
+// the FP32 vector default, or the BF16 matrix-core default.
 constexpr BoxCfg batch_kind_shape(int prec, int np, int nq) {
   if (prec == MF_FP64) {
     BoxCfg c = box_cfg(np, nq, 0);
@@ -442,6 +473,10 @@ constexpr BoxCfg batch_kind_shape(int prec, int np, int nq) {
     c.NT = (nq * nq * c.B + 63) / 64 * 64;
     if (c.NT > 1024) c.NT = 1024;
     return c;
+  }
+  if (prec == MF_FP32_MFMA) {  // the FP32 vector shapes, as the single apply's default
+    const BoxCfg c = vec32_cfg(np, nq, 6);
+    return c.B > 0 ? c : vec32_cfg(np, nq, 5);
   }
   return mixed_cfg(np, nq, 0);
 }

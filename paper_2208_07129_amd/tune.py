@@ -1,7 +1,8 @@
 """Autotuner for the launch shapes of the fused apply kernels.
 
 Single operators: every built launch shape of the kernel the operator uses
-(FP64 box-cell shapes 0..7, mixed-precision shapes 0..3) is timed with the
+(FP64 box-cell shapes 0..9, mixed-precision shapes 0..6, the FP32 vector shapes 4..6
+for FP32 only) is timed with the
 library's per-launch HIP events (mf_timing) on the caller's buffers, and the
 fastest is set on the operator.  Batches: every persistent-kernel shape (0..2)
 is timed with events around mf_batch_apply.  Results are kept in a JSON cache
@@ -65,7 +66,8 @@ def tune_operator(op: mfmv.Operator, X, Y, precision: str = "fp64", reps: int = 
         _set(op, precision, db[key]["cfg"])
         return db[key]
     times = {}
-    for cfg in range(N_BOX if precision == "fp64" else N_MIXED):
+    n = N_BOX if precision == "fp64" else (N_MIXED if precision == "fp32" else mfmv.MIXED_MFMA_CFGS)
+    for cfg in range(n):
         try:
             _set(op, precision, cfg)
         except mfmv.MfError:

@@ -1,5 +1,6 @@
 """GPU parity of the mixed-precision apply (FP32 / BF16 matrix-core contractions,
-FP64 assembly) against the FP64 CPU oracle.
+and FP32 vector contractions for shapes 4..6; FP64 assembly) against the FP64
+CPU oracle.
 
 Gate: FP32 per-column relative error <= 1e-6.  BF16 operands carry a unit
 roundoff of 2^-9 (about 1.95e-3) into each of the nine contraction stages;
@@ -52,6 +53,8 @@ CASES = [
     (6, 7, (2, 2, 2), W.BC_PERIODIC, 21),
     (6, 8, (2, 1, 2), W.BC_NONE, 9),
     (8, 9, (2, 1, 1), W.BC_DIRICHLET0, 17),
+    (6, 7, (2, 2, 2), W.BC_PERIODIC, 16),   # even: the two-column vector shape runs as such
+    (3, 4, (3, 2, 2), W.BC_DIRICHLET0, 40),
 ]
 
 
@@ -63,7 +66,7 @@ def test_mixed_small_meshes_every_shape(p, q, n, bc, nvec):
     orc = fo.Oracle(mesh, p, q, 0.5, vfun, 0.2)
     X = np.random.default_rng(p + 10 * q).uniform(-1, 1, (orc.ndofs, nvec))
     Yref = orc.apply(X)
-    for cfg in range(4):
+    for cfg in range(mfmv.MIXED_CFGS):
         try:
             op.set_launch_mixed(cfg)
         except mfmv.MfError:
@@ -76,12 +79,15 @@ def test_mixed_small_meshes_every_shape(p, q, n, bc, nvec):
             assert np.all(run(op, X, "fp32")[orc.constrained] == 0.0)
 
 
-def test_per_column_scaling_extreme_magnitudes():
+@pytest.mark.parametrize("cfg", [-1, 4, 5, 6])
+def test_per_column_scaling_extreme_magnitudes(cfg):
     """Columns at 1e200 and 1e-200 are outside FP32's range; the per-(cell, column)
-    power-of-two scaling keeps their relative error at the FP32 level."""
+    power-of-two scaling keeps their relative error at the FP32 level (matrix-core
+    default shape and the FP32 vector shapes)."""
     mesh = W.BoxMesh(n=(2, 2, 2), bc=W.BC_PERIODIC)
     Vq = vfun(mfmv.quad_points(mesh, 5))
     op = mfmv.Operator(mesh, 4, 5, 0.5, Vq, 0.2)
+    op.set_launch_mixed(cfg)
     orc = fo.Oracle(mesh, 4, 5, 0.5, vfun, 0.2)
     X = np.random.default_rng(3).uniform(-1, 1, (orc.ndofs, 4))
     X[:, 1] *= 1e200
