@@ -133,7 +133,7 @@ struct BoxGather {
   int node[R1][NP];
   double x[R1 * C][NP];                 // gathered FP64 values
   T xs[F32 ? R1 * C : 1][NP];           // scaled FP32 values (T = float)
-  int ex[F32 ? R1 * C : 1];             // column exponents e (T = float)
+  int ex[F32 ? C : 1];                  // column exponents e (T = float)
 
   // Node numbers from the structured-grid arithmetic: cell e at (cx, cy, cz),
   // local node (i1, i2, i3) -> grid node (cx p + i1, ...) with the periodic
@@ -189,15 +189,18 @@ struct BoxGather {
   // column group, then over the wavefronts through `scratch`, NT / 64 * B
   // ints of LDS not otherwise in use before the next barrier) and the scaled
   // FP32 values.  Every thread of the workgroup must call it (one barrier).
+  // NT is a multiple of G, so all tasks of a thread share its column group.
   __device__ __forceinline__ void scale(int* __restrict__ scratch, int tid) {
-    static_assert(F32 && R1 == 1 && 64 % G == 0, "one task per thread, G divides 64");
+    static_assert(F32 && 64 % G == 0 && NT % G == 0, "G divides 64 and NT");
     constexpr int kNone = -100000;
     int e[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       double m = 0.0;
 #pragma unroll
-      for (int i = 0; i < NP; ++i) m = fmax(m, fabs(x[c][i]));
+      for (int k = 0; k < R1; ++k)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) m = fmax(m, fabs(x[k * C + c][i]));
       int em = kNone;
       if (m > 0.0) (void)frexp(m, &em);
 #pragma unroll
@@ -217,7 +220,9 @@ struct BoxGather {
       for (int w = 0; w < NT / 64; ++w) em = max(em, scratch[w * B + g * C + c]);
       ex[c] = em == kNone ? 0 : em;
 #pragma unroll
-      for (int i = 0; i < NP; ++i) xs[c][i] = (T)ldexp(x[c][i], -ex[c]);
+      for (int k = 0; k < R1; ++k)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) xs[k * C + c][i] = (T)ldexp(x[k * C + c][i], -ex[c]);
     }
   }
 };
