@@ -79,8 +79,8 @@ int mf_jacobi(int64_t n, int k, const double* diag, const double* R, int64_t ldr
 
 /* X := G^{-1} S for a symmetric positive definite k x k block G and a k x m
  * block S (row-major, leading dimensions k and m, device): Cholesky
- * factorisation and two triangular solves in one workgroup, the k x k step of
- * block CG (alpha = (P^T A P)^{-1} P^T R).  G and S are not modified; X must
+ * factorisation and two triangular solves, one workgroup per 64 columns of S,
+ * the k x k step of block CG (alpha = (P^T A P)^{-1} P^T R).  G and S are not modified; X must
  * not overlap them.  If a pivot is not positive (G not numerically SPD),
  * *status (device int) is set to that pivot's index + 1 and X is left
  * unspecified; otherwise *status = 0.  Errors: MF_ERR_ARG (NULL, k < 1,

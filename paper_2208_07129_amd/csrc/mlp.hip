@@ -144,29 +144,56 @@ __device__ inline double pou_weight(const GridDesc& g, int i1, int i2, int i3, i
 // node phase t / 64.  rho = RMS of the cell's residual column (over the
 // cell's F = np^3 node values, constrained nodes as 0); X0t[i][row] =
 // R[node_i][j] / rho as BF16 (rows i in [F, Fp) zero), Tt[i][row] =
-// E[node_i][j] / rho in FP32 when E is given (training targets).
+// E[node_i][j] / rho in FP32 when E is given (training targets).  The node
+// numbers and the per-node input and target factors of the cell are formed
+// once per workgroup in LDS (kMaxCellNodes entries), so the column loops only
+// load, scale and store.
 constexpr int kCols = 64;
+constexpr int kMaxCellNodes = 11 * 11 * 11;
+
+// Per (cell, local node): the node number (-1 constrained), the input factor
+// sqrt(w)^[pou_sqrt] / sqrt(d) and sqrt(d) (d = dsc[node], 1 without dsc).
+__device__ inline void cell_node_factors(const GridDesc& g, int np, int cx, int cy, int cz,
+                                         int pou_sqrt, const double* __restrict__ dsc, int* snode,
+                                         double* sfin, double* sdh) {
+  const int F = np * np * np;
+  for (int i = threadIdx.x; i < F; i += blockDim.x) {
+    const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
+    const int node = grid_node(g, cx, cy, cz, i1, i2, i3);
+    double fi = 0.0, dh = 1.0;
+    if (node >= 0) {
+      const double ws = pou_sqrt ? sqrt(pou_weight(g, i1, i2, i3, cx, cy, cz)) : 1.0;
+      dh = dsc ? sqrt(dsc[node]) : 1.0;
+      fi = ws / dh;
+    }
+    snode[i] = node;
+    sfin[i] = fi;
+    if (sdh) sdh[i] = dh;
+  }
+}
+
 __global__ void __launch_bounds__(256)
 cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int64_t ldr,
                    const double* __restrict__ E, int64_t lde, int Fp, uint16_t* __restrict__ X0t,
                    float* __restrict__ Tt, int64_t ldx, float* __restrict__ rho, int pou_sqrt,
                    const double* __restrict__ dsc) {
   __shared__ double part[256];
+  __shared__ int snode[kMaxCellNodes];
+  __shared__ double sfin[kMaxCellNodes], sdh[kMaxCellNodes];
   const int e = blockIdx.x;
   const int j0 = blockIdx.y * kCols;
   const int t = threadIdx.x, jj = t % kCols, ph = t / kCols;
   const int j = j0 + jj;
   const int F = np * np * np;
   const int cx = e % g.n[0], cy = (e / g.n[0]) % g.n[1], cz = e / (g.n[0] * g.n[1]);
+  cell_node_factors(g, np, cx, cy, cz, pou_sqrt, dsc, snode, sfin, sdh);
+  __syncthreads();
   double ss = 0.0;
   if (j < k)
     for (int i = ph; i < F; i += 4) {
-      const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
-      const int node = grid_node(g, cx, cy, cz, i1, i2, i3);
+      const int node = snode[i];
       if (node >= 0) {
-        double x = R[(int64_t)node * ldr + j];
-        if (pou_sqrt) x *= sqrt(pou_weight(g, i1, i2, i3, cx, cy, cz));
-        if (dsc) x /= sqrt(dsc[node]);
+        const double x = R[(int64_t)node * ldr + j] * sfin[i];
         ss = fma(x, x, ss);
       }
     }
@@ -181,13 +208,10 @@ cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int6
   for (int i = ph; i < Fp; i += 4) {
     double x = 0.0, y = 0.0;
     if (i < F) {
-      const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
-      const int node = grid_node(g, cx, cy, cz, i1, i2, i3);
+      const int node = snode[i];
       if (node >= 0) {
-        const double ws = pou_sqrt ? sqrt(pou_weight(g, i1, i2, i3, cx, cy, cz)) : 1.0;
-        const double dh = dsc ? sqrt(dsc[node]) : 1.0;
-        x = R[(int64_t)node * ldr + j] * s * ws / dh;
-        if (E) y = E[(int64_t)node * lde + j] * s * dh;
+        x = R[(int64_t)node * ldr + j] * s * sfin[i];
+        if (E) y = E[(int64_t)node * lde + j] * s * sdh[i];
       }
     }
     X0t[(int64_t)i * ldx + row] = f32_to_bf16((float)x);
@@ -196,28 +220,40 @@ cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int6
 }
 
 // Z[node][j] += w(node) rho[row] Yt[i][row] over the cell's free nodes
-// (partition-of-unity average of the cell-local predictions).
+// (partition-of-unity average of the cell-local predictions; w or sqrt(w),
+// divided by sqrt(dsc[node])), the per-node factors formed once in LDS.
 __global__ void __launch_bounds__(256)
 cell_scatter_kernel(GridDesc g, int np, int k, const float* __restrict__ Yt, int64_t ldy,
                     const float* __restrict__ rho, double* __restrict__ Z, int64_t ldz,
                     int pou_sqrt, const double* __restrict__ dsc) {
+  __shared__ int snode[kMaxCellNodes];
+  __shared__ double sfac[kMaxCellNodes];
   const int e = blockIdx.x;
   const int j0 = blockIdx.y * kCols;
   const int t = threadIdx.x, jj = t % kCols, ph = t / kCols;
   const int j = j0 + jj;
-  if (j >= k) return;
   const int F = np * np * np;
   const int cx = e % g.n[0], cy = (e / g.n[0]) % g.n[1], cz = e / (g.n[0] * g.n[1]);
+  for (int i = t; i < F; i += blockDim.x) {
+    const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
+    const int node = grid_node(g, cx, cy, cz, i1, i2, i3);
+    double w = 0.0;
+    if (node >= 0) {
+      const double pw = pou_weight(g, i1, i2, i3, cx, cy, cz);
+      w = pou_sqrt ? sqrt(pw) : pw;
+      if (dsc) w /= sqrt(dsc[node]);
+    }
+    snode[i] = node;
+    sfac[i] = w;
+  }
+  __syncthreads();
+  if (j >= k) return;
   const int64_t row = (int64_t)e * k + j;
   const double r = rho[row];
   for (int i = ph; i < F; i += 4) {
-    const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
-    const int node = grid_node(g, cx, cy, cz, i1, i2, i3);
+    const int node = snode[i];
     if (node < 0) continue;
-    const double pw = pou_weight(g, i1, i2, i3, cx, cy, cz);
-    double w = pou_sqrt ? sqrt(pw) : pw;
-    if (dsc) w /= sqrt(dsc[node]);
-    unsafeAtomicAdd(Z + (int64_t)node * ldz + j, w * r * (double)Yt[(int64_t)i * ldy + row]);
+    unsafeAtomicAdd(Z + (int64_t)node * ldz + j, sfac[i] * r * (double)Yt[(int64_t)i * ldy + row]);
   }
 }
 
@@ -322,12 +358,11 @@ __global__ void fill_f32_kernel(float* __restrict__ v, int64_t n, float x) {
 __global__ void init_z_kernel(double* __restrict__ Z, int64_t rows, int cols, int64_t ldz,
                               const double* __restrict__ diag, const double* __restrict__ R,
                               int64_t ldr) {
-  const int64_t total = rows * cols;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / cols;
-    const int c = (int)(i % cols);
-    Z[r * ldz + c] = diag ? R[r * ldr + c] / diag[r] : 0.0;
+  // a wavefront per row, lanes over the columns (no per-element index division)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int64_t r = (int64_t)blockIdx.x * nw + w; r < rows; r += (int64_t)gridDim.x * nw) {
+    const double d = diag ? diag[r] : 1.0;
+    for (int c = lane; c < cols; c += 64) Z[r * ldz + c] = diag ? R[r * ldr + c] / d : 0.0;
   }
 }
 
@@ -371,8 +406,8 @@ hipError_t launch_cell_scatter(const Operator& op, int k, const float* Yt, int64
                                const float* rho, const double* diag, const double* R, int64_t ldr,
                                double* Z, int64_t ldz, int pou_sqrt, const double* dsc,
                                hipStream_t s) {
-  hipLaunchKernelGGL(init_z_kernel, dim3(blocks_for(op.ndofs * k)), dim3(256), 0, s, Z, op.ndofs,
-                     k, ldz, diag, R, ldr);
+  hipLaunchKernelGGL(init_z_kernel, dim3(blocks_for(op.ndofs * 64)), dim3(256), 0, s, Z,
+                     op.ndofs, k, ldz, diag, R, ldr);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   dim3 grid((unsigned)op.ncells, (k + kCols - 1) / kCols);

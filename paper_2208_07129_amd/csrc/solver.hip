@@ -152,81 +152,92 @@ __global__ void jacobi_kernel(int64_t n, int k, const double* __restrict__ diag,
   }
 }
 
-// X := G^{-1} S (G k x k SPD, S k x m), one workgroup.  The lower Cholesky
-// factor is formed in LDS in packed storage (row r at r(r+1)/2; right-looking,
-// one column per step).  The two triangular solves then run on panels of 64
-// right-hand-side columns held in LDS: 4 adjacent lanes own a column, split
-// each row's dot product and combine it with lane shuffles, so a column needs
-// no barrier (its 4 lanes are in one wavefront).
-constexpr int kSpdMaxK = 128, kSpdThreads = 256, kSpdPanel = 64;
+// X := G^{-1} S (G k x k SPD, S k x m).  One workgroup per panel of 64
+// right-hand-side columns; each forms the lower Cholesky factor of G in LDS
+// itself (packed storage, row r at r(r+1)/2; right-looking, one column per
+// step: the scaled column is also copied to a contiguous vector so the rank-1
+// update reads it without bank conflicts, and its rows are dealt to the 16
+// wavefronts without any integer division), then runs the two triangular
+// solves on its panel: 16 adjacent lanes own a column, split each row's dot
+// product and combine it with lane shuffles, so a column needs no barrier
+// (its lanes are in one wavefront).  The factorisation is repeated per panel
+// rather than shared through global memory: it costs less than a second
+// launch.
+constexpr int kSpdMaxK = 128, kSpdThreads = 1024, kSpdPanel = 64;
+constexpr int kSpdLanes = kSpdThreads / kSpdPanel;  // lanes per right-hand side
 __device__ inline int tri(int r, int c) { return r * (r + 1) / 2 + c; }
 __global__ void __launch_bounds__(kSpdThreads)
 spd_solve_kernel(int k, int m, const double* __restrict__ G, const double* __restrict__ S,
                  double* __restrict__ X, int* __restrict__ status) {
   extern __shared__ double sh[];
+  const int ntri = (k * (k + 1) / 2 + 1) / 2 * 2;    // 16-byte aligned sizes
   double* L = sh;                                   // k(k+1)/2
-  double* P = sh + (k * (k + 1) / 2 + 1) / 2 * 2;   // k x kSpdPanel, 16-byte aligned
+  double* Lc = L + ntri;                            // k: the current column
+  double* Dinv = Lc + kSpdMaxK;                     // k: 1 / L(r, r)
+  double* P = Dinv + kSpdMaxK;                      // k x kSpdPanel
   __shared__ int bad;
-  const int t = threadIdx.x;
-  for (int i = t; i < k * k; i += kSpdThreads) {
-    const int r = i / k, c = i % k;
-    if (c <= r) L[tri(r, c)] = G[i];
-  }
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nwaves = kSpdThreads / 64;
+  for (int r = wave; r < k; r += nwaves)
+    for (int c = lane; c <= r; c += 64) L[tri(r, c)] = G[(int64_t)r * k + c];
   if (t == 0) bad = 0;
   __syncthreads();
   for (int c = 0; c < k; ++c) {
     if (t == 0) {
       const double d = L[tri(c, c)];
-      if (!(d > 0.0) || !isfinite(d)) bad = c + 1;
-      else L[tri(c, c)] = sqrt(d);
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = c + 1;
+      } else {
+        L[tri(c, c)] = sqrt(d);
+        Dinv[c] = 1.0 / sqrt(d);
+      }
     }
     __syncthreads();
     if (bad) break;
-    const double dc = L[tri(c, c)];
-    for (int r = c + 1 + t; r < k; r += kSpdThreads) L[tri(r, c)] /= dc;
+    const double ic = Dinv[c];
+    for (int r = c + 1 + t; r < k; r += kSpdThreads) {
+      const double v = L[tri(r, c)] * ic;
+      L[tri(r, c)] = v;
+      Lc[r] = v;
+    }
     __syncthreads();
-    const int rem = k - c - 1;
-    for (int w = t; w < rem * rem; w += kSpdThreads) {
-      const int r = c + 1 + w / rem, s2 = c + 1 + w % rem;
-      if (s2 <= r) L[tri(r, s2)] -= L[tri(r, c)] * L[tri(s2, c)];
+    for (int r = c + 1 + wave; r < k; r += nwaves) {
+      const double lr = Lc[r];
+      double* row = L + tri(r, 0);
+      for (int s2 = c + 1 + lane; s2 <= r; s2 += 64) row[s2] -= lr * Lc[s2];
     }
     __syncthreads();
   }
-  if (t == 0) *status = bad;
+  if (t == 0 && blockIdx.x == 0) *status = bad;
   if (bad) return;
-  const int q = t & 3, jc = t >> 2;   // lane quarter, panel column
-  for (int j0 = 0; j0 < m; j0 += kSpdPanel) {
-    const int w = m - j0 < kSpdPanel ? m - j0 : kSpdPanel;
-    for (int i = t; i < k * kSpdPanel; i += kSpdThreads) {
-      const int r = i / kSpdPanel, c = i % kSpdPanel;
-      P[i] = c < w ? S[(int64_t)r * m + j0 + c] : 0.0;
-    }
-    __syncthreads();
-    // L y = s (rows in order)
-    for (int r = 0; r < k; ++r) {
-      double acc = 0.0;
-      for (int c = q; c < r; c += 4) acc = fma(L[tri(r, c)], P[c * kSpdPanel + jc], acc);
-      acc += __shfl_xor(acc, 1);
-      acc += __shfl_xor(acc, 2);
-      if (q == 0) P[r * kSpdPanel + jc] = (P[r * kSpdPanel + jc] - acc) / L[tri(r, r)];
-      __builtin_amdgcn_wave_barrier();
-    }
-    // L^T x = y (rows in reverse)
-    for (int r = k - 1; r >= 0; --r) {
-      double acc = 0.0;
-      for (int c = r + 1 + q; c < k; c += 4) acc = fma(L[tri(c, r)], P[c * kSpdPanel + jc], acc);
-      acc += __shfl_xor(acc, 1);
-      acc += __shfl_xor(acc, 2);
-      if (q == 0) P[r * kSpdPanel + jc] = (P[r * kSpdPanel + jc] - acc) / L[tri(r, r)];
-      __builtin_amdgcn_wave_barrier();
-    }
-    __syncthreads();
-    for (int i = t; i < k * kSpdPanel; i += kSpdThreads) {
-      const int r = i / kSpdPanel, c = i % kSpdPanel;
-      if (c < w) X[(int64_t)r * m + j0 + c] = P[i];
-    }
-    __syncthreads();
+  const int q = t % kSpdLanes, jc = t / kSpdLanes;  // lane within the column, panel column
+  const int j0 = blockIdx.x * kSpdPanel;
+  const int w = m - j0 < kSpdPanel ? m - j0 : kSpdPanel;
+  for (int r = wave; r < k; r += nwaves)
+    P[r * kSpdPanel + lane] = lane < w ? S[(int64_t)r * m + j0 + lane] : 0.0;
+  __syncthreads();
+  // L y = s (rows in order)
+  for (int r = 0; r < k; ++r) {
+    double acc = 0.0;
+    const double* lrow = L + tri(r, 0);
+    for (int c = q; c < r; c += kSpdLanes) acc = fma(lrow[c], P[c * kSpdPanel + jc], acc);
+#pragma unroll
+    for (int off = 1; off < kSpdLanes; off *= 2) acc += __shfl_xor(acc, off);
+    if (q == 0) P[r * kSpdPanel + jc] = (P[r * kSpdPanel + jc] - acc) * Dinv[r];
+    __builtin_amdgcn_wave_barrier();
   }
+  // L^T x = y (rows in reverse)
+  for (int r = k - 1; r >= 0; --r) {
+    double acc = 0.0;
+    for (int c = r + 1 + q; c < k; c += kSpdLanes)
+      acc = fma(L[tri(c, r)], P[c * kSpdPanel + jc], acc);
+#pragma unroll
+    for (int off = 1; off < kSpdLanes; off *= 2) acc += __shfl_xor(acc, off);
+    if (q == 0) P[r * kSpdPanel + jc] = (P[r * kSpdPanel + jc] - acc) * Dinv[r];
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  for (int r = wave; r < k; r += nwaves)
+    if (lane < w) X[(int64_t)r * m + j0 + lane] = P[r * kSpdPanel + lane];
 }
 
 unsigned grid_for(int64_t total, int threads) {
@@ -297,13 +308,16 @@ int spd_max_k() { return kSpdMaxK; }
 
 hipError_t launch_spd_solve(int k, int m, const double* G, const double* S, double* X, int* status,
                             hipStream_t s) {
-  const size_t lds = ((size_t)(k * (k + 1) / 2 + 1) / 2 * 2 + (size_t)k * kSpdPanel) * sizeof(double);
+  const size_t lds = ((size_t)(k * (k + 1) / 2 + 1) / 2 * 2 + 2 * (size_t)kSpdMaxK +
+                      (size_t)k * kSpdPanel) * sizeof(double);
   if (lds > 64 * 1024) {
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(spd_solve_kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
   }
-  hipLaunchKernelGGL(spd_solve_kernel, dim3(1), dim3(kSpdThreads), lds, s, k, m, G, S, X, status);
+  const unsigned panels = (unsigned)((m + kSpdPanel - 1) / kSpdPanel);
+  hipLaunchKernelGGL(spd_solve_kernel, dim3(panels), dim3(kSpdThreads), lds, s, k, m, G, S, X,
+                     status);
   return hipGetLastError();
 }
 
