@@ -187,9 +187,10 @@ def test_config2_stiffness_kernel_at_full_size():
     assert op.apply(one).abs().max().item() <= 1e-12
 
 
-@pytest.mark.parametrize("nvec", [16, 64])
+@pytest.mark.parametrize("nvec", [16, 64, 256])
 def test_config3_sampled_rows(nvec):
-    """Periodic unit cube, 12^3 cells, p=8, q=9."""
+    """Periodic unit cube, 12^3 cells, p=8, q=9 (nvec 256: the largest multivector of the
+    benchmark configurations, 1.8 GB per operand)."""
     _sampled_parity(W.config3(nvec), 8, nvec)
 
 

@@ -109,7 +109,7 @@ def test_mixed_rejected_on_sheared_cells():
     assert e.value.status == mfmv.MF_ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("nvec", [16, 64])
+@pytest.mark.parametrize("nvec", [16, 64, 256])
 def test_config3_mixed_sampled_rows(nvec):
     """Periodic unit cube 12^3, p=8, q=9: FP32 within 1e-6 of the oracle on sampled rows;
     BF16 error reported."""
