@@ -261,7 +261,69 @@ def solve_leg(a) -> dict:
         j, l = out["solves"][f"jacobi_{prec}"], out["solves"][f"learned_{prec}"]
         out[f"learned_vs_jacobi_{prec}"] = {"time_ratio": l["seconds"] / j["seconds"],
                                             "iteration_ratio": l["iterations"] / max(j["iterations"], 1)}
+    # FP64 work of one Jacobi block-CG iteration: the apply's algorithmic flops and the
+    # six n x k x k block GEMMs (three Gram blocks, three block updates)
+    n, k = int(op.ndofs), w.nvec
+    it_flops = flops_per_cell_vector(w.p, w.q) * op.ncells * k + 6 * 2 * n * k * k
+    j = out["solves"]["jacobi_fp64"]
+    achieved = it_flops * j["iterations"] / j["seconds"] / 1e12
+    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                       "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                       "kernel": "Jacobi block-CG iteration (FP64 apply + 6 block GEMMs)",
+                       "flops_per_iteration": it_flops,
+                       "floor_ms_per_iteration": it_flops / (PEAK_FP64_TFLOPS * 1e12) * 1e3,
+                       "ms_per_iteration": j["seconds"] / max(j["iterations"], 1) * 1e3}
     return out
+
+
+def chebyshev_leg(a) -> dict:
+    """The Chebyshev filter of subspace iteration (Alg. ChFSi) on the standard form
+    M^{-1/2} A M^{-1/2} of config 2 (16^3, p = 6, 64 columns): degree-m filters of fused
+    steps (mf_cheb_step: a D A (D Y) + b Y + c X in one pass), timed per step."""
+    import torch
+    from paper_2208_07129_amd import chebyshev, mfmv
+    w = workload("c2", a.nvec)
+    op = mfmv.Operator.from_workload(w)
+    nvec = w.nvec
+    U = torch.from_numpy(w.X()).cuda()
+    D = mfmv.gll_mass(op, inv_sqrt=True)
+    work = (torch.empty_like(U), torch.empty_like(U))
+    m = a.cheb_degree
+    # spectrum bounds of the standard form: the largest from Lanczos-like growth is not
+    # needed for timing; the filter coefficients only set the scalars of each step
+    lam_min, lam_max, lam_u = 0.0, 400.0, 4.0
+    for _ in range(2):
+        chebyshev.chebyshev_filter(op, D, U, m, lam_min, lam_max, lam_u, work=work)
+    torch.cuda.synchronize()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(3, min(a.steps, 20))
+    s0.record()
+    for _ in range(reps):
+        chebyshev.chebyshev_filter(op, D, U, m, lam_min, lam_max, lam_u, work=work)
+    s1.record()
+    torch.cuda.synchronize()
+    ms_step = s0.elapsed_time(s1) / reps / m
+    free = int(op.ndofs)
+    flops = flops_per_cell_vector(w.p, w.q) * op.ncells * nvec
+    ach = flops / (ms_step * 1e-3) / 1e12
+    # the same degree with separate applies and elementwise updates (torch), for scale
+    Y = torch.empty_like(U)
+    ms_apply = None
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        op.apply(U, Y)
+    t1.record()
+    torch.cuda.synchronize()
+    ms_apply = t0.elapsed_time(t1) / reps
+    return {"metric": "Chebyshev filter step (fused a D A D Y + b Y + c X) GDoF·vec/s",
+            "unit": UNIT, "value": free * nvec / (ms_step * 1e-3) / 1e9, "higher_is_better": True,
+            "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+            "config": {"workload": w.name, "nvec": nvec, "degree": m},
+            "ms_per_step": ms_step, "ms_plain_apply": ms_apply,
+            "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
+                         "kernel": "apply_cheb_kernel"}}
 
 
 def batched_leg(a) -> dict:
@@ -295,6 +357,10 @@ def batched_leg(a) -> dict:
         Xs = [torch.from_numpy(w.X()).cuda() for w in ws]
         Ys = [torch.empty_like(X) for X in Xs]
         work = sum(op.ndofs * k for op, k in zip(ops, nvec))
+        flops = sum(flops_per_cell_vector(w.p, w.q) * op.ncells * k
+                    for w, op, k in zip(ws, ops, nvec))
+        nbytes = sum(algorithmic_bytes(op.ndofs, op.ncells, w.p, w.q, k)
+                     for w, op, k in zip(ws, ops, nvec))
         modes = {}
         for prec in ("fp64", "fp32"):
             ms_loop = timed(lambda: [op.apply(X, Y, precision=prec)
@@ -315,6 +381,17 @@ def batched_leg(a) -> dict:
                 "graph_value": work / (ms_graph * 1e-3) / 1e9,
                 "batched_cfg": tuned["cfg"], "tuner_ms": tuned["ms"],
                 "rel_diff_batched_vs_loop": err}
+            if prec == "fp64":
+                ach = flops / (ms_graph * 1e-3) / 1e12
+                modes[prec]["roofline"] = {"bound": "alu", "achieved": ach,
+                                           "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                           "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
+                                           "kernel": "batched apply (graph replay)"}
+            else:
+                gbs = nbytes / (ms_graph * 1e-3) / 1e9
+                modes[prec]["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                                           "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                                           "traffic": None, "kernel": "batched apply (graph replay)"}
             print(json.dumps({prec: modes[prec]}), file=sys.stderr, flush=True)
             del b
         return work, modes
@@ -328,6 +405,7 @@ def batched_leg(a) -> dict:
                       "dofs_x_columns": int(work),
                       "degrees": sorted(set(w.p for w in ws))}, "modes": modes}
     out["value"] = max(m["graph_value"] for m in modes.values())
+    out["roofline"] = modes["fp64"]["roofline"]
     ws_small = W.small_meshes(64)
     work_s, modes_s = run(ws_small, max(reps, 20))
     out["small_meshes"] = {"workload": "64 periodic meshes n ~ U{2..6}, p ~ U{4,6,8}, "
@@ -352,6 +430,9 @@ def main(argv=None):
                     help="block-CG solve benchmark on the 20^3 p = 6 mesh (own JSON line)")
     ap.add_argument("--batched", action="store_true",
                     help="config-4 batch of 32 uneven meshes: loop vs persistent vs graph")
+    ap.add_argument("--chebyshev", action="store_true",
+                    help="Chebyshev filter steps on the config-2 standard-form operator")
+    ap.add_argument("--cheb-degree", type=int, default=10)
     ap.add_argument("--solve-maxit", type=int, default=4000)
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--train-refresh", type=int, default=25,
@@ -378,6 +459,9 @@ def main(argv=None):
         return 0
     if a.batched:
         print(json.dumps(batched_leg(a)), flush=True)
+        return 0
+    if a.chebyshev:
+        print(json.dumps(chebyshev_leg(a)), flush=True)
         return 0
     w = workload(a.workload, a.nvec)
     prec = mfmv.PRECISIONS[a.precision]

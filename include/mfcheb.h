@@ -1,0 +1,46 @@
+/* libmfmv: the Chebyshev-filter building blocks of subspace iteration for the
+ * eigenproblem H U = M U Lambda (eq. ghep), in its standard form
+ *   H~ U~ = U~ Lambda,  H~ = M^{-1/2} H M^{-1/2},  U~ = M^{1/2} U  (eq. shep),
+ * with M the mass matrix lumped by the Gauss-Lobatto-Legendre rule of the
+ * element's own nodes (diagonal), and H the operator of mf_create_operator.
+ * The filter of Alg. ChFSi repeats X := alpha1 H~ Y + alpha2 X - c alpha1 Y;
+ * mf_cheb_step evaluates one such step in one fused pass over the cells.
+ * Multivectors are dof-major (row i, column j at X[i*ld + j]), device memory;
+ * calls are stream-ordered on `stream` (hipStream_t, NULL = default),
+ * allocate nothing and return MF_OK or a negative mf_status (message in
+ * mf_last_error()).  Axis-aligned cells only (MF_ERR_UNSUPPORTED otherwise).
+ */
+#ifndef MFCHEB_H
+#define MFCHEB_H
+
+#include <stdint.h>
+
+#include "mfmv.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* out[i] := m_i, the GLL-lumped mass of node i (sum over the cells holding
+ * the node of w_a w_b w_c det J, w the GLL weights of the element's nodes,
+ * Sec. Helmholtz eigenvalue problem), or m_i^{-1/2} when inv_sqrt != 0;
+ * constrained rows get 0.  out: device, mf_num_dofs entries.  Errors:
+ * MF_ERR_ARG (NULL), MF_ERR_UNSUPPORTED (sheared cells), MF_ERR_HIP. */
+int mf_gll_mass(mf_operator* op, int inv_sqrt, double* out, void* stream);
+
+/* Out := a D H (D Y) + b Y + c Xp, one step of the Chebyshev filter of
+ * Alg. ChFSi on H~ = D H D (D = M^{-1/2} from mf_gll_mass with inv_sqrt,
+ * device, one entry per row, 0 on constrained rows).  Y, Xp, Out: ndofs x
+ * nvec, common leading dimension ld >= nvec.  Xp may be NULL (the c term is
+ * dropped) and may be Out itself (the in-place recurrence of Alg. ChFSi);
+ * Out must not overlap Y or D.  Constrained rows of Out are written 0.
+ * Errors: MF_ERR_ARG (NULL, nvec < 1, ld < nvec, overlap), MF_ERR_UNSUPPORTED
+ * (sheared cells), MF_ERR_HIP. */
+int mf_cheb_step(mf_operator* op, const double* D, const double* Y, const double* Xp, double* Out,
+                 int nvec, int64_t ld, double a, double b, double c, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFCHEB_H */

@@ -13,7 +13,10 @@ What it computes (Sec. 2.1-2.2 of the paper):
     an n_q-point Gauss rule per direction (eq. quadTensor);
   * the product the "FE-cell level local dense matrices" way (Sec. 2.2.1): dense
     element matrices A^(e), extraction X_e = Q_e C X, batched dense products
-    A^(e) X_e, assembly sum_e Q_e^T (eq. AU with a single partition).
+    A^(e) X_e, assembly sum_e Q_e^T (eq. AU with a single partition);
+  * for the eigenvalue problem (eq. ghep / eq. shep): the GLL-lumped diagonal
+    mass M and one Chebyshev filter step a M^{-1/2} A M^{-1/2} Y + b Y + c X
+    (Alg. ChFSi).
 
 Readings of points the paper leaves open (each also listed in the design notes):
   * J is d x / d xi (reference -> physical); the stated direction of the map
@@ -89,6 +92,13 @@ def gll_nodes(p: int):
         if np.max(np.abs(dx)) < 1e-16:
             break
     return np.concatenate([[-1.0], np.sort(x), [1.0]])
+
+
+def gll_weights(p: int):
+    """Weights of the (p+1)-point Gauss-Lobatto-Legendre rule: 2 / (p (p+1) P_p(x_i)^2)."""
+    x = gll_nodes(p)
+    P, _d, _dd = legendre_with_derivs(p, x)
+    return 2.0 / (p * (p + 1) * P * P)
 
 
 def lagrange_values(nodes, x):
@@ -322,6 +332,34 @@ class Oracle:
         A[self.constrained, :] = 0.0
         A[:, self.constrained] = 0.0
         return A
+
+    # -- lumped mass and the Chebyshev filter step (eigenvalue problem) -------
+    def lumped_mass(self):
+        """The mass matrix with its overlap integral evaluated by the GLL rule of the
+        element's own nodes, which makes it diagonal (Helmholtz eigenvalue problem,
+        eq. shep): m_i = sum over cells and local nodes at i of w_a w_b w_c det J(node).
+        Constrained entries zero."""
+        wg = gll_weights(self.p)
+        xi = self.xi_n
+        n = self.np1
+        i3, i2, i1 = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+        I1, I2, I3 = i1.ravel(), i2.ravel(), i3.ravel()
+        _phi, dphi = trilinear(np.stack([xi[I1], xi[I2], xi[I3]], axis=1))
+        J = np.einsum("kcs,ecd->ekds", dphi, self.corners)              # E x n^3 x 3 x 3
+        vals = wg[I1] * wg[I2] * wg[I3] * np.linalg.det(J)             # E x n^3
+        m = np.zeros(self.ndofs)
+        np.add.at(m, self.map.ravel(), vals.ravel())
+        m[self.constrained] = 0.0
+        return m
+
+    def cheb_step(self, D, Y, Xp, a, b, c):
+        """a D A (D Y) + b Y + c Xp (one step of the Chebyshev filter of Alg. ChFSi on
+        D A D, D = M^{-1/2}); constrained rows zero; Xp may be None."""
+        out = a * D[:, None] * self.apply(D[:, None] * Y) + b * Y
+        if Xp is not None:
+            out = out + c * Xp
+        out[self.constrained] = 0.0
+        return out
 
     def diagonal(self):
         """diag(A) (constrained entries zero), from the element-matrix diagonals."""

@@ -554,4 +554,97 @@ __device__ __forceinline__ void box_cell_tile(T* __restrict__ lds, const GridDes
   box_p8<NP, NQ, B, C, NT, ACCUM, T>(bB, Gt, Y, ldy, nvec, v0, tid);
 }
 
+// ------------------------------------------------ Chebyshev filter step
+// One step of the Chebyshev filter of subspace iteration (Alg. ChFSi) on the
+// standard form of the generalised eigenproblem (eq. shep), fused into one
+// pass:  Out := a D A (D Y) + b Y + c Xp,  D = M^{-1/2} (diagonal; 0 on
+// constrained rows), A the operator.  The gather scales each row by D and
+// loads Xp for the thread's cell-interior rows (its latency hides behind the
+// contractions); the assembly writes
+// a D (.) + b Y + c Xp on those rows (one contributor) and atomically
+// adds a D (.) on face rows, which an initialisation kernel set to b Y + c Xp
+// beforehand.  Out may be Xp (every element is read before it is written, by
+// the same thread); Xp may be NULL (c ignored).
+template <int NP, int NQ, int B, int NT>
+__device__ __forceinline__ void box_cell_tile_cheb(double* __restrict__ lds, const GridDesc& grid,
+                                                   const double* __restrict__ geo,
+                                                   const double* __restrict__ vq,
+                                                   const double* __restrict__ Y,
+                                                   double* Out, int64_t ld, int nvec,
+                                                   int64_t e, int v0, const ChebArgs& ca) {
+  constexpr int C = 1, NQ3 = NQ * NQ * NQ;
+  using GT = BoxGather<NP, B, C, NT>;
+  constexpr int R1 = GT::R1, G = GT::G;
+  double* bA = lds;
+  double* bB = bA + NQ3 * B;
+  double* svq = bB + NQ3 * B;
+  const int tid = threadIdx.x;
+  GT Gt;
+  Gt.load_grid(grid, e, tid);
+  for (int i = tid; i < NQ3; i += NT) svq[i] = vq[e * NQ3 + i];
+  const double g0 = geo[e * 6 + 0], g1 = geo[e * 6 + 3], g2 = geo[e * 6 + 5];
+  Gt.load_x(Y, ld, nvec, v0, tid);
+  // Xp of this thread's cell-interior rows, loaded with the gather and first
+  // used in the assembly, so that its latency hides behind the contractions
+  double xp[R1][NP];
+#pragma unroll
+  for (int k = 0; k < R1; ++k) {
+    const int w = tid + k * NT;
+    const int pen = GT::TK::clamp(w) / G, v = v0 + w % G;
+    const int i2 = pen % NP, i3 = pen / NP;
+    const bool inner_pen = w < GT::T1 && v < nvec && i2 > 0 && i2 < NP - 1 && i3 > 0 &&
+                           i3 < NP - 1;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int node = Gt.node[k][i];
+      const bool inner = inner_pen && i > 0 && i < NP - 1 && node >= 0;
+      xp[k][i] = inner && ca.Xp ? ca.Xp[(int64_t)node * ld + v] : 0.0;
+      Gt.x[k][i] *= node >= 0 ? ca.D[node] : 0.0;
+    }
+  }
+  box_p1<NP, NQ, B, C, NT>(bA, Gt, tid);
+  __syncthreads();
+  box_mid<NP, NQ, B, C, NT>(bA, bB, svq, g0, g1, g2, tid);
+  // P7: N^T along direction 0, then the fused assembly
+  double t[R1][NQ], o[R1][NP];
+#pragma unroll
+  for (int k = 0; k < R1; ++k) {
+    const int w = GT::TK::clamp(tid + k * NT);
+    const int g = w % G, pen = w / G;
+    const int base = ((pen % NP) + NQ * (pen / NP)) * NQ;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) lds_get<C>(bB + (base + q) * B + g, t, k, q);
+  }
+  eo_matvec<MatN<NP, NQ>, NP, NQ, true, NP, R1>(t, o);
+#pragma unroll
+  for (int k = 0; k < R1; ++k) {
+    const int w = tid + k * NT;
+    const int g = w % G, pen = w / G, v = v0 + g;
+    if (w >= GT::T1 || v >= nvec) continue;
+    const int i2 = pen % NP, i3 = pen / NP;
+    const bool inner_pen = i2 > 0 && i2 < NP - 1 && i3 > 0 && i3 < NP - 1;
+    // D and Y again (cache hits: this workgroup gathered them), loaded for the
+    // whole pencil before any store
+    double dn[NP], yv[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int node = Gt.node[k][i];
+      const bool inner = inner_pen && i > 0 && i < NP - 1 && node >= 0;
+      dn[i] = node >= 0 ? ca.D[node] : 0.0;
+      yv[i] = inner ? Y[(int64_t)node * ld + v] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int node = Gt.node[k][i];
+      if (node < 0) continue;
+      const int64_t at = (int64_t)node * ld + v;
+      const double val = ca.a * dn[i] * o[k][i];
+      if (i > 0 && i < NP - 1 && inner_pen)
+        Out[at] = fma(ca.c, xp[k][i], fma(ca.b, yv[i], val));
+      else
+        unsafeAtomicAdd(Out + at, val);
+    }
+  }
+}
+
 }  // namespace mf

@@ -6,6 +6,7 @@
 
 #include "mf_internal.h"
 #include "sf_common.h"
+#include "sf_tables.h"
 
 namespace mf {
 
@@ -206,6 +207,16 @@ int mf_create_operator(const mf_box_mesh* mesh, int p, int q, double mu, const d
     }
   // axis-aligned cells: the off-diagonal entries vanish exactly (J diagonal)
   op->box = G[1] == 0.0 && G[2] == 0.0 && G[5] == 0.0;
+  // lumped (GLL) mass data: det J and the GLL weights 2 / (p (p+1) P_p(x_i)^2)
+  op->detj = detJ;
+  {
+    const std::vector<double> xg = gll_points(p);
+    for (int i = 0; i <= p; ++i) {
+      double P = 0.0, dP = 0.0, ddP = 0.0;
+      ct::legendre(p, xg[i], P, dP, ddP);
+      op->wgll[i] = 2.0 / (p * (p + 1.0) * P * P);
+    }
+  }
   std::vector<double> geo(E * 6);
   for (int64_t e = 0; e < E; ++e) {
     double* g = &geo[e * 6];

@@ -1,0 +1,49 @@
+// C ABI of the Chebyshev-filter building blocks (include/mfcheb.h).
+#include "mf_internal.h"
+#include "mfcheb.h"
+
+using namespace mf;
+
+namespace {
+
+bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
+  const char* a0 = static_cast<const char*>(a);
+  const char* b0 = static_cast<const char*>(b);
+  return a0 < b0 + bn && b0 < a0 + an;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mf_gll_mass(mf_operator* handle, int inv_sqrt, double* out, void* stream) {
+  if (!handle || !out) return fail(MF_ERR_ARG, "operator and out must be non-NULL");
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  if (!op->box) return fail(MF_ERR_UNSUPPORTED, "the lumped mass is built for axis-aligned cells");
+  hipError_t err = launch_gll_mass(*op, inv_sqrt, out, static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "lumped mass kernel launch");
+  return MF_OK;
+}
+
+int mf_cheb_step(mf_operator* handle, const double* D, const double* Y, const double* Xp,
+                 double* Out, int nvec, int64_t ld, double a, double b, double c, void* stream) {
+  if (!handle || !D || !Y || !Out) return fail(MF_ERR_ARG, "operator, D, Y and Out must be non-NULL");
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  if (nvec < 1 || ld < nvec) return fail(MF_ERR_ARG, "need nvec >= 1 and ld >= nvec");
+  if (!op->box) return fail(MF_ERR_UNSUPPORTED, "the Chebyshev step is built for axis-aligned cells");
+  const size_t span = (size_t)((op->ndofs - 1) * ld + nvec) * sizeof(double);
+  const size_t dspan = (size_t)op->ndofs * sizeof(double);
+  if (overlaps(Out, span, Y, span) || overlaps(Out, span, D, dspan))
+    return fail(MF_ERR_ARG, "Out overlaps Y or D");
+  if (Xp && Xp != Out && overlaps(Out, span, Xp, span))
+    return fail(MF_ERR_ARG, "Xp must be Out itself or not overlap it");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t err = launch_cheb_init(*op, Y, Xp, Out, ld, nvec, b, c, s);
+  if (err != hipSuccess) return hip_fail(err, "Chebyshev init kernel launch");
+  const ChebArgs ca{D, Xp, a, b, c};
+  err = launch_apply_cheb(*op, Y, Out, ld, nvec, ca, s);
+  if (err != hipSuccess) return hip_fail(err, "Chebyshev step kernel launch");
+  return MF_OK;
+}
+
+}  // extern "C"

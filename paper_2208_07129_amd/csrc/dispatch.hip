@@ -37,6 +37,55 @@ __global__ void zero_shared_rows_kernel(double* __restrict__ Y, int Nx, int Ny, 
   }
 }
 
+// Chebyshev step initialisation: the face rows of the zero fill's line walk
+// (cell-interior rows are written by the fused kernel) get b Y + c Xp, and
+// constrained rows (the boundary of a zero-Dirichlet mesh) 0.
+__global__ void cheb_init_kernel(const double* __restrict__ Y, const double* Xp, double* Out,
+                                 int Nx, int Ny, int Nz, int p, int dirichlet, int ncols,
+                                 int64_t ld, double b, double c) {
+  const int line = blockIdx.x;
+  const int gy = line % Ny, gz = line / Ny;
+  const bool full = (gy % p == 0) || (gz % p == 0);
+  const bool yz_bnd = dirichlet && (gy == 0 || gy == Ny - 1 || gz == 0 || gz == Nz - 1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int step = full ? 1 : p;
+  for (int gx = wave * step; gx < Nx; gx += nw * step) {
+    const int64_t row = ((int64_t)line * Nx + gx) * ld;
+    const bool cons = yz_bnd || (dirichlet && (gx == 0 || gx == Nx - 1));
+    for (int j = lane; j < ncols; j += 64) {
+      double v = 0.0;
+      if (!cons) {
+        v = b * Y[row + j];
+        if (Xp) v = fma(c, Xp[row + j], v);
+      }
+      Out[row + j] = v;
+    }
+  }
+}
+
+// GLL-lumped mass: per cell and local node, w_a w_b w_c det J added to the
+// node's row (the GLL rule of the element's own nodes makes the mass
+// diagonal).
+struct GllWeights {
+  double w[kMaxP + 1];
+};
+__global__ void gll_mass_kernel(GridDesc g, int np, GllWeights wt, double detj,
+                                double* __restrict__ m) {
+  const int e = blockIdx.x;
+  const int cx = e % g.n[0], cy = (e / g.n[0]) % g.n[1], cz = e / (g.n[0] * g.n[1]);
+  const int F = np * np * np;
+  for (int i = threadIdx.x; i < F; i += blockDim.x) {
+    const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
+    const int node = grid_node(g, cx, cy, cz, i1, i2, i3);
+    if (node >= 0) unsafeAtomicAdd(m + node, wt.w[i1] * wt.w[i2] * wt.w[i3] * detj);
+  }
+}
+__global__ void inv_sqrt_kernel(double* __restrict__ m, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    m[i] = m[i] > 0.0 ? 1.0 / sqrt(m[i]) : 0.0;
+}
+
 // Batched form: kBatchZeroSplit workgroups per node plane gz of any operator of
 // the batch, each taking a contiguous share of the plane's face rows
 // (per-line workgroups are too small for the batch's small meshes and column
@@ -142,6 +191,50 @@ hipError_t launch_zero_shared_rows(double* Y, const int64_t nodes[3], int p, int
   hipLaunchKernelGGL(zero_shared_rows_kernel, dim3((unsigned)lines), dim3(256), 0, s, Y,
                      (int)nodes[0], (int)nodes[1], p, ncols, ld);
   return hipGetLastError();
+}
+
+hipError_t launch_cheb_init(const Operator& op, const double* Y, const double* Xp, double* Out,
+                            int64_t ld, int nvec, double b, double c, hipStream_t s) {
+  const int64_t lines = op.nodes[1] * op.nodes[2];
+  if (lines < 1) return hipSuccess;
+  hipLaunchKernelGGL(cheb_init_kernel, dim3((unsigned)lines), dim3(256), 0, s, Y, Xp, Out,
+                     (int)op.nodes[0], (int)op.nodes[1], (int)op.nodes[2], op.p, op.grid.dirichlet,
+                     nvec, ld, b, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_gll_mass(const Operator& op, int inv_sqrt, double* out, hipStream_t s) {
+  const int64_t n = op.ndofs;
+  unsigned blocks = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(zero_rows_kernel, dim3(blocks), dim3(256), 0, s, out, n, 1, (int64_t)1);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  GllWeights wt{};
+  for (int i = 0; i < op.np && i <= kMaxP; ++i) wt.w[i] = op.wgll[i];
+  hipLaunchKernelGGL(gll_mass_kernel, dim3((unsigned)op.ncells), dim3(256), 0, s, op.grid, op.np,
+                     wt, op.detj, out);
+  err = hipGetLastError();
+  if (err != hipSuccess || !inv_sqrt) return err;
+  hipLaunchKernelGGL(inv_sqrt_kernel, dim3(blocks), dim3(256), 0, s, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_cheb(const Operator& op, const double* Y, double* Out, int64_t ld,
+                             int nvec, const ChebArgs& ca, hipStream_t s) {
+  switch (op.p) {
+    case 1: return launch_cheb_p<1>(op, Y, Out, ld, nvec, ca, s);
+    case 2: return launch_cheb_p<2>(op, Y, Out, ld, nvec, ca, s);
+    case 3: return launch_cheb_p<3>(op, Y, Out, ld, nvec, ca, s);
+    case 4: return launch_cheb_p<4>(op, Y, Out, ld, nvec, ca, s);
+    case 5: return launch_cheb_p<5>(op, Y, Out, ld, nvec, ca, s);
+    case 6: return launch_cheb_p<6>(op, Y, Out, ld, nvec, ca, s);
+    case 7: return launch_cheb_p<7>(op, Y, Out, ld, nvec, ca, s);
+    case 8: return launch_cheb_p<8>(op, Y, Out, ld, nvec, ca, s);
+    case 9: return launch_cheb_p<9>(op, Y, Out, ld, nvec, ca, s);
+    case 10: return launch_cheb_p<10>(op, Y, Out, ld, nvec, ca, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 bool apply_box_supported(int p, int q, int cfg) {

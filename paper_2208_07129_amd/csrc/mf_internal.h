@@ -72,6 +72,8 @@ struct Operator {
   double* d_geo = nullptr;    // E x 6: mu det J (J^-1 J^-T), (00,01,02,11,12,22)
   double* d_vq = nullptr;     // E x nq^3: det J (V + sigma)
   double* d_dtab = nullptr;   // 1D sums of the diagonal (nq np + 3 np)
+  double detj = 0.0;          // det J of every cell (the cell map is affine and uniform)
+  double wgll[kMaxP + 1] = {};  // GLL weights of the np nodes (lumped mass)
   Tables1D t;
   // optional per-launch timing (diagnostics): event triples around the zero
   // fill and the fused kernel of each apply, in a ring
@@ -96,6 +98,22 @@ struct ApplyLaunch {
   int cfg;      // launch shape index (box kernel)
   bool accumulate;
 };
+
+// Arguments of a fused Chebyshev filter step, Out := a D A (D Y) + b Y + c Xp.
+struct ChebArgs {
+  const double* D;   // M^{-1/2} per row (0 on constrained rows)
+  const double* Xp;  // may be NULL (c ignored); may equal Out
+  double a, b, c;
+};
+hipError_t launch_apply_cheb(const Operator& op, const double* Y, double* Out, int64_t ld,
+                             int nvec, const ChebArgs& ca, hipStream_t s);
+// Face rows of Out := b Y + c Xp (0 on constrained rows): the part of a
+// Chebyshev step that the apply's atomics add to.
+hipError_t launch_cheb_init(const Operator& op, const double* Y, const double* Xp, double* Out,
+                            int64_t ld, int nvec, double b, double c, hipStream_t s);
+// out[node] := GLL-lumped mass diagonal (or its inverse square root, 0 on
+// constrained rows).
+hipError_t launch_gll_mass(const Operator& op, int inv_sqrt, double* out, hipStream_t s);
 
 // One operator of a batch, as the persistent kernel sees it (device array).
 struct BatchOp {

@@ -21,7 +21,7 @@ MF_BC_NONE, MF_BC_DIRICHLET0, MF_BC_PERIODIC = 0, 1, 2
 MF_FP64, MF_FP32_MFMA, MF_BF16_MFMA = 0, 1, 2
 PRECISIONS = {"fp64": MF_FP64, "fp32": MF_FP32_MFMA, "bf16": MF_BF16_MFMA}
 BOX_CFGS, MIXED_CFGS, BATCH_CFGS = 10, 7, 6
-MIXED_MFMA_CFGS = 4  # mixed shapes 0..3 are matrix-core kernels; 4..6 are FP32 vector kernels  # launch shapes per kernel (mf_set_launch*)
+MIXED_MFMA_CFGS = 4  # mixed shapes 0..3 are matrix-core kernels; 4..6 are FP32 vector kernels
 
 # Every symbol declared in include/mfmv.h.
 EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask", "mf_basis_1d",
@@ -36,7 +36,9 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_jacobi", "mf_spd_solve",
            # include/mfmlp.h
            "mf_mlp_gemm", "mf_cell_gather", "mf_cell_scatter", "mf_mse_grad", "mf_row_sums",
-           "mf_adam", "mf_symmetrize", "mf_to_bf16", "mf_fill_f32")
+           "mf_adam", "mf_symmetrize", "mf_to_bf16", "mf_fill_f32",
+           # include/mfcheb.h
+           "mf_gll_mass", "mf_cheb_step")
 
 
 class MfError(RuntimeError):
@@ -105,6 +107,8 @@ def lib() -> ctypes.CDLL:
             "mf_adam": (I, [I64, P, P, P, P, P, F32, F32, F32, F32, I, P]),
             "mf_to_bf16": (I, [I64, P, P, P]),
             "mf_fill_f32": (I, [I64, P, F32, P]),
+            "mf_gll_mass": (I, [P, I, P, P]),
+            "mf_cheb_step": (I, [P, P, P, P, P, I, I64, D, D, D, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -277,6 +281,32 @@ def diagonal(op: Operator, out=None, stream=None):
         out = torch.empty(op.ndofs, dtype=torch.float64, device="cuda")
     _check(lib().mf_diagonal(op._h, out.data_ptr(), _stream_ptr(stream)))
     return out
+
+
+def gll_mass(op: Operator, inv_sqrt: bool = False, out=None, stream=None):
+    """GLL-lumped mass diagonal (or its inverse square root; 0 on constrained rows) as a
+    float64 device vector."""
+    import torch
+    if out is None:
+        out = torch.empty(op.ndofs, dtype=torch.float64, device="cuda")
+    _check(lib().mf_gll_mass(op._h, int(bool(inv_sqrt)), out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def cheb_step(op: Operator, D, Y, Xp, Out, a: float, b: float, c: float, stream=None):
+    """Out := a D A (D Y) + b Y + c Xp (Xp may be None or Out itself); returns Out."""
+    py, n, k, ld = _mv(Y, "Y")
+    po, no, ko, ldo = _mv(Out, "Out")
+    if (no, ko, ldo) != (n, k, ld):
+        raise ValueError("Y and Out must have the same shape and row stride")
+    px = 0
+    if Xp is not None:
+        px, nx, kx, ldx = _mv(Xp, "Xp")
+        if (nx, kx, ldx) != (n, k, ld):
+            raise ValueError("Xp must have the shape and row stride of Y")
+    _check(lib().mf_cheb_step(op._h, D.data_ptr(), py, px or None, po, k, ld, float(a), float(b),
+                              float(c), _stream_ptr(stream)))
+    return Out
 
 
 def block_gram_work(n: int, k: int, device="cuda"):

@@ -1,0 +1,112 @@
+"""Pins of the oracle's lumped mass and Chebyshev step (eigenvalue problem,
+eq. shep and Alg. ChFSi), against closed forms and exact integrals.
+
+- GLL weights: closed forms for p <= 4 and sum 2.
+- Lumped mass: the GLL rule of degree p integrates polynomials of degree
+  2p - 1 per direction exactly, so sum_i m_i f(x_i) is the exact integral of
+  f for such f on any mesh (BC none: every node free), and the volume for
+  f = 1 (also on sheared cells); for degree 2p it is not exact (the check is
+  not vacuous).  Periodic meshes give the volume as well.
+- Chebyshev step: with V = 0 on a periodic mesh A 1 = 0, so D A D (M^{1/2} 1)
+  = 0 (the lowest eigenvector of the standard form); and the step is linear
+  in (Y, Xp) with the stated coefficients.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fe_oracle as fo
+
+
+@pytest.mark.parametrize("p,ref", [(1, [1.0, 1.0]), (2, [1 / 3, 4 / 3, 1 / 3]),
+                                   (3, [1 / 6, 5 / 6, 5 / 6, 1 / 6]),
+                                   (4, [1 / 10, 49 / 90, 32 / 45, 49 / 90, 1 / 10])])
+def test_gll_weights_closed_forms(p, ref):
+    np.testing.assert_allclose(fo.gll_weights(p), ref, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("p", range(1, 11))
+def test_gll_weights_sum(p):
+    assert abs(fo.gll_weights(p).sum() - 2.0) <= 1e-13
+
+
+def node_coords(mesh, p):
+    """Physical coordinates of every node of the full numbering (BC none)."""
+    N = fo.nodes_per_dir(mesh, p)
+    xi = fo.gll_nodes(p)
+    lo, hi = np.asarray(mesh.lo, float), np.asarray(mesh.hi, float)
+    h = (hi - lo) / np.asarray(mesh.n, float)
+    axes = []
+    for d in range(3):
+        g = np.arange(N[d])
+        cell, loc = np.minimum(g // p, mesh.n[d] - 1), g - np.minimum(g // p, mesh.n[d] - 1) * p
+        axes.append(lo[d] + h[d] * (cell + (xi[loc] + 1) / 2))
+    z, y, x = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1) @ fo._lin(mesh).T
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_lumped_mass_integrates_exactly_to_degree_2p_minus_1(p):
+    mesh = W.BoxMesh(n=(2, 3, 2), lo=(0.0, -0.5, 0.25), hi=(1.0, 1.0, 1.5), bc=W.BC_NONE)
+    orc = fo.Oracle(mesh, p, p + 1, 0.5)
+    m = orc.lumped_mass()
+    x = node_coords(mesh, p)
+    a = 2 * p - 1
+    exact = ((1.0 ** (a + 1) - 0.0) / (a + 1)) * 1.5 * 1.25          # int x^a over the box
+    assert abs((m * x[:, 0] ** a).sum() - exact) <= 1e-12 * abs(exact)
+    assert abs(m.sum() - 1.0 * 1.5 * 1.25) <= 1e-12
+    # degree 2p in x is not integrated exactly
+    b = 2 * p
+    exact_b = 1.0 / (b + 1) * 1.5 * 1.25
+    assert abs((m * x[:, 0] ** b).sum() - exact_b) > 1e-10 * exact_b
+
+
+@pytest.mark.parametrize("bc", [W.BC_NONE, W.BC_PERIODIC])
+def test_lumped_mass_volume_sheared_and_periodic(bc):
+    lin = np.array([[1.0, 0.3, -0.2], [0.1, 0.9, 0.25], [-0.15, 0.2, 1.1]])
+    mesh = W.BoxMesh(n=(2, 2, 3), lo=(0, 0, 0), hi=(1.0, 2.0, 1.5), bc=bc,
+                     lin=lin if bc == W.BC_NONE else None)
+    orc = fo.Oracle(mesh, 3, 4, 0.5)
+    vol = 3.0 * (abs(np.linalg.det(lin)) if bc == W.BC_NONE else 1.0)
+    assert abs(orc.lumped_mass().sum() - vol) <= 1e-12 * vol
+
+
+def test_chebyshev_step_kills_the_lowest_eigenvector_and_is_linear():
+    mesh = W.BoxMesh(n=(2, 3, 2), lo=(0, 0, 0), hi=(2.0, 3.0, 2.0), bc=W.BC_PERIODIC)
+    orc = fo.Oracle(mesh, 3, 4, 0.5)                  # V = 0: A = K / 2
+    m = orc.lumped_mass()
+    D = 1.0 / np.sqrt(m)
+    u = np.sqrt(m)[:, None]
+    z = orc.cheb_step(D, u, None, 1.0, 0.0, 0.0)
+    assert np.abs(z).max() <= 1e-12 * np.abs(u).max()
+    rng = np.random.default_rng(0)
+    Y, Xp = rng.standard_normal((orc.ndofs, 3)), rng.standard_normal((orc.ndofs, 3))
+    a, b, c = 0.7, -1.3, 0.4
+    full = orc.cheb_step(D, Y, Xp, a, b, c)
+    parts = a * orc.cheb_step(D, Y, None, 1.0, 0.0, 0.0) + b * Y + c * Xp
+    np.testing.assert_allclose(full, parts, rtol=0, atol=1e-12 * np.abs(parts).max())
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 12])
+def test_filter_recurrence_is_the_scaled_chebyshev_polynomial(m):
+    """The step coefficients of the filter reproduce T_m((l - c)/e) / T_m((l_min - c)/e)
+    on scalars (T_m = cos(m arccos x) inside [-1, 1], cosh(m arccosh |x|) sign^m outside)."""
+    from paper_2208_07129_amd.chebyshev import filter_coefficients
+    lmin, lmax, lu = -0.3, 5.0, 1.2
+    e, c = (lmax - lu) / 2, (lmax + lu) / 2
+
+    def T(x):
+        x = np.asarray(x, float)
+        out = np.where(np.abs(x) <= 1, np.cos(m * np.arccos(np.clip(x, -1, 1))),
+                       np.cosh(m * np.arccosh(np.maximum(np.abs(x), 1.0))))
+        return np.where((x < -1) & (m % 2 == 1), -out, out)
+
+    lam = np.linspace(lmin, lmax, 41)
+    steps = filter_coefficients(m, lmin, lmax, lu)
+    prev, cur = np.ones_like(lam), None
+    a, b, _ = steps[0]
+    cur = a * lam * prev + b * prev
+    for a, b, cc in steps[1:]:
+        prev, cur = cur, a * lam * cur + b * cur + cc * prev
+    ref = T((lam - c) / e) / T((lmin - c) / e)
+    np.testing.assert_allclose(cur, ref, rtol=1e-10, atol=1e-12)
