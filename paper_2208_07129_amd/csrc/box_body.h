@@ -584,8 +584,16 @@ __device__ __forceinline__ void box_cell_tile_cheb(double* __restrict__ lds, con
   for (int i = tid; i < NQ3; i += NT) svq[i] = vq[e * NQ3 + i];
   const double g0 = geo[e * 6 + 0], g1 = geo[e * 6 + 3], g2 = geo[e * 6 + 5];
   Gt.load_x(Y, ld, nvec, v0, tid);
-  // Xp of this thread's cell-interior rows, loaded with the gather and first
-  // used in the assembly, so that its latency hides behind the contractions
+#pragma unroll
+  for (int k = 0; k < R1; ++k)
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int node = Gt.node[k][i];
+      Gt.x[k][i] *= node >= 0 ? ca.D[node] : 0.0;
+    }
+  box_p1<NP, NQ, B, C, NT>(bA, Gt, tid);
+  // Xp of this thread's cell-interior rows, issued after P1 and first used in
+  // the assembly, so that its latency hides behind the contractions
   double xp[R1][NP];
 #pragma unroll
   for (int k = 0; k < R1; ++k) {
@@ -599,10 +607,8 @@ __device__ __forceinline__ void box_cell_tile_cheb(double* __restrict__ lds, con
       const int node = Gt.node[k][i];
       const bool inner = inner_pen && i > 0 && i < NP - 1 && node >= 0;
       xp[k][i] = inner && ca.Xp ? ca.Xp[(int64_t)node * ld + v] : 0.0;
-      Gt.x[k][i] *= node >= 0 ? ca.D[node] : 0.0;
     }
   }
-  box_p1<NP, NQ, B, C, NT>(bA, Gt, tid);
   __syncthreads();
   box_mid<NP, NQ, B, C, NT>(bA, bB, svq, g0, g1, g2, tid);
   // P7: N^T along direction 0, then the fused assembly
