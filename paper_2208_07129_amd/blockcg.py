@@ -78,9 +78,24 @@ def block_pcg(op: mfmv.Operator, B, X, precond: Callable, tol: float, maxit: int
     rn2 = torch.empty(k, dtype=torch.float64, device=dev)
     work = mfmv.block_gram_work(n, k, dev)
 
-    precond(R, P)
     it, converged, breakdown = 0, False, False
     active = precond
+
+    def descent_or_fallback(Zb):
+        """Apply the active preconditioner to R into Zb; if it is not the fallback, a
+        direction that is not a descent direction for every column (z_j^T r_j > 0,
+        which a NaN fails too) switches the rest of the run to the fallback."""
+        nonlocal active
+        active(R, Zb)
+        if fallback is not None and active is not fallback:
+            zr = mfmv.col_dots(Zb, R, rn2).cpu().numpy()
+            if not bool(np.all(zr > 0)):
+                active = fallback
+                if stats is not None:
+                    stats.precond_switches += 1
+                active(R, Zb)
+
+    descent_or_fallback(P)
     while it < maxit:
         op.apply(P, Q, precision=precision)
         mfmv.block_gram(P, Q, G, work=work)           # P^T A P
@@ -99,16 +114,7 @@ def block_pcg(op: mfmv.Operator, B, X, precond: Callable, tol: float, maxit: int
             if rel <= tol:
                 converged = True
                 break
-        active(R, Z)
-        if fallback is not None and active is not fallback:
-            # judge: the learned direction must be a descent direction for
-            # every column (z_j^T r_j > 0); else continue with the fallback
-            zr = mfmv.col_dots(Z, R, rn2).cpu().numpy()
-            if bool((zr <= 0).any()):
-                active = fallback
-                if stats is not None:
-                    stats.precond_switches += 1
-                active(R, Z)
+        descent_or_fallback(Z)
         mfmv.block_gram(Q, Z, S, work=work)           # (A P)^T Z
         mfmv.spd_solve(G, S, alpha, st)               # G^{-1} (A P)^T Z
         mfmv.block_update(P, alpha, Z, -1.0, 1.0)     # Z -= P G^{-1} (AP)^T Z

@@ -245,15 +245,19 @@ class Operator:
         import torch
         if X.dtype != torch.float64 or not X.is_cuda:
             raise TypeError("X must be a float64 device tensor")
-        if X.dim() != 2 or X.shape[0] != self.ndofs or X.stride(1) != 1:
+        # the column stride of a single column is immaterial
+        if X.dim() != 2 or X.shape[0] != self.ndofs or (X.shape[1] > 1 and X.stride(1) != 1):
             raise ValueError("X must be (ndofs, nvec) with unit column stride")
         nvec = X.shape[1]
         if Y is None:
-            Y = torch.empty_like(X, memory_format=torch.contiguous_format)
-        if Y.dtype != torch.float64 or Y.shape != X.shape or Y.stride(1) != 1:
+            Y = torch.empty(X.shape, dtype=X.dtype, device=X.device)
+        if Y.dtype != torch.float64 or Y.shape != X.shape or (nvec > 1 and Y.stride(1) != 1):
             raise ValueError("Y must match X")
+        ldx = X.stride(0) if nvec > 1 or X.shape[0] <= 1 else max(X.stride(0), 1)
+        ldy = Y.stride(0) if nvec > 1 or Y.shape[0] <= 1 else max(Y.stride(0), 1)
         fn = self.apply_add_ptr if accumulate else self.apply_ptr
-        fn(X.data_ptr(), Y.data_ptr(), nvec, X.stride(0), Y.stride(0), PRECISIONS[precision], stream)
+        fn(X.data_ptr(), Y.data_ptr(), nvec, max(ldx, nvec), max(ldy, nvec), PRECISIONS[precision],
+           stream)
         return Y
 
 

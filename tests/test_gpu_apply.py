@@ -293,3 +293,68 @@ def test_config2_general_kernel_matches_box_kernel():
     torch.cuda.synchronize()
     rel = (torch.linalg.norm(Yb - Yg, dim=0) / torch.linalg.norm(Yg, dim=0)).max().item()
     assert rel <= TOL
+
+
+# ------------------------------------------------ seeded random draws (properties)
+def _draws(count=10, seed=2024):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        p = int(rng.integers(1, 9))
+        q = p + int(rng.integers(1, 4))
+        if p >= 7:
+            q = p + 1            # keep the oracle's dense cell matrices small
+        bc = int(rng.choice([W.BC_NONE, W.BC_DIRICHLET0, W.BC_PERIODIC]))
+        n = tuple(int(v) for v in rng.integers(1, 4 if p <= 4 else 3, size=3))
+        nvec = int(rng.choice([1, 3, 17, 64, 129, 300]))
+        out.append((p, q, bc, n, nvec, int(rng.integers(0, 1 << 30))))
+    return out
+
+
+@pytest.mark.parametrize("p,q,bc,n,nvec,seed", _draws())
+def test_random_draws_parity_linearity_permutation(p, q, bc, n, nvec, seed):
+    """Seeded draws of degree, quadrature, boundary condition, mesh (one-cell-wide
+    periodic meshes included) and column count (ragged tiles up to 300): parity with
+    the oracle, linearity, and equivariance under a permutation of the columns."""
+    mesh = W.BoxMesh(n=n, lo=(0.0, -0.5, 0.25), hi=(1.0, 1.0, 1.5), bc=bc)
+    op, orc = build_pair(mesh, p, q)
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1, 1, (orc.ndofs, nvec))
+    X2 = rng.uniform(-1, 1, (orc.ndofs, nvec))
+    Y = gpu_apply(op, X)
+    assert colrel(Y, orc.apply(X)) <= TOL
+    Y2 = gpu_apply(op, X2)
+    Ylin = gpu_apply(op, 2.5 * X - 0.75 * X2)
+    assert colrel(Ylin, 2.5 * Y - 0.75 * Y2) <= TOL
+    perm = rng.permutation(nvec)
+    Yp = gpu_apply(op, X[:, perm])
+    assert colrel(Yp, Y[:, perm]) <= TOL
+
+
+# ------------------------------------------------ partition emulation (eq. AU)
+@pytest.mark.parametrize("bc", [W.BC_NONE, W.BC_DIRICHLET0])
+@pytest.mark.parametrize("p", [2, 6])
+def test_partition_emulation_equals_global_apply(bc, p):
+    """The distributed form of eq. AU without a second GPU: the cells split into two
+    sub-boxes (each with its own numbering, interface nodes in both), each applied
+    locally, the owned and ghost contributions summed on the host through the
+    Boolean maps P^(t); constraints applied as C / C^T on the global rows.  Equals
+    the global apply."""
+    q = p + 1
+    mesh = W.BoxMesh(n=(4, 2, 3), lo=(0.0, 0.0, 0.0), hi=(2.0, 1.0, 1.5), bc=bc)
+    op, orc = build_pair(mesh, p, q)
+    N = fo.nodes_per_dir(mesh, p)
+    X = np.random.default_rng(p).uniform(-1, 1, (orc.ndofs, 7))
+    Xc = np.where(orc.constrained[:, None], 0.0, X)
+    Yg = gpu_apply(op, X)
+    Ysum = np.zeros_like(X)
+    for part, (lo_x, hi_x, g0) in enumerate([(0.0, 1.0, 0), (1.0, 2.0, 2 * p)]):
+        sub = W.BoxMesh(n=(2, 2, 3), lo=(lo_x, 0.0, 0.0), hi=(hi_x, 1.0, 1.5), bc=W.BC_NONE)
+        sop = mfmv.Operator(sub, p, q, 0.5, vfun(mfmv.quad_points(sub, q)), 0.2)
+        Ns = fo.nodes_per_dir(sub, p)
+        gz, gy, gx = np.meshgrid(np.arange(Ns[2]), np.arange(Ns[1]), np.arange(Ns[0]),
+                                 indexing="ij")
+        rows = ((gx.ravel() + g0) + N[0] * (gy.ravel() + N[1] * gz.ravel()))   # P^(t)
+        Ysum[rows] += gpu_apply(sop, Xc[rows])
+    Ysum[orc.constrained] = 0.0
+    assert colrel(Ysum, Yg) <= TOL

@@ -249,3 +249,26 @@ def test_learned_preconditioner_gain_over_jacobi():
     assert sj.converged and sl.converged and sf.converged
     assert jd["ratio"] < 1.0
     assert sl.iterations < sj.iterations
+
+
+@pytest.mark.parametrize("corruption", ["nan", "negated"])
+def test_corrupted_network_falls_back_to_jacobi(corruption):
+    """A broken network (NaN weights, or a skip block that makes the learned step an
+    ascent direction) is caught by the descent check: the solve switches to Jacobi
+    and still reaches 1e-10 in every column."""
+    mesh, op = small_op(W.BC_PERIODIC, p=3, n=(3, 3, 3))
+    diag = mfmv.diagonal(op)
+    net = mlp.CellMLP(op, hidden=64, seed=1, dscale=diag)
+    H, F = net.H, net.F
+    with torch.no_grad():
+        if corruption == "nan":
+            net.params[4].fill_(float("nan"))
+        else:  # S = -4 I: z = D^-1 r - 4 (D^-1/2 sqrt(w) ...) pushes z^T r below zero
+            net.params[4].zero_()
+            net.params[4][:F, H:H + F] = -4.0 * torch.eye(F, device=dev())
+        net.wbf[4].copy_(torch.from_numpy(mlp._host_bf16(net.params[4].cpu().numpy())))
+    B = torch.from_numpy(np.random.default_rng(6).uniform(-1, 1, (op.ndofs, 4))).to(dev())
+    jac = blockcg.jacobi_preconditioner(diag)
+    _, st = blockcg.solve(op, B, net.preconditioner(diag), tol=1e-10, maxit=3000, fallback=jac)
+    assert st.converged and st.rel_residual <= 1e-10, st
+    assert st.precond_switches >= 1
