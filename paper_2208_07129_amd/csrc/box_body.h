@@ -611,7 +611,27 @@ __device__ __forceinline__ void box_cell_tile_cheb(double* __restrict__ lds, con
   }
   __syncthreads();
   box_mid<NP, NQ, B, C, NT>(bA, bB, svq, g0, g1, g2, tid);
-  // P7: N^T along direction 0, then the fused assembly
+  // P7: N^T along direction 0, then the fused assembly.  D and Y of the
+  // thread's rows are loaded again (cache hits: this workgroup gathered them)
+  // before the stage's LDS reads, so their latency overlaps the stage instead
+  // of delaying the stores (holding them in registers through the whole chain
+  // would exceed the register budget of three workgroups per CU).
+  double dn[R1][NP], yv[R1][NP];
+#pragma unroll
+  for (int k = 0; k < R1; ++k) {
+    const int w = tid + k * NT;
+    const int pen = GT::TK::clamp(w) / G, v = v0 + w % G;
+    const int i2 = pen % NP, i3 = pen / NP;
+    const bool inner_pen = w < GT::T1 && v < nvec && i2 > 0 && i2 < NP - 1 && i3 > 0 &&
+                           i3 < NP - 1;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int node = Gt.node[k][i];
+      const bool inner = inner_pen && i > 0 && i < NP - 1 && node >= 0;
+      dn[k][i] = node >= 0 ? ca.D[node] : 0.0;
+      yv[k][i] = inner ? Y[(int64_t)node * ld + v] : 0.0;
+    }
+  }
   double t[R1][NQ], o[R1][NP];
 #pragma unroll
   for (int k = 0; k < R1; ++k) {
@@ -629,24 +649,14 @@ __device__ __forceinline__ void box_cell_tile_cheb(double* __restrict__ lds, con
     if (w >= GT::T1 || v >= nvec) continue;
     const int i2 = pen % NP, i3 = pen / NP;
     const bool inner_pen = i2 > 0 && i2 < NP - 1 && i3 > 0 && i3 < NP - 1;
-    // D and Y again (cache hits: this workgroup gathered them), loaded for the
-    // whole pencil before any store
-    double dn[NP], yv[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      const int node = Gt.node[k][i];
-      const bool inner = inner_pen && i > 0 && i < NP - 1 && node >= 0;
-      dn[i] = node >= 0 ? ca.D[node] : 0.0;
-      yv[i] = inner ? Y[(int64_t)node * ld + v] : 0.0;
-    }
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
       const int node = Gt.node[k][i];
       if (node < 0) continue;
       const int64_t at = (int64_t)node * ld + v;
-      const double val = ca.a * dn[i] * o[k][i];
+      const double val = ca.a * dn[k][i] * o[k][i];
       if (i > 0 && i < NP - 1 && inner_pen)
-        Out[at] = fma(ca.c, xp[k][i], fma(ca.b, yv[i], val));
+        Out[at] = fma(ca.c, xp[k][i], fma(ca.b, yv[k][i], val));
       else
         unsafeAtomicAdd(Out + at, val);
     }
