@@ -39,6 +39,20 @@ int mf_gll_mass(mf_operator* op, int inv_sqrt, double* out, void* stream);
 int mf_cheb_step(mf_operator* op, const double* D, const double* Y, const double* Xp, double* Out,
                  int nvec, int64_t ld, double a, double b, double c, void* stream);
 
+/* Symmetric eigen-decomposition of a k x k block (the Rayleigh-Ritz and
+ * orthogonalisation steps of Alg. ChFSi): A = V diag(w) V^T with w ascending
+ * and V's columns orthonormal, by the cyclic Jacobi method in one workgroup.
+ * A: row-major k x k (lda >= k), only read; w: k entries; V: row-major k x k
+ * (ldv >= k), V[i*ldv + j] = component i of eigenvector j.  With vpow != 0
+ * every column j is scaled by w_j^vpow (vpow = -1/2: V diag(w)^{-1/2}, the
+ * orthonormalising factor of a Gram block).  *status (device int): 0
+ * converged (off-diagonal norm <= 1e-14 of the block's); 1 not converged in
+ * 40 sweeps (results are the last iterate); 2 vpow != 0 and some w_j <= 0.
+ * w and V must not overlap A or each other.  Errors: MF_ERR_ARG (NULL,
+ * ld < k, overlap), MF_ERR_UNSUPPORTED (k < 1 or k > 64), MF_ERR_HIP. */
+int mf_sym_eig(int k, const double* A, int64_t lda, double* w, double* V, int64_t ldv,
+               double vpow, int* status, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

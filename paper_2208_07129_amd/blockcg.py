@@ -186,10 +186,12 @@ def solve(op: mfmv.Operator, B, precond: Callable, tol: float = 1e-10, maxit: in
     return X, stats
 
 
-def lanczos_extremes(op: mfmv.Operator, steps: int = 100, seed: int = 0) -> dict:
+def lanczos_extremes(op: mfmv.Operator, steps: int = 100, seed: int = 0,
+                     matvec: Optional[Callable] = None) -> dict:
     """Ritz estimates of the extreme eigenvalues of A (FP64 apply, plain Lanczos
     from a seeded random vector on the free dofs): the SPD check before a solve
-    (lambda_min > 0; Ritz values of the smallest end converge from above)."""
+    (lambda_min > 0; Ritz values of the smallest end converge from above).
+    `matvec(v, w)` (w := S v) replaces the apply for another symmetric S."""
     import torch
     n = op.ndofs
     rng = np.random.default_rng(seed)
@@ -203,7 +205,10 @@ def lanczos_extremes(op: mfmv.Operator, steps: int = 100, seed: int = 0) -> dict
     alphas, betas = [], []
     beta = 0.0
     for j in range(steps):
-        op.apply(v, w)
+        if matvec is None:
+            op.apply(v, w)
+        else:
+            matvec(v, w)
         if j > 0:
             mfmv.axpby(-beta, vp, 1.0, w)
         alpha = float(mfmv.col_dots(w, v).cpu().numpy()[0])

@@ -46,4 +46,20 @@ int mf_cheb_step(mf_operator* handle, const double* D, const double* Y, const do
   return MF_OK;
 }
 
+int mf_sym_eig(int k, const double* A, int64_t lda, double* w, double* V, int64_t ldv,
+               double vpow, int* status, void* stream) {
+  if (!A || !w || !V || !status) return fail(MF_ERR_ARG, "A, w, V and status must be non-NULL");
+  if (k < 1 || k > eig_max_k()) return fail(MF_ERR_UNSUPPORTED, "need 1 <= k <= 64");
+  if (lda < k || ldv < k) return fail(MF_ERR_ARG, "need lda, ldv >= k");
+  const size_t as = (size_t)((k - 1) * lda + k) * sizeof(double);
+  const size_t vs = (size_t)((k - 1) * ldv + k) * sizeof(double);
+  const size_t ws = (size_t)k * sizeof(double);
+  if (overlaps(V, vs, A, as) || overlaps(w, ws, A, as) || overlaps(w, ws, V, vs))
+    return fail(MF_ERR_ARG, "w and V must not overlap A or each other");
+  hipError_t err = launch_sym_eig(k, A, lda, w, V, ldv, vpow, status,
+                                  static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "eigen-decomposition kernel launch");
+  return MF_OK;
+}
+
 }  // extern "C"

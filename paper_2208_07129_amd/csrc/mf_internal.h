@@ -183,6 +183,9 @@ hipError_t launch_jacobi(int64_t n, int k, const double* diag, const double* R, 
 hipError_t launch_spd_solve(int k, int m, const double* G, const double* S, double* X, int* status,
                             hipStream_t s);
 int spd_max_k();
+int eig_max_k();
+hipError_t launch_sym_eig(int k, const double* A, int64_t lda, double* w, double* V, int64_t ldv,
+                          double vpow, int* status, hipStream_t s);
 // learned-preconditioner kernels (mlp.hip)
 struct GemmEpi {  // epilogue of the BF16 matrix-core GEMM (see mfmlp.h)
   const float* bias;

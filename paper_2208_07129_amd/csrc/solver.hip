@@ -240,6 +240,139 @@ spd_solve_kernel(int k, int m, const double* __restrict__ G, const double* __res
     if (lane < w) X[(int64_t)r * m + j0 + lane] = P[r * kSpdPanel + lane];
 }
 
+// Symmetric eigen-decomposition of a k x k block (k <= kEigMaxK) by the
+// cyclic Jacobi method, one workgroup: the block and the accumulated rotations
+// in LDS; each round applies k/2 disjoint plane rotations (round-robin pairing,
+// so every pair of indices meets once per sweep): the rotation angles of the
+// round's pairs, then the row updates, then the column updates of the block
+// and of the rotations, a barrier after each.  Sweeps until the off-diagonal
+// Frobenius norm is below 1e-14 of the block's (at most kEigMaxSweeps).  The
+// eigenvalues are sorted ascending by rank; with vpow != 0 the eigenvector
+// columns are scaled by w_j^vpow (every w_j must then be positive).
+constexpr int kEigMaxK = 64, kEigThreads = 256, kEigMaxSweeps = 40, kEigLd = kEigMaxK + 1;
+__global__ void __launch_bounds__(kEigThreads)
+sym_eig_kernel(int k, const double* __restrict__ A, int64_t lda, double* __restrict__ w,
+               double* __restrict__ V, int64_t ldv, double vpow, int* __restrict__ status) {
+  extern __shared__ double sh[];
+  double* a = sh;                           // kk x kEigLd
+  double* v = a + kEigMaxK * kEigLd;        // kk x kEigLd
+  __shared__ double cs_c[kEigMaxK / 2], cs_s[kEigMaxK / 2], red[kEigThreads];
+  __shared__ int pp[kEigMaxK / 2], pq[kEigMaxK / 2];
+  __shared__ int done;
+  const int t = threadIdx.x;
+  const int kk = k + (k & 1);               // an odd k gets a decoupled padding index
+  for (int i = t; i < kk * kk; i += kEigThreads) {
+    const int r = i / kk, c = i % kk;
+    a[r * kEigLd + c] = (r < k && c < k) ? A[(int64_t)r * lda + c] : 0.0;
+    v[r * kEigLd + c] = r == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double nrm = 0.0;
+  for (int i = t; i < k * k; i += kEigThreads) {
+    const double x = a[(i / k) * kEigLd + i % k];
+    nrm += x * x;
+  }
+  red[t] = nrm;
+  __syncthreads();
+  for (int st = kEigThreads / 2; st > 0; st >>= 1) {
+    if (t < st) red[t] += red[t + st];
+    __syncthreads();
+  }
+  const double thresh = 1e-28 * red[0];
+  __syncthreads();
+  const int m = kk - 1, np2 = kk / 2;
+  int sweeps = 0;
+  if (t == 0) done = (kk < 2) ? 1 : 0;
+  __syncthreads();
+  while (!done && sweeps < kEigMaxSweeps) {
+    for (int r = 0; r < m; ++r) {
+      if (t < np2) {
+        // circle method: position 0 holds index 0, position i the index 1 + (i - 1 + r) mod m
+        const int i0 = t, i1 = kk - 1 - t;
+        const int x0 = i0 == 0 ? 0 : 1 + (i0 - 1 + r) % m;
+        const int x1 = 1 + (i1 - 1 + r) % m;
+        const int p = x0 < x1 ? x0 : x1, q = x0 < x1 ? x1 : x0;
+        double c = 1.0, s = 0.0;
+        const double apq = a[p * kEigLd + q];
+        if (q < k && fabs(apq) > 1e-300) {
+          const double th = (a[q * kEigLd + q] - a[p * kEigLd + p]) / (2.0 * apq);
+          const double at = fabs(th);
+          const double tn = (th >= 0.0 ? 1.0 : -1.0) / (at + (at < 1e150 ? sqrt(th * th + 1.0) : at));
+          c = 1.0 / sqrt(tn * tn + 1.0);
+          s = tn * c;
+        }
+        pp[t] = p;
+        pq[t] = q;
+        cs_c[t] = c;
+        cs_s[t] = s;
+      }
+      __syncthreads();
+      for (int i = t; i < np2 * kk; i += kEigThreads) {  // rows p, q of every pair
+        const int pr = i / kk, j = i % kk;
+        const int p = pp[pr], q = pq[pr];
+        const double c = cs_c[pr], s = cs_s[pr];
+        const double ap = a[p * kEigLd + j], aq = a[q * kEigLd + j];
+        a[p * kEigLd + j] = c * ap - s * aq;
+        a[q * kEigLd + j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      for (int i = t; i < np2 * kk; i += kEigThreads) {  // columns p, q: block and rotations
+        const int pr = i / kk, j = i % kk;
+        const int p = pp[pr], q = pq[pr];
+        const double c = cs_c[pr], s = cs_s[pr];
+        const double ap = a[j * kEigLd + p], aq = a[j * kEigLd + q];
+        a[j * kEigLd + p] = c * ap - s * aq;
+        a[j * kEigLd + q] = s * ap + c * aq;
+        const double vp = v[j * kEigLd + p], vq = v[j * kEigLd + q];
+        v[j * kEigLd + p] = c * vp - s * vq;
+        v[j * kEigLd + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    ++sweeps;
+    double off = 0.0;
+    for (int i = t; i < k * k; i += kEigThreads) {
+      const int r = i / k, c = i % k;
+      if (r != c) {
+        const double x = a[r * kEigLd + c];
+        off += x * x;
+      }
+    }
+    red[t] = off;
+    __syncthreads();
+    for (int st = kEigThreads / 2; st > 0; st >>= 1) {
+      if (t < st) red[t] += red[t + st];
+      __syncthreads();
+    }
+    if (t == 0) done = red[0] <= thresh;
+    __syncthreads();
+  }
+  // sort by rank (ties by index) and write w and the scaled eigenvectors
+  int bad = 0;
+  for (int j = t; j < k; j += kEigThreads) {
+    const double lj = a[j * kEigLd + j];
+    int rank = 0;
+    for (int i = 0; i < k; ++i) {
+      const double li = a[i * kEigLd + i];
+      rank += (li < lj) || (li == lj && i < j);
+    }
+    w[rank] = lj;
+    double f = 1.0;
+    if (vpow != 0.0) {
+      if (lj > 0.0) f = pow(lj, vpow);
+      else bad = 1;
+    }
+    for (int i = 0; i < k; ++i) V[(int64_t)i * ldv + rank] = v[i * kEigLd + j] * f;
+  }
+  red[t] = bad;
+  __syncthreads();
+  if (t == 0) {
+    int anybad = 0;
+    for (int i = 0; i < kEigThreads; ++i) anybad |= red[i] != 0.0;
+    *status = anybad ? 2 : (done ? 0 : 1);
+  }
+}
+
 unsigned grid_for(int64_t total, int threads) {
   int64_t b = (total + threads - 1) / threads;
   if (b > 65536) b = 65536;
@@ -305,6 +438,18 @@ hipError_t launch_jacobi(int64_t n, int k, const double* diag, const double* R, 
 }
 
 int spd_max_k() { return kSpdMaxK; }
+int eig_max_k() { return kEigMaxK; }
+
+hipError_t launch_sym_eig(int k, const double* A, int64_t lda, double* w, double* V, int64_t ldv,
+                          double vpow, int* status, hipStream_t s) {
+  const size_t lds = 2 * (size_t)kEigMaxK * kEigLd * sizeof(double);
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(sym_eig_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(sym_eig_kernel, dim3(1), dim3(kEigThreads), lds, s, k, A, lda, w, V, ldv, vpow,
+                     status);
+  return hipGetLastError();
+}
 
 hipError_t launch_spd_solve(int k, int m, const double* G, const double* S, double* X, int* status,
                             hipStream_t s) {

@@ -38,7 +38,7 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_mlp_gemm", "mf_cell_gather", "mf_cell_scatter", "mf_mse_grad", "mf_row_sums",
            "mf_adam", "mf_symmetrize", "mf_to_bf16", "mf_fill_f32",
            # include/mfcheb.h
-           "mf_gll_mass", "mf_cheb_step")
+           "mf_gll_mass", "mf_cheb_step", "mf_sym_eig")
 
 
 class MfError(RuntimeError):
@@ -109,6 +109,7 @@ def lib() -> ctypes.CDLL:
             "mf_fill_f32": (I, [I64, P, F32, P]),
             "mf_gll_mass": (I, [P, I, P, P]),
             "mf_cheb_step": (I, [P, P, P, P, P, I, I64, D, D, D, P]),
+            "mf_sym_eig": (I, [I, P, I64, P, P, I64, D, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -311,6 +312,24 @@ def cheb_step(op: Operator, D, Y, Xp, Out, a: float, b: float, c: float, stream=
     _check(lib().mf_cheb_step(op._h, D.data_ptr(), py, px or None, po, k, ld, float(a), float(b),
                               float(c), _stream_ptr(stream)))
     return Out
+
+
+def sym_eig(A, w=None, V=None, status=None, vpow: float = 0.0, stream=None):
+    """(w ascending, V columns scaled by w^vpow, status) of a symmetric k x k float64
+    device block (k <= 64)."""
+    import torch
+    pa, k, k2, lda = _mv(A, "A")
+    if k != k2:
+        raise ValueError("A must be square")
+    if w is None:
+        w = torch.empty(k, dtype=torch.float64, device=A.device)
+    if V is None:
+        V = torch.empty(k, k, dtype=torch.float64, device=A.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=A.device)
+    _check(lib().mf_sym_eig(k, pa, lda, w.data_ptr(), V.data_ptr(), V.stride(0), float(vpow),
+                            status.data_ptr(), _stream_ptr(stream)))
+    return w, V, status
 
 
 def block_gram_work(n: int, k: int, device="cuda"):

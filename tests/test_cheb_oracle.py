@@ -110,3 +110,21 @@ def test_filter_recurrence_is_the_scaled_chebyshev_polynomial(m):
         prev, cur = cur, a * lam * cur + b * cur + cc * prev
     ref = T((lam - c) / e) / T((lmin - c) / e)
     np.testing.assert_allclose(cur, ref, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("bc", [W.BC_PERIODIC, W.BC_DIRICHLET0])
+def test_standard_form_eigenvalues_equal_the_generalised_problem(bc):
+    """eig(M^{-1/2} A M^{-1/2}) (eq. shep) equals the generalised eigenvalues of
+    (A, M) (eq. ghep) computed by the library's generalised solver, on the free rows."""
+    import scipy.linalg as sla
+    mesh = W.BoxMesh(n=(2, 2, 2), lo=(0, 0, 0), hi=(2.0, 2.0, 2.0), bc=bc)
+    V = W.gaussian_wells(3, L=2.0, k=2, width=0.5)
+    orc = fo.Oracle(mesh, 3, 4, 0.5, V, 0.0)
+    free = ~orc.constrained
+    A = orc.assemble_dense()[np.ix_(free, free)]
+    m = orc.lumped_mass()[free]
+    D = 1.0 / np.sqrt(m)
+    S = D[:, None] * A * D[None, :]
+    ev = np.linalg.eigvalsh(S)
+    ref = sla.eigh(A, np.diag(m), eigvals_only=True)
+    np.testing.assert_allclose(ev, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())

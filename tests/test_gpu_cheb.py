@@ -138,3 +138,61 @@ def test_chebyshev_filter_matches_oracle_recurrence():
     for a, b, c in steps[1:]:
         prev, cur = cur, orc.cheb_step(D_ref, cur, prev, a, b, c)
     assert colrel(Yd.cpu().numpy(), cur) <= 1e-11
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 33, 64])
+def test_sym_eig_matches_numpy(k):
+    rng = np.random.default_rng(k)
+    Z = rng.standard_normal((k, k))
+    A = Z + Z.T
+    w, V, st = mfmv.sym_eig(T(A))
+    assert int(st.item()) == 0
+    wh, Vh = w.cpu().numpy(), V.cpu().numpy()
+    ref = np.linalg.eigvalsh(A)
+    np.testing.assert_allclose(wh, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+    assert np.abs(A @ Vh - Vh * wh).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(Vh.T @ Vh - np.eye(k)).max() <= 1e-13
+    # the orthonormalising factor of an SPD block, and the status of an indefinite one
+    Gs = Z @ Z.T + k * np.eye(k)
+    _, Mh, st = mfmv.sym_eig(T(Gs), vpow=-0.5)
+    assert int(st.item()) == 0
+    Mh = Mh.cpu().numpy()
+    np.testing.assert_allclose(Mh.T @ Gs @ Mh, np.eye(k), rtol=0, atol=1e-12)
+    if k > 1:
+        _, _, st = mfmv.sym_eig(T(A), vpow=-0.5)
+        assert int(st.item()) == 2
+
+
+def test_sym_eig_rejects_large_blocks():
+    with pytest.raises(mfmv.MfError) as e:
+        mfmv.sym_eig(torch.eye(65, dtype=torch.float64, device=dev()))
+    assert e.value.status == mfmv.MF_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("bc", [W.BC_PERIODIC, W.BC_DIRICHLET0])
+def test_subspace_iteration_finds_the_lowest_eigenpairs(bc):
+    """Chebyshev-filtered subspace iteration against a dense eigen-solve of the
+    oracle's standard-form matrix: the nev lowest eigenvalues to 1e-9 once every
+    residual norm is below 2e-7."""
+    from paper_2208_07129_amd.chebyshev import SubspaceIteration
+    mesh = W.BoxMesh(n=(3, 3, 3), lo=(0, 0, 0), hi=(3.0, 3.0, 3.0), bc=bc)
+    Vf = W.gaussian_wells(8, L=3.0, k=3, width=0.6)
+    op = mfmv.Operator(mesh, 3, 4, 0.5, Vf(mfmv.quad_points(mesh, 4)), 0.0)
+    orc = fo.Oracle(mesh, 3, 4, 0.5, Vf, 0.0)
+    free = ~orc.constrained
+    m = orc.lumped_mass()
+    Dr = np.zeros_like(m)
+    Dr[free] = 1.0 / np.sqrt(m[free])
+    S = Dr[:, None] * orc.assemble_dense() * Dr[None, :]
+    ref = np.linalg.eigvalsh(S[np.ix_(free, free)])
+    k, nev = 16, 10
+    U0 = np.random.default_rng(2).uniform(-1, 1, (orc.ndofs, k))
+    U0[orc.constrained] = 0.0
+    si = SubspaceIteration(op, k)
+    # residual norms come from ||H~ u||^2 - theta^2 (resolution ~1e-8 |theta|); the
+    # eigenvalues then carry errors of order residual^2 / gap
+    out = si.solve(T(U0), nev, degree=12, tol=2e-7, maxit=60)
+    print(out["iterations"], out["residual"])
+    assert out["converged"], out["history"][-5:]
+    np.testing.assert_allclose(out["eigenvalues"], ref[:nev], rtol=0,
+                               atol=1e-9 * max(1.0, abs(ref[:nev]).max()))
