@@ -160,9 +160,10 @@ struct BoxGather {
       }
     }
   }
-  // branch-free: invalid lanes (constrained node, columns past nvec, task past
-  // the tile) read X[0] and select zero.  C = 2 needs nvec, ldx even and X
-  // 16-byte aligned (checked by the host).
+  // Invalid lanes (constrained node, columns past nvec, task past the tile)
+  // skip the load and keep zero: the loaded registers are not read until the
+  // first stage, so a prefetch (the persistent form) does not wait for them.
+  // C = 2 needs nvec, ldx even and X 16-byte aligned (checked by the host).
   __device__ __forceinline__ void load_x(const double* __restrict__ X, int64_t ldx, int nvec, int v0,
                                          int tid) {
 #pragma unroll
@@ -173,14 +174,18 @@ struct BoxGather {
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
         const bool ok = wok && node[k][i] >= 0;
-        const int64_t at = ok ? (int64_t)node[k][i] * ldx + v : 0;
+        const int64_t at = (int64_t)node[k][i] * ldx + v;
         if constexpr (C == 1) {
-          const double xv = X[at];
-          x[k][i] = ok ? xv : 0.0;
+          x[k][i] = 0.0;
+          if (ok) x[k][i] = X[at];
         } else {
-          const double2 xv = *reinterpret_cast<const double2*>(X + at);
-          x[2 * k][i] = ok ? xv.x : 0.0;
-          x[2 * k + 1][i] = ok ? xv.y : 0.0;
+          x[2 * k][i] = 0.0;
+          x[2 * k + 1][i] = 0.0;
+          if (ok) {
+            const double2 xv = *reinterpret_cast<const double2*>(X + at);
+            x[2 * k][i] = xv.x;
+            x[2 * k + 1][i] = xv.y;
+          }
         }
       }
     }
@@ -261,9 +266,15 @@ __device__ __forceinline__ void box_p1(T* __restrict__ bA, BoxGather<NP, B, C, N
 // (q, j, k) -> q + NQ j + NQ^2 k (q < NQ; j, k < NP).  In-place stages are
 // safe because every pencil of a stage has a single owner that reads it whole
 // before writing it.
-template <int NP, int NQ, int B, int C, int NT, typename T = double>
+struct NoHook {
+  __device__ void operator()() const {}
+};
+// `after_p3` runs once P3's results are behind a barrier (the persistent form
+// issues the next item's loads there).
+template <int NP, int NQ, int B, int C, int NT, typename T = double, class Hook = NoHook>
 __device__ __forceinline__ void box_mid(T* __restrict__ bA, T* __restrict__ bB,
-                                        const T* __restrict__ svq, T g0, T g1, T g2, int tid) {
+                                        const T* __restrict__ svq, T g0, T g1, T g2, int tid,
+                                        Hook after_p3 = Hook()) {
   constexpr int NQ2 = NQ * NQ, G = B / C;
   using Nf = MatN<NP, NQ>;
   using Lf = MatL<NP, NQ>;
@@ -315,6 +326,7 @@ __device__ __forceinline__ void box_mid(T* __restrict__ bA, T* __restrict__ bB,
     }
   }
   __syncthreads();
+  after_p3();
 
   // P4: direction-0 pencils (b, c): U += g0 Lf_0 T.
   {
@@ -505,14 +517,18 @@ __device__ __forceinline__ void box_items(T* __restrict__ lds, const GridDesc& g
       if (RV * NT == NQ3 || tid + k * NT < NQ3) svq[tid + k * NT] = vqc[k];
     box_p1<NP, NQ, B, C, NT, T>(bA, cur, tid);
     const int64_t nx = it + W;
-    if (nx < end) {  // prefetch the next item into the registers P1 just freed
-      const int64_t en = order[nx / ntiles];
-      cur.load_grid(grid, en, tid);
-      cur.load_x(X, ldx, nvec, (int)(nx % ntiles) * B, tid);
-      load_vq(en, vqc);
-    }
     __syncthreads();
-    box_mid<NP, NQ, B, C, NT, T>(bA, bB, svq, g0, g1, g2, tid);
+    // prefetch the next item into the registers P1 freed, once P3 is done: the
+    // loads then overlap P4 .. P7, and their registers stay free through the
+    // heavier stages before
+    box_mid<NP, NQ, B, C, NT, T>(bA, bB, svq, g0, g1, g2, tid, [&]() {
+      if (nx < end) {
+        const int64_t en = order[nx / ntiles];
+        cur.load_grid(grid, en, tid);
+        cur.load_x(X, ldx, nvec, (int)(nx % ntiles) * B, tid);
+        load_vq(en, vqc);
+      }
+    });
     {
       BoxGather<NP, B, C, NT, T> here;  // node numbers only (x unused)
       here.load_grid(grid, e, tid);
