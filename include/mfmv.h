@@ -33,6 +33,9 @@
  *  - Streams are passed as `void*` holding a hipStream_t (NULL = the null
  *    stream).  Device entry points are stream-ordered and asynchronous: they
  *    enqueue work and return without synchronising, and allocate nothing.
+ *  - An operator or a batch may be used from one host thread at a time (its
+ *    launch settings, timing events and the batch's side streams are shared
+ *    state); distinct handles are independent.
  */
 #ifndef MFMV_H
 #define MFMV_H
