@@ -221,7 +221,11 @@ class Oracle:
         self.ndofs = int(np.prod(nodes_per_dir(mesh, p)))
         self.constrained = constrained_mask(mesh, p)
         self.corners = cell_corners(mesh)
+        self._setup(V)
 
+    def _setup(self, V):
+        """Basis tables and per-point geometry; needs p, q, E, map and corners set."""
+        p, q = self.p, self.q
         # 1D tables: GLL nodal basis (values, derivatives) at the Gauss points.
         self.xi_q, self.w_q = gauss_legendre(q)
         self.xi_n = gll_nodes(p)
