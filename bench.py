@@ -340,6 +340,71 @@ def chebyshev_leg(a) -> dict:
                          "kernel": "apply_cheb_kernel"}}
 
 
+def refined_surface_nodes(mesh, p: int, fine: bool) -> int:
+    """Lattice nodes on the surface of the refined box (the masters of the hanging-node
+    constraints on the coarse lattice, or the hanging nodes on the fine one), without the
+    zero-Dirichlet nodes on the outer boundary.  Closed form for a box strictly inside."""
+    k = 2 * p if fine else p
+    ext = [(mesh.rhi[d] - mesh.rlo[d]) * k + 1 for d in range(3)]
+    inner = [max(e - 2, 0) for e in ext]
+    return int(np.prod(ext) - np.prod(inner))
+
+
+def refined_leg(a) -> dict:
+    """Hanging-node constraints (Sec. 3.2.2) on the once-refined stand-in mesh (12^3 coarse
+    cells, central 6^3 refined, p = 6, zero Dirichlet, 64 columns): one step is
+    C (mf_constraints_distribute), A_u (mf_apply on the refined map) and C^T
+    (mf_constraints_condense), with each part also timed alone."""
+    import torch
+    from paper_2208_07129_amd import mfmv
+    w = W.refined_config(a.nvec or 64)
+    op = mfmv.RefinedOperator.from_workload(w)
+    nvec = w.nvec
+    X = torch.from_numpy(w.X(op.ndofs)).cuda()
+    Y = torch.empty_like(X)
+    for _ in range(max(a.warmup, 2)):
+        op.apply_constrained(X, Y)
+    torch.cuda.synchronize()
+    reps = max(5, min(a.steps, 50))
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_step = timed(lambda: op.apply_constrained(X, Y))
+    ms_dist = timed(lambda: op.distribute(X))
+    ms_cond = timed(lambda: op.condense(Y))
+    op.timing(reps)
+    ms_apply = timed(lambda: op.apply(X, Y))
+    n, z, k = op.timing_read()
+    ms_kernel = k / n
+    flops = flops_per_cell_vector(w.p, w.q) * op.ncells * nvec
+    ach = flops / (ms_kernel * 1e-3) / 1e12
+    nm = refined_surface_nodes(w.mesh, w.p, fine=False)
+    ns = op.nslaves
+    row = 8 * nvec
+    bytes_dist = (nm + ns) * row                 # masters read, slaves written
+    bytes_cond = (2 * ns + 2 * nm) * row         # slaves read and cleared, masters updated
+    return {"metric": "constrained A·X on a refined mesh (C, A_u, C^T) GDoF·vec/s",
+            "unit": UNIT, "value": op.ndofs * nvec / (ms_step * 1e-3) / 1e9,
+            "higher_is_better": True, "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+            "config": {"workload": w.name, "nvec": nvec, "ndofs": op.ndofs, "cells": op.ncells,
+                       "hanging": ns, "masters": nm, "sets": op.nsets},
+            "ms_per_step": ms_step, "ms_distribute": ms_dist, "ms_apply": ms_apply,
+            "ms_apply_kernel": ms_kernel, "ms_zero_fill": z / n, "ms_condense": ms_cond,
+            "constraints_gbs": {"distribute": bytes_dist / (ms_dist * 1e-3) / 1e9,
+                                "condense": bytes_cond / (ms_cond * 1e-3) / 1e9,
+                                "peak": PEAK_HBM_GBS},
+            "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
+                         "kernel": "apply_f64_kernel"}}
+
+
 def batched_leg(a) -> dict:
     """Config 4: 32 uneven periodic meshes (n ~ U{6..16}, p ~ U{4,6,8}, nvec ~
     U{16..128}) applied (a) one mf_apply per operator back to back, (b) as one
@@ -446,6 +511,8 @@ def main(argv=None):
                     help="config-4 batch of 32 uneven meshes: loop vs persistent vs graph")
     ap.add_argument("--chebyshev", action="store_true",
                     help="Chebyshev filter steps on the config-2 standard-form operator")
+    ap.add_argument("--refined", action="store_true",
+                    help="also time the hanging-node constrained apply on the refined mesh")
     ap.add_argument("--cheb-degree", type=int, default=10)
     ap.add_argument("--chfsi-maxit", type=int, default=80)
     ap.add_argument("--chfsi-degree", type=int, default=40)
@@ -478,6 +545,9 @@ def main(argv=None):
         return 0
     if a.chebyshev:
         print(json.dumps(chebyshev_leg(a)), flush=True)
+        return 0
+    if a.refined:
+        print(json.dumps(refined_leg(a)), flush=True)
         return 0
     w = workload(a.workload, a.nvec)
     prec = mfmv.PRECISIONS[a.precision]

@@ -169,15 +169,13 @@ def constraint_matrix(lay, p):
             c = lay["host"][i]
             r = 2.0 * (pos[i] - np.asarray(c, float)) - 1.0     # reference coordinates in [-1, 1]
             L = [lagrange_values(xi, np.array([r[d]]))[0] for d in range(3)]
-            for a3 in range(n1):
-                for a2 in range(n1):
-                    for a1 in range(n1):
-                        w = L[0][a1] * L[1][a2] * L[2][a3]
-                        m = cidx[c[2] * p + a3, c[1] * p + a2, c[0] * p + a1]
-                        if w != 0.0 and kind[m] != DIRICHLET:
-                            rows.append(i)
-                            cols.append(m)
-                            vals.append(w)
+            # weight of the host node (a1, a2, a3): L_a1(r1) L_a2(r2) L_a3(r3), a1 fastest
+            w = (L[2][:, None, None] * L[1][None, :, None] * L[0][None, None, :]).ravel()
+            m = cidx[c[2] * p:c[2] * p + n1, c[1] * p:c[1] * p + n1, c[0] * p:c[0] * p + n1].ravel()
+            keep = (w != 0.0) & (kind[m] != DIRICHLET)
+            rows.extend([i] * int(keep.sum()))
+            cols.extend(m[keep].tolist())
+            vals.extend(w[keep].tolist())
     n = lay["ndofs"]
     return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
 

@@ -48,12 +48,15 @@ def jobs():
         ("mlp.hip", "mlp.o", []),
         ("capi_mlp.cpp", "capi_mlp.o", []),
         ("capi_cheb.cpp", "capi_cheb.o", []),
+        ("refine.cpp", "refine.o", []),
+        ("constraints.hip", "constraints.o", []),
     ]
     for p in range(1, MAX_P + 1):
         out.append(("apply_f64.hip", f"apply_f64_p{p}.o", [f"-DMF_P={p}"]))
         out.append(("apply_box.hip", f"apply_box_p{p}.o", [f"-DMF_P={p}"]))
         out.append(("apply_mixed.hip", f"apply_mixed_p{p}.o", [f"-DMF_P={p}"]))
         out.append(("apply_cheb.hip", f"apply_cheb_p{p}.o", [f"-DMF_P={p}"]))
+        out.append(("apply_box_map.hip", f"apply_box_map_p{p}.o", [f"-DMF_P={p}"]))
     for prec in range(3):
         for cfg in range(3):
             out.append(("apply_batched.hip", f"apply_batched_{prec}_{cfg}.o",

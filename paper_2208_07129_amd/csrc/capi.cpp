@@ -184,29 +184,10 @@ int mf_create_operator(const mf_box_mesh* mesh, int p, int q, double mu, const d
   lin_matrix(*mesh, L);
   double h[3];
   for (int d = 0; d < 3; ++d) h[d] = (mesh->hi[d] - mesh->lo[d]) / mesh->n[d];
-  double J[9], Ji[9];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) J[3 * r + c] = L[3 * r + c] * 0.5 * h[c];
-  const double detJ = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
-                      J[2] * (J[3] * J[7] - J[4] * J[6]);
-  Ji[0] = (J[4] * J[8] - J[5] * J[7]) / detJ;
-  Ji[1] = (J[2] * J[7] - J[1] * J[8]) / detJ;
-  Ji[2] = (J[1] * J[5] - J[2] * J[4]) / detJ;
-  Ji[3] = (J[5] * J[6] - J[3] * J[8]) / detJ;
-  Ji[4] = (J[0] * J[8] - J[2] * J[6]) / detJ;
-  Ji[5] = (J[2] * J[3] - J[0] * J[5]) / detJ;
-  Ji[6] = (J[3] * J[7] - J[4] * J[6]) / detJ;
-  Ji[7] = (J[1] * J[6] - J[0] * J[7]) / detJ;
-  Ji[8] = (J[0] * J[4] - J[1] * J[3]) / detJ;
-  double G[9];  // mu det J J^-1 J^-T
-  for (int s = 0; s < 3; ++s)
-    for (int d = 0; d < 3; ++d) {
-      double acc = 0.0;
-      for (int k = 0; k < 3; ++k) acc += Ji[3 * s + k] * Ji[3 * d + k];
-      G[3 * s + d] = mu * detJ * acc;
-    }
+  double G6[6];
+  const double detJ = cell_factor(L, h, mu, G6);
   // axis-aligned cells: the off-diagonal entries vanish exactly (J diagonal)
-  op->box = G[1] == 0.0 && G[2] == 0.0 && G[5] == 0.0;
+  op->box = G6[1] == 0.0 && G6[2] == 0.0 && G6[4] == 0.0;
   // lumped (GLL) mass data: det J and the GLL weights 2 / (p (p+1) P_p(x_i)^2)
   op->detj = detJ;
   {
@@ -218,15 +199,8 @@ int mf_create_operator(const mf_box_mesh* mesh, int p, int q, double mu, const d
     }
   }
   std::vector<double> geo(E * 6);
-  for (int64_t e = 0; e < E; ++e) {
-    double* g = &geo[e * 6];
-    g[0] = G[0];
-    g[1] = G[1];
-    g[2] = G[2];
-    g[3] = G[4];
-    g[4] = G[5];
-    g[5] = G[8];
-  }
+  for (int64_t e = 0; e < E; ++e)
+    for (int k = 0; k < 6; ++k) geo[e * 6 + k] = G6[k];
   std::vector<double> vq(E * nq3);
   for (int64_t k = 0; k < E * nq3; ++k) {
     const double v = Vq ? Vq[k] : 0.0;
@@ -289,6 +263,9 @@ void mf_destroy_operator(mf_operator* handle) {
   if (op->d_geo) (void)hipFree(op->d_geo);
   if (op->d_vq) (void)hipFree(op->d_vq);
   if (op->d_dtab) (void)hipFree(op->d_dtab);
+  if (op->d_sets) (void)hipFree(op->d_sets);
+  if (op->d_cidx) (void)hipFree(op->d_cidx);
+  if (op->d_cw) (void)hipFree(op->d_cw);
   delete op;
 }
 
@@ -364,7 +341,9 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
   }
   if (ev) (void)hipEventRecord(ev[1], s);
   err = mixed ? launch_apply_mixed(*op, a, prec, s)
-              : (op->box ? launch_apply_box(*op, a, s) : launch_apply_f64(*op, a, s));
+              : (op->box       ? launch_apply_box(*op, a, s)
+                 : op->map_box ? launch_apply_box_map(*op, a, s)
+                               : launch_apply_f64(*op, a, s));
   if (err != hipSuccess) return hip_fail(err, "apply kernel launch");
   if (ev) (void)hipEventRecord(ev[2], s);
   return MF_OK;
@@ -386,7 +365,10 @@ int mf_set_launch(mf_operator* handle, int general, int cfg) {
   if (cfg < -1 || cfg >= kBoxCfgs) return fail(MF_ERR_ARG, "cfg out of range");
   if (cfg >= 0 && !apply_box_supported(op->p, op->q, cfg))
     return fail(MF_ERR_UNSUPPORTED, "launch shape does not fit this (p, q)");
-  if (general) op->box = false;
+  if (general) {
+    op->box = false;
+    op->map_box = false;
+  }
   op->cfg = cfg;
   return MF_OK;
 }

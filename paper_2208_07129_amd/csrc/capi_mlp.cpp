@@ -42,6 +42,7 @@ int mf_cell_gather(mf_operator* handle, int k, const double* R, int64_t ldr, con
                    int pou_sqrt, const double* dscale, void* stream) {
   if (!handle || !R || !X0t || !rho) return fail(MF_ERR_ARG, "operator, R, X0t, rho non-NULL");
   Operator* op = reinterpret_cast<Operator*>(handle);
+  if (op->refined) return fail(MF_ERR_UNSUPPORTED, "cell gather/scatter are built for uniform box meshes");
   const int F = op->np * op->np * op->np;
   if (k < 1 || ldr < k || (E && lde < k)) return fail(MF_ERR_ARG, "need k >= 1, ld >= k");
   if (E && !Tt) return fail(MF_ERR_ARG, "E needs Tt");
@@ -59,6 +60,7 @@ int mf_cell_scatter(mf_operator* handle, int k, const float* Yt, int64_t ldy, co
                     int pou_sqrt, const double* dscale, void* stream) {
   if (!handle || !Yt || !rho || !Z) return fail(MF_ERR_ARG, "operator, Yt, rho, Z non-NULL");
   Operator* op = reinterpret_cast<Operator*>(handle);
+  if (op->refined) return fail(MF_ERR_UNSUPPORTED, "cell gather/scatter are built for uniform box meshes");
   if (k < 1 || ldz < k) return fail(MF_ERR_ARG, "need k >= 1, ldz >= k");
   if (ldy < op->ncells * k) return fail(MF_ERR_ARG, "ldy < ncells * k");
   if (diag && (!R || ldr < k)) return fail(MF_ERR_ARG, "diag needs R with ldr >= k");

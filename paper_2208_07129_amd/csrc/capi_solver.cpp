@@ -55,6 +55,7 @@ extern "C" {
 int mf_diagonal(mf_operator* handle, double* diag, void* stream) {
   if (!handle || !diag) return fail(MF_ERR_ARG, "operator and diag must be non-NULL");
   Operator* op = reinterpret_cast<Operator*>(handle);
+  if (op->refined) return fail(MF_ERR_UNSUPPORTED, "mf_diagonal is built for uniform box meshes");
   hipError_t err = launch_diagonal(*op, op->d_dtab, diag, static_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "diagonal kernel launch");
   return MF_OK;

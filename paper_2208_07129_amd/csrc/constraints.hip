@@ -1,0 +1,115 @@
+// Hanging-node constraints as locally dense products (Sec. 3.2.2): each set I
+// holds the slave rows S_I, the master rows M_I (one coarse face) and the
+// dense weights W_I.  C:   X_S := W_I X_M.   C^T:  Y_M += W_I^T Y_S, Y_S := 0.
+//
+// One workgroup per (set, 64-column tile): lane = column, so every row access
+// is one contiguous 512-byte segment of a dof-major multivector, and the
+// weights are wave-uniform (one W_I row or column per wave step).  The work is
+// bound by the bytes of the slave and master rows; W_I is small and cached.
+#include "mf_internal.h"
+
+namespace mf {
+namespace {
+
+constexpr int kCT = 64;                       // columns per tile, one per lane
+constexpr int kDistThreads = 256;             // 4 waves
+constexpr int kCondThreads = 512;             // 8 waves
+constexpr int kCondWaves = kCondThreads / kCT;
+constexpr int kMaxMPerWave = 16;              // masters per wave in C^T
+constexpr int kSChunk = 64;                   // slave rows staged per step in C^T
+static_assert(kCondWaves * kMaxMPerWave >= (kMaxP + 1) * (kMaxP + 1), "masters of one face");
+
+__global__ void __launch_bounds__(kDistThreads)
+distribute_kernel(const ConstraintSet* __restrict__ sets, const int32_t* __restrict__ idx,
+                  const double* __restrict__ W, double* __restrict__ X, int64_t ld, int nvec) {
+  extern __shared__ double xm[];  // nm x kCT master values
+  const ConstraintSet cs = sets[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid % kCT;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kCT);
+  const int col = blockIdx.y * kCT + lane;
+  const bool ok = col < nvec;
+  for (int m = wave; m < cs.nm; m += kDistThreads / kCT) {
+    const int g = idx[cs.m0 + m];
+    xm[m * kCT + lane] = (ok && g >= 0) ? X[(int64_t)g * ld + col] : 0.0;
+  }
+  __syncthreads();
+  for (int s = wave; s < cs.ns; s += kDistThreads / kCT) {
+    const double* w = W + cs.w0 + (int64_t)s * cs.nm;
+    double acc = 0.0;
+    for (int m = 0; m < cs.nm; ++m) acc = fma(w[m], xm[m * kCT + lane], acc);
+    if (ok) X[(int64_t)idx[cs.s0 + s] * ld + col] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(kCondThreads)
+condense_kernel(const ConstraintSet* __restrict__ sets, const int32_t* __restrict__ idx,
+                const double* __restrict__ W, double* __restrict__ Y, int64_t ld, int nvec) {
+  __shared__ double ys[kSChunk * kCT];  // staged slave values
+  const ConstraintSet cs = sets[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid % kCT;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kCT);
+  const int col = blockIdx.y * kCT + lane;
+  const bool ok = col < nvec;
+  double acc[kMaxMPerWave];
+#pragma unroll
+  for (int j = 0; j < kMaxMPerWave; ++j) acc[j] = 0.0;
+  for (int s0 = 0; s0 < cs.ns; s0 += kSChunk) {
+    const int cnt = min(kSChunk, cs.ns - s0);
+    __syncthreads();  // the previous chunk has been consumed
+    // each slave row belongs to exactly one set: read it, then clear it
+    for (int s = wave; s < cnt; s += kCondWaves) {
+      double v = 0.0;
+      if (ok) {
+        const int64_t at = (int64_t)idx[cs.s0 + s0 + s] * ld + col;
+        v = Y[at];
+        Y[at] = 0.0;
+      }
+      ys[s * kCT + lane] = v;
+    }
+    __syncthreads();
+    for (int s = 0; s < cnt; ++s) {
+      const double v = ys[s * kCT + lane];
+      const double* w = W + cs.w0 + (int64_t)(s0 + s) * cs.nm;
+#pragma unroll
+      for (int j = 0; j < kMaxMPerWave; ++j) {
+        const int m = wave + kCondWaves * j;
+        if (m < cs.nm) acc[j] = fma(w[m], v, acc[j]);
+      }
+    }
+  }
+  if (!ok) return;
+#pragma unroll
+  for (int j = 0; j < kMaxMPerWave; ++j) {
+    const int m = wave + kCondWaves * j;
+    if (m < cs.nm) {
+      const int g = idx[cs.m0 + m];
+      // masters on a coarse edge belong to two sets
+      if (g >= 0) unsafeAtomicAdd(Y + (int64_t)g * ld + col, acc[j]);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_constraints_distribute(const Operator& op, double* X, int nvec, int64_t ld,
+                                         hipStream_t s) {
+  if (op.nsets <= 0) return hipSuccess;
+  if (op.max_masters > (kMaxP + 1) * (kMaxP + 1)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)op.nsets, (unsigned)((nvec + kCT - 1) / kCT));
+  const size_t lds = (size_t)op.max_masters * kCT * sizeof(double);
+  hipLaunchKernelGGL(distribute_kernel, grid, dim3(kDistThreads), lds, s, op.d_sets, op.d_cidx,
+                     op.d_cw, X, ld, nvec);
+  return hipGetLastError();
+}
+
+hipError_t launch_constraints_condense(const Operator& op, double* Y, int nvec, int64_t ld,
+                                       hipStream_t s) {
+  if (op.nsets <= 0) return hipSuccess;
+  if (op.max_masters > kCondWaves * kMaxMPerWave) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)op.nsets, (unsigned)((nvec + kCT - 1) / kCT));
+  hipLaunchKernelGGL(condense_kernel, grid, dim3(kCondThreads), 0, s, op.d_sets, op.d_cidx,
+                     op.d_cw, Y, ld, nvec);
+  return hipGetLastError();
+}
+
+}  // namespace mf

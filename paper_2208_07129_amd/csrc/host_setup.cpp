@@ -52,6 +52,37 @@ static double det3(const double A[9]) {
          A[2] * (A[3] * A[7] - A[4] * A[6]);
 }
 
+double cell_factor(const double L[9], const double h[3], double mu, double G6[6]) {
+  double J[9], Ji[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) J[3 * r + c] = L[3 * r + c] * 0.5 * h[c];
+  const double detJ = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                      J[2] * (J[3] * J[7] - J[4] * J[6]);
+  Ji[0] = (J[4] * J[8] - J[5] * J[7]) / detJ;
+  Ji[1] = (J[2] * J[7] - J[1] * J[8]) / detJ;
+  Ji[2] = (J[1] * J[5] - J[2] * J[4]) / detJ;
+  Ji[3] = (J[5] * J[6] - J[3] * J[8]) / detJ;
+  Ji[4] = (J[0] * J[8] - J[2] * J[6]) / detJ;
+  Ji[5] = (J[2] * J[3] - J[0] * J[5]) / detJ;
+  Ji[6] = (J[3] * J[7] - J[4] * J[6]) / detJ;
+  Ji[7] = (J[1] * J[6] - J[0] * J[7]) / detJ;
+  Ji[8] = (J[0] * J[4] - J[1] * J[3]) / detJ;
+  double G[9];  // mu det J J^-1 J^-T
+  for (int s = 0; s < 3; ++s)
+    for (int d = 0; d < 3; ++d) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += Ji[3 * s + k] * Ji[3 * d + k];
+      G[3 * s + d] = mu * detJ * acc;
+    }
+  G6[0] = G[0];
+  G6[1] = G[1];
+  G6[2] = G[2];
+  G6[3] = G[4];
+  G6[4] = G[5];
+  G6[5] = G[8];
+  return detJ;
+}
+
 int validate_mesh(const mf_box_mesh* m) {
   if (!m) return fail(MF_ERR_ARG, "mesh is NULL");
   for (int d = 0; d < 3; ++d) {

@@ -56,6 +56,13 @@ struct GridDesc {
   int dirichlet;
 };
 
+// One set I of hanging-node constraints (Sec. 3.2.2): slaves [s0, s0+ns) and
+// masters [m0, m0+nm) of the operator's index array, W_I row-major at w0.
+struct ConstraintSet {
+  int32_t s0, ns, m0, nm;
+  int64_t w0;
+};
+
 struct Operator {
   int device = 0;
   int p = 0, q = 0, np = 0, nq = 0;
@@ -75,6 +82,15 @@ struct Operator {
   double detj = 0.0;          // det J of every cell (the cell map is affine and uniform)
   double wgll[kMaxP + 1] = {};  // GLL weights of the np nodes (lumped mass)
   Tables1D t;
+  // hanging-node constraints of a refined mesh (mf_create_refined_operator):
+  // the grid fields above do not describe it, so the grid-based calls refuse it
+  bool refined = false;
+  bool map_box = false;       // refined and every cell axis-aligned: the map-based box kernel
+  int64_t nsets = 0;
+  int max_slaves = 0, max_masters = 0;
+  ConstraintSet* d_sets = nullptr;
+  int32_t* d_cidx = nullptr;  // slave and master node indices (-1: zero-Dirichlet master)
+  double* d_cw = nullptr;     // the W_I, concatenated
   // optional per-launch timing (diagnostics): event triples around the zero
   // fill and the fused kernel of each apply, in a ring
   std::vector<hipEvent_t> ev;
@@ -152,6 +168,22 @@ int batched_kind_blocks_per_cu(int prec, int p);
 // plane_op[plane]: the operator that owns that plane.
 hipError_t launch_batch_zero(const BatchOp* ops, const uint8_t* plane_op, const BatchPtrs& ptrs,
                              int64_t first, int64_t planes, hipStream_t s);
+
+// Hanging-node constraints: X_S := W X_M (distribute) and Y_M += W^T Y_S,
+// Y_S := 0 (condense) over all sets of a refined operator.
+hipError_t launch_constraints_distribute(const Operator& op, double* X, int nvec, int64_t ld,
+                                         hipStream_t s);
+hipError_t launch_constraints_condense(const Operator& op, double* Y, int nvec, int64_t ld,
+                                       hipStream_t s);
+// mu det J J^-1 J^-T of an affine cell with J = L diag(h / 2), as the six
+// entries (00, 01, 02, 11, 12, 22); returns det J.
+double cell_factor(const double L[9], const double h[3], double mu, double G6[6]);
+
+// FP64 fused apply of axis-aligned cells through the cell-to-node map (one
+// instantiation per degree; dispatcher below).
+template <int P>
+hipError_t launch_apply_box_map_p(const Operator& op, const ApplyLaunch& a, hipStream_t s);
+hipError_t launch_apply_box_map(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 
 // FP64 fused apply; returns hipSuccess or the launch error.
 hipError_t launch_apply_f64(const Operator& op, const ApplyLaunch& a, hipStream_t s);

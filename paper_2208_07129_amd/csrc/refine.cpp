@@ -1,0 +1,410 @@
+// Once-refined box meshes: numbering, geometry and hanging-node constraint
+// sets (include/mfrefine.h).  Host code; the constraint kernels are in
+// constraints.hip and the apply is the general-geometry kernel.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "mf_internal.h"
+#include "mfrefine.h"
+#include "sf_tables.h"
+
+namespace mf {
+namespace {
+
+constexpr uint8_t kFree = 0, kDirichlet = 1, kHanging = 2;
+
+struct RefinedLayout {
+  int p = 0;
+  int64_t ndofs = 0, ncells = 0, ncoarse_cells = 0, nslaves = 0;
+  std::vector<int32_t> map;     // ncells x np^3, full numbering
+  std::vector<uint8_t> kind;    // per node
+  std::vector<double> origin;   // ncells x 3, in coarse-cell units
+  std::vector<double> size;     // ncells: 1 (coarse) or 0.5 (fine)
+  std::vector<ConstraintSet> sets;
+  std::vector<int32_t> cidx;    // slaves and masters of every set
+  std::vector<double> W;
+};
+
+bool empty_box(const mf_refined_mesh& m) {
+  for (int d = 0; d < 3; ++d)
+    if (m.rlo[d] >= m.rhi[d]) return true;
+  return false;
+}
+
+int validate_refined(const mf_refined_mesh* m, int p) {
+  if (!m) return fail(MF_ERR_ARG, "mesh is NULL");
+  if (int s = validate_mesh(&m->coarse)) return s;
+  if (m->coarse.bc == MF_BC_PERIODIC)
+    return fail(MF_ERR_UNSUPPORTED, "refined meshes: periodic boundaries are not supported");
+  for (int d = 0; d < 3; ++d)
+    if (m->rlo[d] < 0 || m->rhi[d] < m->rlo[d] || m->rhi[d] > m->coarse.n[d])
+      return fail(MF_ERR_ARG, "refined box: need 0 <= rlo <= rhi <= n");
+  if (p < 1 || p > kMaxP) return fail(MF_ERR_UNSUPPORTED, "p must be in [1, 10]");
+  return MF_OK;
+}
+
+// Reference coordinate in [-1, 1] of fine lattice offset o in [0, 2p] across
+// one coarse cell: child o / p, GLL node o % p of the child (o = 2p: the last
+// node of child 1).  Exact at o = 0, p, 2p.
+double coarse_ref(int o, int p, const std::vector<double>& xi) {
+  const int child = o >= 2 * p ? 1 : o / p;
+  const int a = o - child * p;
+  return child == 0 ? 0.5 * (xi[a] - 1.0) : 0.5 * (xi[a] + 1.0);
+}
+
+// Lagrange basis of the GLL nodes xi at t (product formula).
+void lagrange_at(const std::vector<double>& xi, double t, double* L) {
+  const int n = (int)xi.size();
+  for (int i = 0; i < n; ++i) {
+    double v = 1.0;
+    for (int k = 0; k < n; ++k)
+      if (k != i) v *= (t - xi[k]) / (xi[i] - xi[k]);
+    L[i] = v;
+  }
+}
+
+int build_layout(const mf_refined_mesh& m, int p, bool with_sets, RefinedLayout& out) {
+  const int n[3] = {m.coarse.n[0], m.coarse.n[1], m.coarse.n[2]};
+  const bool empty = empty_box(m);
+  const int np = p + 1, np3 = np * np * np;
+  auto refined = [&](int cx, int cy, int cz) {
+    return !empty && cx >= m.rlo[0] && cx < m.rhi[0] && cy >= m.rlo[1] && cy < m.rhi[1] &&
+           cz >= m.rlo[2] && cz < m.rhi[2];
+  };
+  RefinedLayout L;
+  L.p = p;
+  // cells
+  for (int cz = 0; cz < n[2]; ++cz)
+    for (int cy = 0; cy < n[1]; ++cy)
+      for (int cx = 0; cx < n[0]; ++cx)
+        if (!refined(cx, cy, cz)) {
+          L.origin.insert(L.origin.end(), {(double)cx, (double)cy, (double)cz});
+          L.size.push_back(1.0);
+        }
+  L.ncoarse_cells = (int64_t)L.size.size();
+  if (!empty)
+    for (int fz = 2 * m.rlo[2]; fz < 2 * m.rhi[2]; ++fz)
+      for (int fy = 2 * m.rlo[1]; fy < 2 * m.rhi[1]; ++fy)
+        for (int fx = 2 * m.rlo[0]; fx < 2 * m.rhi[0]; ++fx) {
+          L.origin.insert(L.origin.end(), {0.5 * fx, 0.5 * fy, 0.5 * fz});
+          L.size.push_back(0.5);
+        }
+  L.ncells = (int64_t)L.size.size();
+
+  // coarse lattice nodes of unrefined cells, numbered lexicographically
+  const int64_t N[3] = {(int64_t)n[0] * p + 1, (int64_t)n[1] * p + 1, (int64_t)n[2] * p + 1};
+  const int64_t F[3] = {empty ? 0 : 2 * (int64_t)(m.rhi[0] - m.rlo[0]) * p + 1,
+                        empty ? 0 : 2 * (int64_t)(m.rhi[1] - m.rlo[1]) * p + 1,
+                        empty ? 0 : 2 * (int64_t)(m.rhi[2] - m.rlo[2]) * p + 1};
+  if ((double)N[0] * N[1] * N[2] + (double)F[0] * F[1] * F[2] >= 2147483647.0)
+    return fail(MF_ERR_UNSUPPORTED, "more than 2^31-1 nodes");
+  std::vector<int32_t> cnum((size_t)(N[0] * N[1] * N[2]), -1);
+  auto cat = [&](int64_t gx, int64_t gy, int64_t gz) -> int32_t& {
+    return cnum[(size_t)(gx + N[0] * (gy + N[1] * gz))];
+  };
+  for (int64_t e = 0; e < L.ncoarse_cells; ++e) {
+    const int64_t cx = (int64_t)L.origin[3 * e], cy = (int64_t)L.origin[3 * e + 1],
+                  cz = (int64_t)L.origin[3 * e + 2];
+    for (int i3 = 0; i3 < np; ++i3)
+      for (int i2 = 0; i2 < np; ++i2)
+        for (int i1 = 0; i1 < np; ++i1) cat(cx * p + i1, cy * p + i2, cz * p + i3) = 0;
+  }
+  int64_t nc = 0;
+  for (auto& v : cnum)
+    if (v == 0) v = (int32_t)nc++;
+  L.ndofs = nc + F[0] * F[1] * F[2];
+  const int64_t f0[3] = {2 * (int64_t)m.rlo[0] * p, 2 * (int64_t)m.rlo[1] * p,
+                         2 * (int64_t)m.rlo[2] * p};  // fine lattice origin of the refined box
+  auto fnum = [&](int64_t fx, int64_t fy, int64_t fz) {  // absolute fine lattice -> node
+    return (int32_t)(nc + (fx - f0[0]) + F[0] * ((fy - f0[1]) + F[1] * (fz - f0[2])));
+  };
+
+  // cell-to-node map
+  L.map.resize((size_t)(L.ncells * np3));
+  for (int64_t e = 0; e < L.ncells; ++e) {
+    const bool coarse = e < L.ncoarse_cells;
+    const int64_t c[3] = {(int64_t)std::lround(L.origin[3 * e] * (coarse ? 1 : 2)),
+                          (int64_t)std::lround(L.origin[3 * e + 1] * (coarse ? 1 : 2)),
+                          (int64_t)std::lround(L.origin[3 * e + 2] * (coarse ? 1 : 2))};
+    for (int i3 = 0; i3 < np; ++i3)
+      for (int i2 = 0; i2 < np; ++i2)
+        for (int i1 = 0; i1 < np; ++i1)
+          L.map[(size_t)(e * np3 + i1 + np * (i2 + np * i3))] =
+              coarse ? cat(c[0] * p + i1, c[1] * p + i2, c[2] * p + i3)
+                     : fnum(c[0] * p + i1, c[1] * p + i2, c[2] * p + i3);
+  }
+
+  // node kinds: zero-Dirichlet on the outer boundary, then hanging fine nodes
+  // (in the closure of an unrefined coarse cell: integer lattice tests)
+  L.kind.assign((size_t)L.ndofs, kFree);
+  const bool dir = m.coarse.bc == MF_BC_DIRICHLET0;
+  if (dir) {
+    for (int64_t gz = 0; gz < N[2]; ++gz)
+      for (int64_t gy = 0; gy < N[1]; ++gy)
+        for (int64_t gx = 0; gx < N[0]; ++gx) {
+          const int32_t v = cat(gx, gy, gz);
+          if (v >= 0 && (gx == 0 || gx == N[0] - 1 || gy == 0 || gy == N[1] - 1 || gz == 0 ||
+                         gz == N[2] - 1))
+            L.kind[(size_t)v] = kDirichlet;
+        }
+  }
+  const int64_t P2 = 2 * (int64_t)p;
+  for (int64_t fz = f0[2]; fz < f0[2] + F[2]; ++fz)
+    for (int64_t fy = f0[1]; fy < f0[1] + F[1]; ++fy)
+      for (int64_t fx = f0[0]; fx < f0[0] + F[0]; ++fx) {
+        const int64_t f[3] = {fx, fy, fz};
+        const int32_t v = fnum(fx, fy, fz);
+        bool bnd = false;
+        for (int d = 0; d < 3; ++d) bnd = bnd || f[d] == 0 || f[d] == P2 * n[d];
+        if (dir && bnd) {
+          L.kind[(size_t)v] = kDirichlet;
+          continue;
+        }
+        int lo[3], hi[3];  // candidate coarse cells per direction
+        for (int d = 0; d < 3; ++d) {
+          lo[d] = (int)std::max<int64_t>(f[d] % P2 == 0 ? f[d] / P2 - 1 : f[d] / P2, 0);
+          hi[d] = (int)std::min<int64_t>(f[d] / P2, n[d] - 1);
+        }
+        bool hang = false;
+        for (int cz = lo[2]; cz <= hi[2] && !hang; ++cz)
+          for (int cy = lo[1]; cy <= hi[1] && !hang; ++cy)
+            for (int cx = lo[0]; cx <= hi[0] && !hang; ++cx) hang = !refined(cx, cy, cz);
+        if (hang) {
+          L.kind[(size_t)v] = kHanging;
+          ++L.nslaves;
+        }
+      }
+
+  if (with_sets && L.nslaves > 0) {
+    const std::vector<double> xi = gll_points(p);
+    std::vector<uint8_t> taken((size_t)L.ndofs, 0);
+    std::vector<double> L1(np), L2(np);
+    int64_t assigned = 0;
+    for (int64_t e = 0; e < L.ncoarse_cells; ++e) {
+      const int c[3] = {(int)L.origin[3 * e], (int)L.origin[3 * e + 1], (int)L.origin[3 * e + 2]};
+      for (int d = 0; d < 3; ++d)
+        for (int side = 0; side < 2; ++side) {
+          int nb[3] = {c[0], c[1], c[2]};
+          nb[d] += side ? 1 : -1;
+          if (nb[d] < 0 || nb[d] >= n[d] || !refined(nb[0], nb[1], nb[2])) continue;
+          const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;  // tangential directions
+          ConstraintSet cs{};
+          cs.m0 = (int32_t)L.cidx.size();
+          cs.nm = np * np;
+          int64_t g[3];
+          g[d] = (int64_t)(c[d] + side) * p;
+          for (int b = 0; b < np; ++b)
+            for (int a = 0; a < np; ++a) {
+              g[t1] = (int64_t)c[t1] * p + a;
+              g[t2] = (int64_t)c[t2] * p + b;
+              const int32_t v = cat(g[0], g[1], g[2]);
+              L.cidx.push_back(L.kind[(size_t)v] == kDirichlet ? -1 : v);
+            }
+          cs.s0 = (int32_t)L.cidx.size();
+          cs.w0 = (int64_t)L.W.size();
+          int64_t f[3];
+          f[d] = 2 * g[d];
+          for (int o2 = 0; o2 <= 2 * p; ++o2)
+            for (int o1 = 0; o1 <= 2 * p; ++o1) {
+              f[t1] = P2 * c[t1] + o1;
+              f[t2] = P2 * c[t2] + o2;
+              const int32_t v = fnum(f[0], f[1], f[2]);
+              if (L.kind[(size_t)v] != kHanging || taken[(size_t)v]) continue;
+              taken[(size_t)v] = 1;
+              L.cidx.push_back(v);
+              lagrange_at(xi, coarse_ref(o1, p, xi), L1.data());
+              lagrange_at(xi, coarse_ref(o2, p, xi), L2.data());
+              for (int b = 0; b < np; ++b)
+                for (int a = 0; a < np; ++a) L.W.push_back(L1[a] * L2[b]);
+            }
+          cs.ns = (int32_t)L.cidx.size() - cs.s0;
+          if (cs.ns == 0) {
+            L.cidx.resize((size_t)cs.m0);
+            continue;
+          }
+          assigned += cs.ns;
+          L.sets.push_back(cs);
+        }
+    }
+    if (assigned != L.nslaves) return fail(MF_ERR_ARG, "internal: hanging nodes left unassigned");
+  }
+  out = std::move(L);
+  return MF_OK;
+}
+
+}  // namespace
+}  // namespace mf
+
+using namespace mf;
+
+extern "C" {
+
+int mf_refined_sizes(const mf_refined_mesh* mesh, int p, int64_t* ndofs, int64_t* ncells,
+                     int64_t* nslaves, int64_t* nsets) {
+  if (int s = validate_refined(mesh, p)) return s;
+  RefinedLayout L;
+  if (int s = build_layout(*mesh, p, nsets != nullptr, L)) return s;
+  if (ndofs) *ndofs = L.ndofs;
+  if (ncells) *ncells = L.ncells;
+  if (nslaves) *nslaves = L.nslaves;
+  if (nsets) *nsets = (int64_t)L.sets.size();
+  return MF_OK;
+}
+
+int mf_refined_layout(const mf_refined_mesh* mesh, int p, int32_t* map, uint8_t* kind) {
+  if (int s = validate_refined(mesh, p)) return s;
+  RefinedLayout L;
+  if (int s = build_layout(*mesh, p, false, L)) return s;
+  if (map) std::memcpy(map, L.map.data(), L.map.size() * sizeof(int32_t));
+  if (kind) std::memcpy(kind, L.kind.data(), L.kind.size());
+  return MF_OK;
+}
+
+int mf_refined_quad_points(const mf_refined_mesh* mesh, int q, double* xq) {
+  if (int s = validate_refined(mesh, 1)) return s;
+  if (q < 1 || q > kMaxP + 1 + kMaxQExtra) return fail(MF_ERR_UNSUPPORTED, "q out of range");
+  if (!xq) return fail(MF_ERR_ARG, "xq is NULL");
+  RefinedLayout L;
+  if (int s = build_layout(*mesh, 1, false, L)) return s;
+  const Rule1D g = gauss_rule(q);
+  double Lm[9];
+  lin_matrix(mesh->coarse, Lm);
+  double h[3];
+  for (int d = 0; d < 3; ++d) h[d] = (mesh->coarse.hi[d] - mesh->coarse.lo[d]) / mesh->coarse.n[d];
+  int64_t idx = 0;
+  for (int64_t e = 0; e < L.ncells; ++e)
+    for (int a3 = 0; a3 < q; ++a3)
+      for (int a2 = 0; a2 < q; ++a2)
+        for (int a1 = 0; a1 < q; ++a1) {
+          const int a[3] = {a1, a2, a3};
+          double y[3];
+          for (int d = 0; d < 3; ++d)
+            y[d] = mesh->coarse.lo[d] +
+                   h[d] * (L.origin[3 * e + d] + L.size[e] * 0.5 * (g.x[a[d]] + 1.0));
+          for (int r = 0; r < 3; ++r)
+            xq[idx * 3 + r] = Lm[3 * r] * y[0] + Lm[3 * r + 1] * y[1] + Lm[3 * r + 2] * y[2];
+          ++idx;
+        }
+  return MF_OK;
+}
+
+int mf_create_refined_operator(const mf_refined_mesh* mesh, int p, int q, double mu,
+                               const double* Vq, double sigma, mf_operator** out) {
+  if (!out) return fail(MF_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (int s = validate_refined(mesh, p)) return s;
+  if (q < p + 1 || q > p + kMaxQExtra)
+    return fail(MF_ERR_UNSUPPORTED, "q must be in [p+1, p+3]: the collocation factorisation needs q >= p+1");
+  if (!std::isfinite(mu) || !std::isfinite(sigma)) return fail(MF_ERR_ARG, "mu and sigma must be finite");
+  if (!apply_f64_supported(p, q)) return fail(MF_ERR_UNSUPPORTED, "no kernel built for this (p, q)");
+  RefinedLayout L;
+  if (int s = build_layout(*mesh, p, true, L)) return s;
+
+  Operator* op = new (std::nothrow) Operator();
+  if (!op) return fail(MF_ERR_OOM, "host allocation failed");
+  op->p = p;
+  op->q = q;
+  op->np = p + 1;
+  op->nq = q;
+  op->mu = mu;
+  op->sigma = sigma;
+  op->cfg = -1;
+  op->t = make_tables(p, q);
+  op->ndofs = L.ndofs;
+  op->ncells = L.ncells;
+  op->box = false;  // the general-geometry kernel: explicit map, per-cell factors
+  op->refined = true;
+  op->nsets = (int64_t)L.sets.size();
+  for (const ConstraintSet& cs : L.sets) {
+    op->max_slaves = std::max(op->max_slaves, (int)cs.ns);
+    op->max_masters = std::max(op->max_masters, (int)cs.nm);
+  }
+  const int np3 = op->np * op->np * op->np, nq3 = q * q * q;
+  const int64_t E = L.ncells;
+
+  // zero-Dirichlet nodes read as zero and are skipped on assembly (empty masters)
+  std::vector<int32_t> map(L.map);
+  for (auto& v : map)
+    if (L.kind[(size_t)v] == kDirichlet) v = -1;
+  // per-cell geometry (eq. sjacobian / eq. mjacobian) for cells of two sizes
+  double Lm[9];
+  lin_matrix(mesh->coarse, Lm);
+  std::vector<double> geo((size_t)E * 6), vq((size_t)E * nq3);
+  double hc[3];
+  for (int d = 0; d < 3; ++d) hc[d] = (mesh->coarse.hi[d] - mesh->coarse.lo[d]) / mesh->coarse.n[d];
+  for (int64_t e = 0; e < E; ++e) {
+    const double h[3] = {hc[0] * L.size[e], hc[1] * L.size[e], hc[2] * L.size[e]};
+    const double detJ = cell_factor(Lm, h, mu, &geo[(size_t)e * 6]);
+    for (int k = 0; k < nq3; ++k) {
+      const double v = Vq ? Vq[e * nq3 + k] : 0.0;
+      if (!std::isfinite(v)) {
+        delete op;
+        return fail(MF_ERR_ARG, "Vq holds a non-finite value");
+      }
+      vq[(size_t)(e * nq3 + k)] = detJ * (v + sigma);
+    }
+  }
+  bool diag = true;  // axis-aligned cells: the off-diagonal factor entries vanish exactly
+  for (int64_t e = 0; e < E; ++e)
+    diag = diag && geo[(size_t)e * 6 + 1] == 0.0 && geo[(size_t)e * 6 + 2] == 0.0 &&
+           geo[(size_t)e * 6 + 4] == 0.0;
+  op->map_box = diag;
+  std::vector<int32_t> order((size_t)E);
+  for (int64_t e = 0; e < E; ++e) order[(size_t)e] = (int32_t)e;
+
+  hipError_t err = hipGetDevice(&op->device);
+  if (err != hipSuccess) {
+    delete op;
+    return hip_fail(err, "hipGetDevice");
+  }
+  auto alloc_copy = [&](void** dst, const void* src, size_t bytes) -> int {
+    if (bytes == 0) return MF_OK;
+    hipError_t e2 = hipMalloc(dst, bytes);
+    if (e2 != hipSuccess) {
+      *dst = nullptr;
+      return e2 == hipErrorOutOfMemory ? fail(MF_ERR_OOM, "hipMalloc failed") : hip_fail(e2, "hipMalloc");
+    }
+    e2 = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    if (e2 != hipSuccess) return hip_fail(e2, "hipMemcpy");
+    return MF_OK;
+  };
+  int s = alloc_copy((void**)&op->d_map, map.data(), map.size() * sizeof(int32_t));
+  if (!s) s = alloc_copy((void**)&op->d_order, order.data(), order.size() * sizeof(int32_t));
+  if (!s) s = alloc_copy((void**)&op->d_geo, geo.data(), geo.size() * sizeof(double));
+  if (!s) s = alloc_copy((void**)&op->d_vq, vq.data(), vq.size() * sizeof(double));
+  if (!s) s = alloc_copy((void**)&op->d_sets, L.sets.data(), L.sets.size() * sizeof(ConstraintSet));
+  if (!s) s = alloc_copy((void**)&op->d_cidx, L.cidx.data(), L.cidx.size() * sizeof(int32_t));
+  if (!s) s = alloc_copy((void**)&op->d_cw, L.W.data(), L.W.size() * sizeof(double));
+  if (s) {
+    mf_destroy_operator(reinterpret_cast<mf_operator*>(op));
+    return s;
+  }
+  *out = reinterpret_cast<mf_operator*>(op);
+  return MF_OK;
+}
+
+static int constraints_common(mf_operator* handle, double* X, int nvec, int64_t ld, void* stream,
+                              bool transpose) {
+  if (!handle || !X) return fail(MF_ERR_ARG, "operator and X must be non-NULL");
+  if (nvec < 1 || ld < nvec) return fail(MF_ERR_ARG, "need nvec >= 1 and ld >= nvec");
+  if (nvec > 64 * 65535) return fail(MF_ERR_UNSUPPORTED, "nvec too large");
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  if (op->nsets == 0) return MF_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t err = transpose ? launch_constraints_condense(*op, X, nvec, ld, s)
+                             : launch_constraints_distribute(*op, X, nvec, ld, s);
+  if (err != hipSuccess) return hip_fail(err, "constraint kernel launch");
+  return MF_OK;
+}
+
+int mf_constraints_distribute(mf_operator* op, double* X, int nvec, int64_t ld, void* stream) {
+  return constraints_common(op, X, nvec, ld, stream, false);
+}
+
+int mf_constraints_condense(mf_operator* op, double* Y, int nvec, int64_t ld, void* stream) {
+  return constraints_common(op, Y, nvec, ld, stream, true);
+}
+
+}  // extern "C"

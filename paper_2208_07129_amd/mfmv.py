@@ -38,7 +38,10 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_mlp_gemm", "mf_cell_gather", "mf_cell_scatter", "mf_mse_grad", "mf_row_sums",
            "mf_adam", "mf_symmetrize", "mf_to_bf16", "mf_fill_f32",
            # include/mfcheb.h
-           "mf_gll_mass", "mf_cheb_step", "mf_sym_eig")
+           "mf_gll_mass", "mf_cheb_step", "mf_sym_eig",
+           # include/mfrefine.h
+           "mf_refined_sizes", "mf_refined_layout", "mf_refined_quad_points",
+           "mf_create_refined_operator", "mf_constraints_distribute", "mf_constraints_condense")
 
 
 class MfError(RuntimeError):
@@ -50,6 +53,10 @@ class MfError(RuntimeError):
 class MeshC(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("bc", ctypes.c_int32), ("lin", ctypes.c_double * 9)]
+
+
+class RefinedMeshC(ctypes.Structure):
+    _fields_ = [("coarse", MeshC), ("rlo", ctypes.c_int32 * 3), ("rhi", ctypes.c_int32 * 3)]
 
 
 _lib = None
@@ -64,6 +71,7 @@ def lib() -> ctypes.CDLL:
         P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
         F32 = ctypes.c_float
         MP = ctypes.POINTER(MeshC)
+        RP = ctypes.POINTER(RefinedMeshC)
         sig = {
             "mf_num_dofs": (I, [MP, I, ctypes.POINTER(I64)]),
             "mf_num_cells": (I, [MP, ctypes.POINTER(I64)]),
@@ -110,6 +118,13 @@ def lib() -> ctypes.CDLL:
             "mf_gll_mass": (I, [P, I, P, P]),
             "mf_cheb_step": (I, [P, P, P, P, P, I, I64, D, D, D, P]),
             "mf_sym_eig": (I, [I, P, I64, P, P, I64, D, P, P]),
+            "mf_refined_sizes": (I, [RP, I, ctypes.POINTER(I64), ctypes.POINTER(I64),
+                                     ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+            "mf_refined_layout": (I, [RP, I, P, P]),
+            "mf_refined_quad_points": (I, [RP, I, P]),
+            "mf_create_refined_operator": (I, [RP, I, I, D, P, D, ctypes.POINTER(P)]),
+            "mf_constraints_distribute": (I, [P, P, I, I64, P]),
+            "mf_constraints_condense": (I, [P, P, I, I64, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -260,6 +275,93 @@ class Operator:
         fn(X.data_ptr(), Y.data_ptr(), nvec, max(ldx, nvec), max(ldy, nvec), PRECISIONS[precision],
            stream)
         return Y
+
+
+# ----------------------------------------------------------- include/mfrefine.h
+def refined_mesh_c(rmesh) -> RefinedMeshC:
+    """Convert a workloads.RefinedMesh (n, lo, hi, bc, lin, rlo, rhi) to the C struct."""
+    m = RefinedMeshC()
+    m.coarse = mesh_c(rmesh)
+    for d in range(3):
+        m.rlo[d] = int(rmesh.rlo[d])
+        m.rhi[d] = int(rmesh.rhi[d])
+    return m
+
+
+def refined_sizes(rmesh, p: int) -> dict:
+    """Nodes, cells, hanging nodes and constraint sets of a refined mesh of degree p."""
+    v = [ctypes.c_int64() for _ in range(4)]
+    _check(lib().mf_refined_sizes(ctypes.byref(refined_mesh_c(rmesh)), p, *map(ctypes.byref, v)))
+    return dict(zip(("ndofs", "ncells", "nslaves", "nsets"), (x.value for x in v)))
+
+
+def refined_layout(rmesh, p: int):
+    """(cell-to-node map E x (p+1)^3, node kinds: 0 free, 1 zero-Dirichlet, 2 hanging)."""
+    sz = refined_sizes(rmesh, p)
+    cmap = np.empty((sz["ncells"], (p + 1) ** 3), dtype=np.int32)
+    kind = np.empty(sz["ndofs"], dtype=np.uint8)
+    _check(lib().mf_refined_layout(ctypes.byref(refined_mesh_c(rmesh)), p, cmap.ctypes.data,
+                                   kind.ctypes.data))
+    return cmap, kind
+
+
+def refined_quad_points(rmesh, q: int) -> np.ndarray:
+    ncells = refined_sizes(rmesh, 1)["ncells"]
+    out = np.empty((ncells, q ** 3, 3))
+    _check(lib().mf_refined_quad_points(ctypes.byref(refined_mesh_c(rmesh)), q, out.ctypes.data))
+    return out
+
+
+class RefinedOperator(Operator):
+    """A = mu K + M_{V+sigma} on a once-refined box with hanging-node constraints: ``apply``
+    is A_u (hanging rows as ordinary rows); ``distribute`` / ``condense`` are C and C^T;
+    ``apply_constrained`` runs the three in order."""
+
+    def __init__(self, rmesh, p: int, q: int, mu: float = 0.5, Vq: Optional[np.ndarray] = None,
+                 sigma: float = 0.0):
+        self._h = ctypes.c_void_p()
+        self.mesh, self.p, self.q, self.mu, self.sigma = rmesh, p, q, mu, sigma
+        sz = refined_sizes(rmesh, p)
+        self.nslaves, self.nsets = sz["nslaves"], sz["nsets"]
+        vptr = None
+        if Vq is not None:
+            self._vq = np.ascontiguousarray(Vq, dtype=np.float64).reshape(-1)
+            if self._vq.size != sz["ncells"] * q ** 3:
+                raise ValueError("Vq must hold E*q^3 values")
+            vptr = self._vq.ctypes.data
+        _check(lib().mf_create_refined_operator(ctypes.byref(refined_mesh_c(rmesh)), p, q,
+                                                float(mu), vptr, float(sigma),
+                                                ctypes.byref(self._h)))
+        self.ndofs, self.ncells = sz["ndofs"], sz["ncells"]
+
+    @classmethod
+    def from_workload(cls, w):
+        Vq = w.V(refined_quad_points(w.mesh, w.q)) if w.V is not None else None
+        return cls(w.mesh, w.p, w.q, w.mu, Vq, w.sigma)
+
+    def _ptr(self, V, name):
+        ptr, n, k, ld = _mv(V, name)
+        if n != self.ndofs:
+            raise ValueError(f"{name} must have ndofs rows")
+        return ptr, k, ld
+
+    def distribute(self, X, stream=None):
+        """C: hanging rows of X := W_I X_M, in place."""
+        ptr, k, ld = self._ptr(X, "X")
+        _check(lib().mf_constraints_distribute(self._h, ptr, k, ld, _stream_ptr(stream)))
+        return X
+
+    def condense(self, Y, stream=None):
+        """C^T: Y_M += W_I^T Y_S, Y_S := 0, in place."""
+        ptr, k, ld = self._ptr(Y, "Y")
+        _check(lib().mf_constraints_condense(self._h, ptr, k, ld, _stream_ptr(stream)))
+        return Y
+
+    def apply_constrained(self, X, Y=None, stream=None):
+        """Y := C^T A_u C X; the hanging rows of X are overwritten by C X."""
+        self.distribute(X, stream)
+        Y = self.apply(X, Y, stream=stream)
+        return self.condense(Y, stream)
 
 
 def zero_ptr(Y_ptr: int, nrows: int, ncols: int, ld: int, stream=None):

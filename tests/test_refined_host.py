@@ -1,0 +1,69 @@
+"""Host logic of the refined-mesh C ABI (no GPU): numbering, node kinds, cell
+order and quadrature points agree with the hanging-node oracle's independent
+construction; argument errors are reported before any device work."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle.hanging_oracle import RefinedOracle, DIRICHLET, HANGING
+from paper_2208_07129_amd import mfmv
+from workloads import RefinedMesh, BC_NONE, BC_DIRICHLET0, BC_PERIODIC, refined_config
+
+SHEAR = np.array([[1.0, 0.3, -0.2], [0.1, 0.9, 0.25], [-0.15, 0.2, 1.1]])
+
+CASES = [
+    dict(n=(3, 3, 3), rlo=(1, 1, 1), rhi=(2, 2, 2)),      # refined core
+    dict(n=(4, 3, 2), rlo=(0, 1, 0), rhi=(2, 3, 1)),      # block on the boundary
+    dict(n=(3, 2, 2), rlo=(0, 0, 0), rhi=(3, 2, 2)),      # everything refined
+    dict(n=(3, 2, 2), rlo=(1, 0, 0), rhi=(1, 2, 2)),      # nothing refined
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("bc", [BC_NONE, BC_DIRICHLET0])
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_layout_matches_oracle(case, bc, p):
+    rm = RefinedMesh(case["n"], (0.0, -1.0, 0.5), (1.0, 1.0, 2.0), case["rlo"], case["rhi"], bc,
+                     SHEAR)
+    orc = RefinedOracle(rm, p, p + 1, 0.5)
+    sz = mfmv.refined_sizes(rm, p)
+    assert sz["ndofs"] == orc.ndofs and sz["ncells"] == orc.E
+    assert sz["nslaves"] == int(orc.hanging.sum())
+    cmap, kind = mfmv.refined_layout(rm, p)
+    np.testing.assert_array_equal(cmap, orc.map)
+    np.testing.assert_array_equal(kind == DIRICHLET, orc.constrained)
+    np.testing.assert_array_equal(kind == HANGING, orc.hanging)
+    np.testing.assert_allclose(mfmv.refined_quad_points(rm, p + 1), orc.xq, atol=1e-13)
+    if sz["nslaves"]:
+        # one set per coarse face toward the refined block that still has unassigned slaves
+        assert 1 <= sz["nsets"] <= 6 * orc.layout["ncoarse_cells"]
+
+
+def test_refined_workload_sizes():
+    w = refined_config()
+    sz = mfmv.refined_sizes(w.mesh, w.p)
+    assert (sz["ncells"], sz["ndofs"]) == (1512 + 1728, 735159)
+    assert sz["nslaves"] > 0 and sz["nsets"] == 6 * 36
+
+
+def test_argument_errors_without_device_work():
+    L = mfmv.lib()
+    good = RefinedMesh((3, 3, 3), (0, 0, 0), (1, 1, 1), (1, 1, 1), (2, 2, 2), BC_DIRICHLET0)
+    out = ctypes.c_int64()
+    per = RefinedMesh((3, 3, 3), (0, 0, 0), (1, 1, 1), (1, 1, 1), (2, 2, 2), BC_PERIODIC)
+    assert L.mf_refined_sizes(ctypes.byref(mfmv.refined_mesh_c(per)), 2, ctypes.byref(out),
+                              None, None, None) == mfmv.MF_ERR_UNSUPPORTED
+    for rlo, rhi in [((-1, 1, 1), (2, 2, 2)), ((1, 1, 1), (4, 2, 2)), ((2, 1, 1), (1, 2, 2))]:
+        bad = RefinedMesh((3, 3, 3), (0, 0, 0), (1, 1, 1), rlo, rhi, BC_NONE)
+        assert L.mf_refined_sizes(ctypes.byref(mfmv.refined_mesh_c(bad)), 2, ctypes.byref(out),
+                                  None, None, None) == mfmv.MF_ERR_ARG
+    assert L.mf_refined_sizes(ctypes.byref(mfmv.refined_mesh_c(good)), 11, ctypes.byref(out),
+                              None, None, None) == mfmv.MF_ERR_UNSUPPORTED
+    assert L.mf_refined_sizes(None, 2, ctypes.byref(out), None, None, None) == mfmv.MF_ERR_ARG
+    h = ctypes.c_void_p()
+    assert L.mf_create_refined_operator(ctypes.byref(mfmv.refined_mesh_c(good)), 2, 2, 0.5, None,
+                                        0.0, ctypes.byref(h)) == mfmv.MF_ERR_UNSUPPORTED
+    assert not h.value
+    assert L.mf_constraints_distribute(None, None, 1, 1, None) == mfmv.MF_ERR_ARG
+    assert L.mf_constraints_condense(None, None, 1, 1, None) == mfmv.MF_ERR_ARG

@@ -182,3 +182,43 @@ def config5() -> Workload:
     m = BoxMesh(n=(20, 20, 20), lo=(0, 0, 0), hi=(10, 10, 10), bc=BC_PERIODIC)
     return Workload("periodic-box10-20^3-p6q7-shift0.5", m, 6, 7, 0.5, gaussian_wells((1005, 0)),
                     0.5, 128, (1005, 99))
+
+
+@dataclasses.dataclass
+class RefinedMesh:
+    """A coarse box mesh (n, lo, hi, bc, lin as in BoxMesh) whose cells in the index box
+    [rlo, rhi) are each split into 2 x 2 x 2 children (hanging nodes on the interface)."""
+    n: Sequence[int]
+    lo: Sequence[float]
+    hi: Sequence[float]
+    rlo: Sequence[int]
+    rhi: Sequence[int]
+    bc: int = BC_DIRICHLET0
+    lin: Optional[np.ndarray] = None
+
+
+@dataclasses.dataclass
+class RefinedWorkload:
+    name: str
+    mesh: RefinedMesh
+    p: int
+    q: int
+    mu: float
+    V: Callable[[np.ndarray], np.ndarray]
+    sigma: float
+    nvec: int
+    x_seed: tuple
+
+    def X(self, ndofs: int, nvec: Optional[int] = None) -> np.ndarray:
+        return random_multivector(self.x_seed, ndofs, nvec or self.nvec)
+
+
+def refined_config(nvec: int = 64) -> RefinedWorkload:
+    """Adaptively refined stand-in for the paper's refined-mesh runs: zero-Dirichlet [0,10]^3,
+    12^3 coarse cells with the central 6^3 block refined once (1,512 coarse + 1,728 fine
+    cells, 735,159 nodes), p=6, q=7, 8 Gaussian wells, nvec=64."""
+    m = RefinedMesh(n=(12, 12, 12), lo=(0, 0, 0), hi=(10, 10, 10), rlo=(3, 3, 3), rhi=(9, 9, 9),
+                    bc=BC_DIRICHLET0)
+    return RefinedWorkload("refined-box10-12^3-core6^3-p6q7-dirichlet", m, 6, 7, 0.5,
+                           gaussian_wells((1006, 0)), 0.0, nvec, (1006, 99))
+
