@@ -402,7 +402,7 @@ def refined_leg(a) -> dict:
                                 "peak": PEAK_HBM_GBS},
             "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
                          "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
-                         "kernel": "apply_f64_kernel"}}
+                         "kernel": "apply_box_map_kernel"}}
 
 
 def batched_leg(a) -> dict:

@@ -266,6 +266,7 @@ void mf_destroy_operator(mf_operator* handle) {
   if (op->d_sets) (void)hipFree(op->d_sets);
   if (op->d_cidx) (void)hipFree(op->d_cidx);
   if (op->d_cw) (void)hipFree(op->d_cw);
+  if (op->d_zrows) (void)hipFree(op->d_zrows);
   delete op;
 }
 
@@ -335,8 +336,10 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
   }
   hipError_t err = hipSuccess;
   if (!accumulate) {
-    err = op->box ? launch_zero_shared_rows(Y, op->nodes, op->p, nvec, ldy, s)
-                  : launch_zero_rows(Y, op->ndofs, nvec, ldy, s);
+    // the box kernels store cell-interior rows and add to the others
+    err = op->box       ? launch_zero_shared_rows(Y, op->nodes, op->p, nvec, ldy, s)
+        : op->map_box ? launch_zero_listed_rows(Y, op->d_zrows, op->nzrows, nvec, ldy, s)
+                      : launch_zero_rows(Y, op->ndofs, nvec, ldy, s);
     if (err != hipSuccess) return hip_fail(err, "zero kernel launch");
   }
   if (ev) (void)hipEventRecord(ev[1], s);

@@ -91,6 +91,8 @@ struct Operator {
   ConstraintSet* d_sets = nullptr;
   int32_t* d_cidx = nullptr;  // slave and master node indices (-1: zero-Dirichlet master)
   double* d_cw = nullptr;     // the W_I, concatenated
+  int32_t* d_zrows = nullptr; // rows that are not cell-interior (the map kernel's zero fill)
+  int64_t nzrows = 0;
   // optional per-launch timing (diagnostics): event triples around the zero
   // fill and the fused kernel of each apply, in a ring
   std::vector<hipEvent_t> ev;
@@ -175,6 +177,9 @@ hipError_t launch_constraints_distribute(const Operator& op, double* X, int nvec
                                          hipStream_t s);
 hipError_t launch_constraints_condense(const Operator& op, double* Y, int nvec, int64_t ld,
                                        hipStream_t s);
+// Y[rows[i]][0 .. ncols) := 0 for i < n (a kernel, graph-capturable).
+hipError_t launch_zero_listed_rows(double* Y, const int32_t* rows, int64_t n, int ncols, int64_t ld,
+                                   hipStream_t s);
 // mu det J J^-1 J^-T of an affine cell with J = L diag(h / 2), as the six
 // entries (00, 01, 02, 11, 12, 22); returns det J.
 double cell_factor(const double L[9], const double h[3], double mu, double G6[6]);

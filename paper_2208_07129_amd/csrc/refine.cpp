@@ -351,6 +351,19 @@ int mf_create_refined_operator(const mf_refined_mesh* mesh, int p, int q, double
     diag = diag && geo[(size_t)e * 6 + 1] == 0.0 && geo[(size_t)e * 6 + 2] == 0.0 &&
            geo[(size_t)e * 6 + 4] == 0.0;
   op->map_box = diag;
+  // rows the map kernel does not store: every row that is not the interior
+  // node of a cell (face, hanging and zero-Dirichlet rows)
+  std::vector<uint8_t> inner((size_t)L.ndofs, 0);
+  const int np = op->np;
+  for (int64_t e = 0; e < E; ++e)
+    for (int i3 = 1; i3 < np - 1; ++i3)
+      for (int i2 = 1; i2 < np - 1; ++i2)
+        for (int i1 = 1; i1 < np - 1; ++i1)
+          inner[(size_t)L.map[(size_t)(e * np3 + i1 + np * (i2 + np * i3))]] = 1;
+  std::vector<int32_t> zrows;
+  for (int64_t r = 0; r < L.ndofs; ++r)
+    if (!inner[(size_t)r]) zrows.push_back((int32_t)r);
+  op->nzrows = (int64_t)zrows.size();
   std::vector<int32_t> order((size_t)E);
   for (int64_t e = 0; e < E; ++e) order[(size_t)e] = (int32_t)e;
 
@@ -377,6 +390,7 @@ int mf_create_refined_operator(const mf_refined_mesh* mesh, int p, int q, double
   if (!s) s = alloc_copy((void**)&op->d_sets, L.sets.data(), L.sets.size() * sizeof(ConstraintSet));
   if (!s) s = alloc_copy((void**)&op->d_cidx, L.cidx.data(), L.cidx.size() * sizeof(int32_t));
   if (!s) s = alloc_copy((void**)&op->d_cw, L.W.data(), L.W.size() * sizeof(double));
+  if (!s) s = alloc_copy((void**)&op->d_zrows, zrows.data(), zrows.size() * sizeof(int32_t));
   if (s) {
     mf_destroy_operator(reinterpret_cast<mf_operator*>(op));
     return s;
