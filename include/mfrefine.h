@@ -29,8 +29,8 @@
  * The operator A = mu K + M_{V+sigma} on the conforming space is
  *   Y = C^T A_u C X        (eq. AU with one partition)
  * where A_u assembles every cell with hanging nodes as ordinary rows.  With
- * the handle of mf_create_refined_operator it runs as three stream-ordered
- * calls: mf_constraints_distribute (C, in place on X), mf_apply (A_u through
+ * the handle of mf_create_refined_operator it runs as mf_apply_constrained,
+ * or as three stream-ordered calls: mf_constraints_distribute (C, in place on X), mf_apply (A_u through
  * the cell-to-node map: the box kernel's body for axis-aligned cells, the
  * general-geometry kernel for sheared cells or after mf_set_launch with
  * general != 0; zero-Dirichlet rows read as zero and written as zero) and
@@ -39,9 +39,11 @@
  * X[i*ld + j]) device arrays.  Every call returns MF_OK or a negative
  * mf_status (message in mf_last_error()).
  *
- * A refined operator supports mf_apply / mf_apply_add in MF_FP64 only; the
- * calls built on the uniform grid (mf_diagonal, mf_gll_mass, mf_cheb_step,
- * mf_cell_gather / mf_cell_scatter, batches, matrix-core precisions) return
+ * A refined operator supports mf_apply / mf_apply_add in MF_FP64, and in
+ * MF_FP32_MFMA on axis-aligned cells (FP32 cell arrays with power-of-two
+ * scaling per cell and column, the FP32 vector contractions, FP64 assembly);
+ * the calls built on the uniform grid (mf_diagonal, mf_gll_mass,
+ * mf_cheb_step, mf_cell_gather / mf_cell_scatter, batches, BF16) return
  * MF_ERR_UNSUPPORTED for it.
  */
 #ifndef MFREFINE_H
@@ -90,6 +92,16 @@ int mf_refined_quad_points(const mf_refined_mesh* mesh, int q, double* xq);
  * (p, q, periodic, size), MF_ERR_OOM, MF_ERR_HIP. */
 int mf_create_refined_operator(const mf_refined_mesh* mesh, int p, int q, double mu,
                                const double* Vq, double sigma, mf_operator** out);
+
+/* Y := C^T A_u C X, the constrained product of eq. AU, in one call: the three
+ * steps above, in order on `stream`.  X (ldx >= nvec) is in/out: its hanging rows are
+ * overwritten with C X; Y (ldy >= nvec) is overwritten (hanging and
+ * zero-Dirichlet rows 0).  X and Y must not overlap.  FP64.  On an operator
+ * of mf_create_operator it is mf_apply.  Allocates nothing.  Errors:
+ * MF_ERR_ARG (NULL, nvec < 1, ld < nvec, overlap), MF_ERR_UNSUPPORTED (nvec
+ * above 4,194,240), MF_ERR_HIP. */
+int mf_apply_constrained(mf_operator* op, double* X, double* Y, int nvec, int64_t ldx,
+                         int64_t ldy, void* stream);
 
 /* X_S := W_I X_M for every set I: the action of C (Sec. 3.2.2), in place on
  * the slave rows of X (columns [0, nvec), row stride ld >= nvec); every other

@@ -286,8 +286,10 @@ static bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes)
   return ca < cb + bbytes && cb < ca + abytes;
 }
 
-static int apply_common(mf_operator* handle, const double* X, double* Y, int nvec, int64_t ldx,
-                        int64_t ldy, int prec, void* stream, bool accumulate) {
+}  // extern "C"
+
+int mf::apply_dispatch(mf_operator* handle, const double* X, double* Y, int nvec, int64_t ldx,
+                       int64_t ldy, int prec, void* stream, bool accumulate) {
   if (!handle) return fail(MF_ERR_ARG, "operator is NULL");
   if (!X || !Y) return fail(MF_ERR_ARG, "X and Y must be non-NULL device pointers");
   if (nvec < 1) return fail(MF_ERR_ARG, "nvec must be >= 1");
@@ -299,8 +301,11 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
   if (prec != MF_FP64 && prec != MF_FP32_MFMA && prec != MF_BF16_MFMA)
     return fail(MF_ERR_UNSUPPORTED, "unknown precision");
   const bool mixed = prec != MF_FP64;
-  if (mixed && !op->box)
-    return fail(MF_ERR_UNSUPPORTED, "mixed precision is built for axis-aligned cells only");
+  // mixed precision: axis-aligned cells; on a refined map FP32 vector only
+  const bool map32 = mixed && op->map_box && prec == MF_FP32_MFMA;
+  if (mixed && !op->box && !map32)
+    return fail(MF_ERR_UNSUPPORTED,
+                "mixed precision is built for axis-aligned cells only (FP32 on refined meshes)");
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   ApplyLaunch a{};
@@ -343,7 +348,8 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
     if (err != hipSuccess) return hip_fail(err, "zero kernel launch");
   }
   if (ev) (void)hipEventRecord(ev[1], s);
-  err = mixed ? launch_apply_mixed(*op, a, prec, s)
+  err = map32   ? launch_apply_box_map32(*op, a, s)
+        : mixed ? launch_apply_mixed(*op, a, prec, s)
               : (op->box       ? launch_apply_box(*op, a, s)
                  : op->map_box ? launch_apply_box_map(*op, a, s)
                                : launch_apply_f64(*op, a, s));
@@ -352,14 +358,16 @@ static int apply_common(mf_operator* handle, const double* X, double* Y, int nve
   return MF_OK;
 }
 
+extern "C" {
+
 int mf_apply(mf_operator* handle, const double* X, double* Y, int nvec, int64_t ldx, int64_t ldy,
              int prec, void* stream) {
-  return apply_common(handle, X, Y, nvec, ldx, ldy, prec, stream, /*accumulate=*/false);
+  return apply_dispatch(handle, X, Y, nvec, ldx, ldy, prec, stream, /*accumulate=*/false);
 }
 
 int mf_apply_add(mf_operator* handle, const double* X, double* Y, int nvec, int64_t ldx,
                  int64_t ldy, int prec, void* stream) {
-  return apply_common(handle, X, Y, nvec, ldx, ldy, prec, stream, /*accumulate=*/true);
+  return apply_dispatch(handle, X, Y, nvec, ldx, ldy, prec, stream, /*accumulate=*/true);
 }
 
 int mf_set_launch(mf_operator* handle, int general, int cfg) {

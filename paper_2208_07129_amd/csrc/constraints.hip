@@ -23,17 +23,20 @@ constexpr int kDistSlaves = 32;               // slaves per workgroup in C
 constexpr int kCondSlaves = 32;               // slaves per workgroup in C^T
 static_assert(kCondWaves * kMaxMPerWave >= (kMaxP + 1) * (kMaxP + 1), "masters of one face");
 
-__global__ void __launch_bounds__(kDistThreads)
-distribute_kernel(const ConstraintSet* __restrict__ sets, const int32_t* __restrict__ idx,
-                  const double* __restrict__ W, double* __restrict__ X, int64_t ld, int nvec) {
-  extern __shared__ double xm[];  // nm x kCT master values
-  const ConstraintSet cs = sets[blockIdx.x];
-  const int sb = blockIdx.z * kDistSlaves;
+// C for slaves [chunk * kDistSlaves, ...) of set `set`, columns of tile `tile`.
+__device__ __forceinline__ void distribute_item(const ConstraintSet* __restrict__ sets,
+                                                const int32_t* __restrict__ idx,
+                                                const double* __restrict__ W,
+                                                double* __restrict__ X, int64_t ld, int nvec,
+                                                double* __restrict__ xm, int64_t set, int tile,
+                                                int chunk) {
+  const ConstraintSet cs = sets[set];
+  const int sb = chunk * kDistSlaves;
   if (sb >= cs.ns) return;  // uniform over the workgroup
   const int se = min(cs.ns, sb + kDistSlaves);
   const int tid = threadIdx.x, lane = tid % kCT;
   const int wave = __builtin_amdgcn_readfirstlane(tid / kCT);
-  const int col = blockIdx.y * kCT + lane;
+  const int col = tile * kCT + lane;
   const bool ok = col < nvec;
   for (int m = wave; m < cs.nm; m += kDistThreads / kCT) {
     const int g = idx[cs.m0 + m];
@@ -47,6 +50,13 @@ distribute_kernel(const ConstraintSet* __restrict__ sets, const int32_t* __restr
     for (int m = 0; m < cs.nm; ++m) acc = fma(w[m], xm[m * kCT + lane], acc);
     if (ok) X[(int64_t)idx[cs.s0 + s] * ld + col] = acc;
   }
+}
+
+__global__ void __launch_bounds__(kDistThreads)
+distribute_kernel(const ConstraintSet* __restrict__ sets, const int32_t* __restrict__ idx,
+                  const double* __restrict__ W, double* __restrict__ X, int64_t ld, int nvec) {
+  extern __shared__ double xm[];  // nm x kCT master values
+  distribute_item(sets, idx, W, X, ld, nvec, xm, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 __global__ void __launch_bounds__(kCondThreads)
@@ -101,17 +111,23 @@ condense_kernel(const ConstraintSet* __restrict__ sets, const int32_t* __restric
 
 // kZeroRows rows per workgroup (a quarter per wavefront), one column per lane.
 constexpr int kZeroRows = 32;
-__global__ void __launch_bounds__(256)
-zero_listed_kernel(double* __restrict__ Y, const int32_t* __restrict__ rows, int64_t n, int ncols,
-                   int64_t ld) {
+__device__ __forceinline__ void zero_rows_item(double* __restrict__ Y,
+                                               const int32_t* __restrict__ rows, int64_t n,
+                                               int ncols, int64_t ld, int64_t block) {
   const int wave = threadIdx.x / kCT, lane = threadIdx.x % kCT;
-  const int64_t i0 = (int64_t)blockIdx.x * kZeroRows + wave * (kZeroRows / 4);
+  const int64_t i0 = block * kZeroRows + wave * (kZeroRows / 4);
   for (int k = 0; k < kZeroRows / 4; ++k) {
     const int64_t i = i0 + k;
     if (i >= n) return;
     double* row = Y + (int64_t)rows[i] * ld;
     for (int c = lane; c < ncols; c += kCT) row[c] = 0.0;
   }
+}
+
+__global__ void __launch_bounds__(256)
+zero_listed_kernel(double* __restrict__ Y, const int32_t* __restrict__ rows, int64_t n, int ncols,
+                   int64_t ld) {
+  zero_rows_item(Y, rows, n, ncols, ld, blockIdx.x);
 }
 
 }  // namespace

@@ -334,6 +334,22 @@ hipError_t launch_apply_box_map(const Operator& op, const ApplyLaunch& a, hipStr
   }
 }
 
+hipError_t launch_apply_box_map32(const Operator& op, const ApplyLaunch& a, hipStream_t s) {
+  switch (op.p) {
+    case 1: return launch_apply_box_map32_p<1>(op, a, s);
+    case 2: return launch_apply_box_map32_p<2>(op, a, s);
+    case 3: return launch_apply_box_map32_p<3>(op, a, s);
+    case 4: return launch_apply_box_map32_p<4>(op, a, s);
+    case 5: return launch_apply_box_map32_p<5>(op, a, s);
+    case 6: return launch_apply_box_map32_p<6>(op, a, s);
+    case 7: return launch_apply_box_map32_p<7>(op, a, s);
+    case 8: return launch_apply_box_map32_p<8>(op, a, s);
+    case 9: return launch_apply_box_map32_p<9>(op, a, s);
+    case 10: return launch_apply_box_map32_p<10>(op, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_zero_rows(double* Y, int64_t nrows, int ncols, int64_t ld, hipStream_t s) {
   const int64_t total = nrows * ncols;
   int64_t blocks = (total + 255) / 256;

@@ -177,6 +177,9 @@ hipError_t launch_constraints_distribute(const Operator& op, double* X, int nvec
                                          hipStream_t s);
 hipError_t launch_constraints_condense(const Operator& op, double* Y, int nvec, int64_t ld,
                                        hipStream_t s);
+// The body of mf_apply / mf_apply_add.
+int apply_dispatch(mf_operator* handle, const double* X, double* Y, int nvec, int64_t ldx,
+                   int64_t ldy, int prec, void* stream, bool accumulate);
 // Y[rows[i]][0 .. ncols) := 0 for i < n (a kernel, graph-capturable).
 hipError_t launch_zero_listed_rows(double* Y, const int32_t* rows, int64_t n, int ncols, int64_t ld,
                                    hipStream_t s);
@@ -189,6 +192,10 @@ double cell_factor(const double L[9], const double h[3], double mu, double G6[6]
 template <int P>
 hipError_t launch_apply_box_map_p(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 hipError_t launch_apply_box_map(const Operator& op, const ApplyLaunch& a, hipStream_t s);
+// The same with FP32 cell arrays (MF_FP32_MFMA on a refined operator).
+template <int P>
+hipError_t launch_apply_box_map32_p(const Operator& op, const ApplyLaunch& a, hipStream_t s);
+hipError_t launch_apply_box_map32(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 
 // FP64 fused apply; returns hipSuccess or the launch error.
 hipError_t launch_apply_f64(const Operator& op, const ApplyLaunch& a, hipStream_t s);

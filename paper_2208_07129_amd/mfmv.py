@@ -41,7 +41,8 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_gll_mass", "mf_cheb_step", "mf_sym_eig",
            # include/mfrefine.h
            "mf_refined_sizes", "mf_refined_layout", "mf_refined_quad_points",
-           "mf_create_refined_operator", "mf_constraints_distribute", "mf_constraints_condense")
+           "mf_create_refined_operator", "mf_apply_constrained", "mf_constraints_distribute",
+           "mf_constraints_condense")
 
 
 class MfError(RuntimeError):
@@ -123,6 +124,7 @@ def lib() -> ctypes.CDLL:
             "mf_refined_layout": (I, [RP, I, P, P]),
             "mf_refined_quad_points": (I, [RP, I, P]),
             "mf_create_refined_operator": (I, [RP, I, I, D, P, D, ctypes.POINTER(P)]),
+            "mf_apply_constrained": (I, [P, P, P, I, I64, I64, P]),
             "mf_constraints_distribute": (I, [P, P, I, I64, P]),
             "mf_constraints_condense": (I, [P, P, I, I64, P]),
         }
@@ -357,11 +359,22 @@ class RefinedOperator(Operator):
         _check(lib().mf_constraints_condense(self._h, ptr, k, ld, _stream_ptr(stream)))
         return Y
 
-    def apply_constrained(self, X, Y=None, stream=None):
-        """Y := C^T A_u C X; the hanging rows of X are overwritten by C X."""
-        self.distribute(X, stream)
-        Y = self.apply(X, Y, stream=stream)
-        return self.condense(Y, stream)
+    def apply_constrained(self, X, Y=None, stream=None, steps: bool = False):
+        """Y := C^T A_u C X (mf_apply_constrained); the hanging rows of X are overwritten by
+        C X.  steps=True issues the three calls (C, A_u, C^T) separately instead."""
+        import torch
+        if steps:
+            self.distribute(X, stream)
+            Y = self.apply(X, Y, stream=stream)
+            return self.condense(Y, stream)
+        xp, k, ldx = self._ptr(X, "X")
+        if Y is None:
+            Y = torch.empty((self.ndofs, k), dtype=torch.float64, device=X.device)
+        yp, ky, ldy = self._ptr(Y, "Y")
+        if ky != k:
+            raise ValueError("Y must have as many columns as X")
+        _check(lib().mf_apply_constrained(self._h, xp, yp, k, ldx, ldy, _stream_ptr(stream)))
+        return Y
 
 
 def zero_ptr(Y_ptr: int, nrows: int, ncols: int, ld: int, stream=None):

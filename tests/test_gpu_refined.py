@@ -91,10 +91,12 @@ def test_constraints_and_apply_match_oracle(p, n, rlo, rhi, bc, nvec):
     free = ~orc.constrained
     assert colrel(got[free], want[free]) <= TOL
     np.testing.assert_array_equal(got[orc.constrained], R[orc.constrained])
-    # the one-call composition of the binding
-    Xc = T(X)
-    Yc = op.apply_constrained(Xc)
-    assert colrel(Yc.cpu().numpy(), orc.apply_constrained(X)) <= TOL
+    # the one-call product (zero fill and C fused) and the three-call sequence
+    for steps in (False, True):
+        Xc = T(X)
+        Yc = op.apply_constrained(Xc, steps=steps)
+        assert colrel(Yc.cpu().numpy(), orc.apply_constrained(X)) <= TOL
+        np.testing.assert_allclose(Xc.cpu().numpy(), orc.distribute(X), rtol=0, atol=1e-13)
 
 
 SHEAR = np.array([[1.0, 0.3, -0.2], [0.1, 0.9, 0.25], [-0.15, 0.2, 1.1]])
@@ -121,6 +123,26 @@ def test_general_kernel_and_sheared_cells(p, general, lin):
     want = Y0 + orc.apply(orc.distribute(X))
     free = ~orc.constrained
     assert colrel(Ya[free], want[free]) <= TOL
+
+
+@pytest.mark.parametrize("p,nvec", [(2, 5), (4, 16), (6, 64), (8, 3)])
+def test_fp32_apply_on_refined_map(p, nvec):
+    """FP32 cell arrays through the map: per-column relative error <= 1e-6 against the
+    FP64 oracle, with column magnitudes from 1e-30 to 1e30 (power-of-two scaling)."""
+    print(f"refined fp32 p={p} nvec={nvec}", flush=True)
+    rm = W.RefinedMesh((3, 2, 2), LO, HI, (1, 0, 0), (2, 2, 1), W.BC_DIRICHLET0)
+    q = p + 1
+    op = mfmv.RefinedOperator(rm, p, q, 0.5, vfun(mfmv.refined_quad_points(rm, q)), 0.2)
+    orc = RefinedOracle(rm, p, q, 0.5, vfun, 0.2)
+    rng = np.random.default_rng(300 + p)
+    X = rng.uniform(-1, 1, (orc.ndofs, nvec)) * np.logspace(-30, 30, nvec)[None, :]
+    Xd = orc.distribute(X)
+    Y = op.apply(T(Xd), precision="fp32").cpu().numpy()
+    assert colrel(Y, orc.apply(Xd)) <= 1e-6
+    # the accumulating form
+    Ya = op.apply(T(Xd), T(np.zeros_like(Xd)), precision="fp32", accumulate=True).cpu().numpy()
+    free = ~orc.constrained
+    assert colrel(Ya[free], orc.apply(Xd)[free]) <= 1e-6
 
 
 def test_strided_single_column():
@@ -238,8 +260,9 @@ def test_grid_calls_refuse_refined_operator():
     out = torch.zeros_like(buf)
     assert L.mf_cheb_step(op._h, p, p, None, out.data_ptr(), 2, 2, 1.0, 0.0, 0.0,
                           None) == mfmv.MF_ERR_UNSUPPORTED
-    assert L.mf_apply(op._h, p, out.data_ptr(), 2, 2, 2, mfmv.MF_FP32_MFMA,
+    assert L.mf_apply(op._h, p, out.data_ptr(), 2, 2, 2, mfmv.MF_BF16_MFMA,
                       None) == mfmv.MF_ERR_UNSUPPORTED
+    assert L.mf_apply_constrained(op._h, p, p, 2, 2, 2, None) == mfmv.MF_ERR_ARG  # overlap
     nv = (ctypes.c_int * 1)(2)
     hs = (ctypes.c_void_p * 1)(op._h)
     b = ctypes.c_void_p()

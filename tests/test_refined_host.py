@@ -67,3 +67,4 @@ def test_argument_errors_without_device_work():
     assert not h.value
     assert L.mf_constraints_distribute(None, None, 1, 1, None) == mfmv.MF_ERR_ARG
     assert L.mf_constraints_condense(None, None, 1, 1, None) == mfmv.MF_ERR_ARG
+    assert L.mf_apply_constrained(None, None, None, 1, 1, 1, None) == mfmv.MF_ERR_ARG
