@@ -145,6 +145,20 @@ def test_fp32_apply_on_refined_map(p, nvec):
     assert colrel(Ya[free], orc.apply(Xd)[free]) <= 1e-6
 
 
+def test_constrained_call_on_uniform_operator_is_the_apply():
+    mesh = W.BoxMesh(n=(3, 2, 2), lo=LO, hi=HI, bc=W.BC_DIRICHLET0)
+    op = mfmv.Operator(mesh, 3, 4, 0.5, None, 0.3)
+    X = T(np.random.default_rng(9).uniform(-1, 1, (op.ndofs, 6)))
+    X0 = X.clone()
+    Y = torch.empty_like(X)
+    rc = mfmv.lib().mf_apply_constrained(op._h, X.data_ptr(), Y.data_ptr(), 6, 6, 6, None)
+    assert rc == mfmv.MF_OK
+    Yr = op.apply(X0)
+    torch.cuda.synchronize()
+    assert torch.equal(X, X0)                     # no constraint sets: X untouched
+    assert colrel(Y.cpu().numpy(), Yr.cpu().numpy()) <= TOL
+
+
 def test_strided_single_column():
     rm = W.RefinedMesh((3, 3, 3), LO, HI, (1, 1, 1), (2, 2, 2), W.BC_NONE)
     op = mfmv.RefinedOperator(rm, 3, 4, 0.5, None, 0.1)
