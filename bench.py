@@ -85,9 +85,12 @@ def apply_kernel_name(p: int, q: int, precision: str) -> str:
     return "apply_box_kernel" if (2 * q ** 3 * 8 + q ** 3) * 8 <= 80 * 1024 else "apply_box_pers_kernel"
 
 
-def kernel_hash() -> str:
+MAP_KERNEL_SOURCES = ["paper_2208_07129_amd/csrc/apply_box_map.hip"] + KERNEL_SOURCES[1:]
+
+
+def kernel_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -106,7 +109,7 @@ def workload(name: str, nvec: int | None):
     return w
 
 
-def traffic_for(wname: str, nvec: int, precision: str):
+def traffic_for(wname: str, nvec: int, precision: str, sources=None):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or
     None if they were taken on a different kernel source or workload."""
     try:
@@ -115,7 +118,7 @@ def traffic_for(wname: str, nvec: int, precision: str):
         return None
     key = f"{wname}/nvec{nvec}/{precision}"
     rec = t.get(key)
-    if not rec or rec.get("kernel_hash") != kernel_hash():
+    if not rec or rec.get("kernel_hash") != kernel_hash(sources):
         return None
     return rec.get("bytes_per_launch")
 
@@ -408,7 +411,10 @@ def refined_leg(a) -> dict:
                                 "condense": bytes_cond / (ms_cond * 1e-3) / 1e9,
                                 "peak": PEAK_HBM_GBS},
             "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
-                         "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
+                         "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
+                         "traffic": traffic_for(w.name, nvec, "fp64", MAP_KERNEL_SOURCES),
+                         "algorithmic_bytes": algorithmic_bytes(op.ndofs, op.ncells, w.p, w.q,
+                                                                nvec),
                          "kernel": "apply_box_map_kernel"}}
 
 
