@@ -145,6 +145,22 @@ def test_fp32_apply_on_refined_map(p, nvec):
     assert colrel(Ya[free], orc.apply(Xd)[free]) <= 1e-6
 
 
+@pytest.mark.parametrize("q", [11, 12])
+def test_degree_10(q):
+    """The largest degree: FP64 (B = 4 map tiles), FP32, and the constraint kernels
+    with 121 masters per set."""
+    print(f"refined p=10 q={q}", flush=True)
+    rm = W.RefinedMesh((2, 1, 1), LO, HI, (1, 0, 0), (2, 1, 1), W.BC_NONE)
+    op = mfmv.RefinedOperator(rm, 10, q, 0.5, vfun(mfmv.refined_quad_points(rm, q)), 0.2)
+    orc = RefinedOracle(rm, 10, q, 0.5, vfun, 0.2)
+    X = np.random.default_rng(q).uniform(-1, 1, (orc.ndofs, 5))
+    want = orc.apply_constrained(X)
+    assert colrel(op.apply_constrained(T(X)).cpu().numpy(), want) <= TOL
+    if q == 11:
+        Xd = orc.distribute(X)
+        assert colrel(op.apply(T(Xd), precision="fp32").cpu().numpy(), orc.apply(Xd)) <= 1e-6
+
+
 def test_constrained_call_on_uniform_operator_is_the_apply():
     mesh = W.BoxMesh(n=(3, 2, 2), lo=LO, hi=HI, bc=W.BC_DIRICHLET0)
     op = mfmv.Operator(mesh, 3, 4, 0.5, None, 0.3)
