@@ -14,7 +14,12 @@ What it computes (eq. AU with one partition; Sec. 3.2.2 for C):
     tensor-product Lagrange interpolation of that cell's nodal values (the
     continuity requirement that makes the refined space conforming);
   * the constrained product Y = C^T Z (sum_e Q_e^T A^(e) Q_e) Z C X, with the
-    element matrices of fe_oracle on cells of two sizes.
+    element matrices of fe_oracle on cells of two sizes;
+  * for the eigenproblem on the refined mesh (eq. shep): the GLL-lumped mass of
+    the constrained space lumped by rows, m_c = C^T m_u (m_u the lumped mass of
+    every cell, as in fe_oracle; row sums of C^T M_u C, since every row of C
+    sums to one), and one Chebyshev filter step a D C^T A_u C D Y + b Y + c X
+    with D = m_c^{-1/2} on free rows and 0 elsewhere.
 
 Numbering (the layout the library's refined operator uses):
   * cells: unrefined coarse cells in lexicographic order (first index fastest),
@@ -218,3 +223,15 @@ class RefinedOracle(Oracle):
     def apply_constrained(self, X):
         """Y = C^T Z A_u Z C X: the operator on the conforming (constrained) space."""
         return self.condense(self.apply(self.C @ np.asarray(X, dtype=np.float64)))
+
+    def lumped_mass_constrained(self):
+        """m_c = C^T m_u: zero on hanging and zero-Dirichlet rows."""
+        return self.C.T @ self.lumped_mass()
+
+    def cheb_step_constrained(self, D, Y, Xp, a, b, c):
+        """a D C^T A_u C (D Y) + b Y + c Xp on rows with D > 0; 0 on the others."""
+        out = a * D[:, None] * self.apply_constrained(D[:, None] * Y) + b * Y
+        if Xp is not None:
+            out = out + c * Xp
+        out[D == 0.0] = 0.0
+        return out

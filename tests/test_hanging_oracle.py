@@ -151,3 +151,32 @@ def test_constrained_stiffness_symmetric_with_constant_null_space(p):
     assert np.sum(ev < 1e-9 * ev[-1]) == 1                  # only the constants
     ones = np.where(orc.hanging, 0.0, 1.0)
     assert np.abs(orc.apply_constrained(ones[:, None])).max() < 1e-12
+
+
+# ------------------------------------------------- eigenproblem on the refined mesh
+def test_constrained_lumped_mass_volume_and_uniform_limit():
+    rm = RefinedMesh([3, 3, 3], LO, HI, [1, 1, 1], [2, 2, 2])
+    orc = RefinedOracle(rm, 3, 4, 0.5)
+    m = orc.lumped_mass_constrained()
+    assert abs(m.sum() - np.prod(np.subtract(HI, LO))) < 1e-13      # rows of C sum to one
+    assert np.all(m[orc.hanging] == 0.0) and np.all(m[~orc.hanging] > 0.0)
+    box = BoxMesh([3, 2, 2], LO, HI, BC_DIRICHLET0)
+    empty = RefinedMesh([3, 2, 2], LO, HI, [1, 0, 0], [1, 2, 2], bc=BC_DIRICHLET0)
+    np.testing.assert_allclose(RefinedOracle(empty, 3, 4, 0.5).lumped_mass_constrained(),
+                               fo.Oracle(box, 3, 4, 0.5).lumped_mass(), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("p,tol", [(3, 1e-4), (4, 1e-6)])
+def test_lowest_dirichlet_eigenvalue_on_refined_mesh(p, tol):
+    """Standard form D C^T A_u C D (D = m_c^{-1/2}) of (1/2) K on the box with zero Dirichlet:
+    the lowest eigenvalue converges to (1/2) pi^2 sum_d L_d^-2."""
+    rm = RefinedMesh([3, 3, 3], LO, HI, [1, 1, 1], [2, 2, 2], bc=BC_DIRICHLET0)
+    orc = RefinedOracle(rm, p, p + 1, 0.5)
+    m = orc.lumped_mass_constrained()
+    free = m > 0
+    D = np.zeros_like(m)
+    D[free] = 1.0 / np.sqrt(m[free])
+    S = orc.cheb_step_constrained(D, np.eye(orc.ndofs)[:, free], None, 1.0, 0.0, 0.0)[free]
+    lam = np.linalg.eigvalsh(0.5 * (S + S.T))[0]
+    exact = 0.5 * np.pi ** 2 * sum(1.0 / (HI[d] - LO[d]) ** 2 for d in range(3))
+    assert abs(lam - exact) <= tol * exact
