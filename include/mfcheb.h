@@ -24,8 +24,11 @@ extern "C" {
 /* out[i] := m_i, the GLL-lumped mass of node i (sum over the cells holding
  * the node of w_a w_b w_c det J, w the GLL weights of the element's nodes,
  * Sec. Helmholtz eigenvalue problem), or m_i^{-1/2} when inv_sqrt != 0;
- * constrained rows get 0.  out: device, mf_num_dofs entries.  Errors:
- * MF_ERR_ARG (NULL), MF_ERR_UNSUPPORTED (sheared cells), MF_ERR_HIP. */
+ * constrained rows get 0.  out: device, mf_num_dofs entries.  On an operator
+ * of mf_create_refined_operator: m_c = C^T m_u, the mass lumped by rows on the
+ * constrained space (0 on hanging rows; see include/mfrefine.h).  Errors:
+ * MF_ERR_ARG (NULL), MF_ERR_UNSUPPORTED (sheared cells of a uniform mesh),
+ * MF_ERR_HIP. */
 int mf_gll_mass(mf_operator* op, int inv_sqrt, double* out, void* stream);
 
 /* Out := a D H (D Y) + b Y + c Xp, one step of the Chebyshev filter of

@@ -42,9 +42,10 @@
  * A refined operator supports mf_apply / mf_apply_add in MF_FP64, and in
  * MF_FP32_MFMA on axis-aligned cells (FP32 cell arrays with power-of-two
  * scaling per cell and column, the FP32 vector contractions, FP64 assembly);
- * the calls built on the uniform grid (mf_diagonal, mf_gll_mass,
- * mf_cheb_step, mf_cell_gather / mf_cell_scatter, batches, BF16) return
- * MF_ERR_UNSUPPORTED for it.
+ * mf_gll_mass gives the constrained lumped mass (see
+ * mf_cheb_step_constrained); the calls built on the uniform grid
+ * (mf_diagonal, mf_cheb_step, mf_cell_gather / mf_cell_scatter, batches,
+ * BF16) return MF_ERR_UNSUPPORTED for it.
  */
 #ifndef MFREFINE_H
 #define MFREFINE_H
@@ -102,6 +103,23 @@ int mf_create_refined_operator(const mf_refined_mesh* mesh, int p, int q, double
  * above 4,194,240), MF_ERR_HIP. */
 int mf_apply_constrained(mf_operator* op, double* X, double* Y, int nvec, int64_t ldx,
                          int64_t ldy, void* stream);
+
+/* One step of the Chebyshev filter of Alg. ChFSi on the constrained space of a
+ * refined mesh: Out := a D C^T A_u C (D Y) + b Y + c Xp on rows with D != 0,
+ * 0 on the others.  D = m_c^{-1/2} from mf_gll_mass(op, 1, ...), which on a
+ * refined operator lumps the constrained mass by rows: m_c = C^T m_u, m_u the
+ * GLL-lumped mass of every cell (every row of C sums to one), so D is 0 on
+ * hanging and zero-Dirichlet rows.  Y, Xp, Out: ndofs x nvec, leading
+ * dimension ld >= nvec; Xp may be NULL (c dropped) or Out itself; Out must
+ * not overlap Y or D.  work: device, 2 ndofs nvec doubles, caller-owned (the
+ * scaled input and the product), overlapping nothing else.  Runs row scaling,
+ * mf_apply_constrained and a combining kernel in stream order; allocates
+ * nothing.  On an operator of mf_create_operator it is the same step with C
+ * the identity.  Errors: MF_ERR_ARG (NULL, nvec < 1, ld < nvec, overlap),
+ * MF_ERR_UNSUPPORTED, MF_ERR_HIP. */
+int mf_cheb_step_constrained(mf_operator* op, const double* D, const double* Y,
+                             const double* Xp, double* Out, int nvec, int64_t ld, double a,
+                             double b, double c, double* work, void* stream);
 
 /* X_S := W_I X_M for every set I: the action of C (Sec. 3.2.2), in place on
  * the slave rows of X (columns [0, nvec), row stride ld >= nvec); every other

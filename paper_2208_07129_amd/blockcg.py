@@ -196,7 +196,7 @@ def lanczos_extremes(op: mfmv.Operator, steps: int = 100, seed: int = 0,
     n = op.ndofs
     rng = np.random.default_rng(seed)
     v0 = rng.uniform(-1.0, 1.0, (n, 1))
-    v0[mfmv.constrained_mask(op.mesh, op.p).astype(bool)] = 0.0
+    v0[op.constrained_rows()] = 0.0
     v = torch.from_numpy(v0).cuda()
     w = torch.empty_like(v)
     vp = torch.zeros_like(v)

@@ -267,6 +267,7 @@ void mf_destroy_operator(mf_operator* handle) {
   if (op->d_cidx) (void)hipFree(op->d_cidx);
   if (op->d_cw) (void)hipFree(op->d_cw);
   if (op->d_zrows) (void)hipFree(op->d_zrows);
+  if (op->d_detj) (void)hipFree(op->d_detj);
   delete op;
 }
 

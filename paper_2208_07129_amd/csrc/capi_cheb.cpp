@@ -1,6 +1,7 @@
 // C ABI of the Chebyshev-filter building blocks (include/mfcheb.h).
 #include "mf_internal.h"
 #include "mfcheb.h"
+#include "mfrefine.h"
 
 using namespace mf;
 
@@ -19,8 +20,17 @@ extern "C" {
 int mf_gll_mass(mf_operator* handle, int inv_sqrt, double* out, void* stream) {
   if (!handle || !out) return fail(MF_ERR_ARG, "operator and out must be non-NULL");
   Operator* op = reinterpret_cast<Operator*>(handle);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (op->refined) {
+    // the lumped mass of every cell, then C^T (row sums of C^T M C), then m^{-1/2}
+    hipError_t err = launch_gll_mass_map(*op, out, s);
+    if (err == hipSuccess && op->nsets > 0) err = launch_constraints_condense(*op, out, 1, 1, s);
+    if (err == hipSuccess && inv_sqrt) err = launch_inv_sqrt(out, op->ndofs, s);
+    if (err != hipSuccess) return hip_fail(err, "lumped mass kernel launch");
+    return MF_OK;
+  }
   if (!op->box) return fail(MF_ERR_UNSUPPORTED, "the lumped mass is built for axis-aligned cells");
-  hipError_t err = launch_gll_mass(*op, inv_sqrt, out, static_cast<hipStream_t>(stream));
+  hipError_t err = launch_gll_mass(*op, inv_sqrt, out, s);
   if (err != hipSuccess) return hip_fail(err, "lumped mass kernel launch");
   return MF_OK;
 }
@@ -43,6 +53,35 @@ int mf_cheb_step(mf_operator* handle, const double* D, const double* Y, const do
   const ChebArgs ca{D, Xp, a, b, c};
   err = launch_apply_cheb(*op, Y, Out, ld, nvec, ca, s);
   if (err != hipSuccess) return hip_fail(err, "Chebyshev step kernel launch");
+  return MF_OK;
+}
+
+int mf_cheb_step_constrained(mf_operator* handle, const double* D, const double* Y,
+                             const double* Xp, double* Out, int nvec, int64_t ld, double a,
+                             double b, double c, double* work, void* stream) {
+  if (!handle || !D || !Y || !Out || !work)
+    return fail(MF_ERR_ARG, "operator, D, Y, Out and work must be non-NULL");
+  if (nvec < 1 || ld < nvec) return fail(MF_ERR_ARG, "need nvec >= 1 and ld >= nvec");
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  const size_t span = (size_t)((op->ndofs - 1) * ld + nvec) * sizeof(double);
+  const size_t dspan = (size_t)op->ndofs * sizeof(double);
+  const size_t wspan = 2 * (size_t)op->ndofs * nvec * sizeof(double);
+  if (overlaps(Out, span, Y, span) || overlaps(Out, span, D, dspan) ||
+      overlaps(Out, span, work, wspan))
+    return fail(MF_ERR_ARG, "Out overlaps Y, D or work");
+  if (overlaps(work, wspan, Y, span) || overlaps(work, wspan, D, dspan) ||
+      (Xp && overlaps(work, wspan, Xp, span)))
+    return fail(MF_ERR_ARG, "work overlaps an input");
+  if (Xp && Xp != Out && overlaps(Out, span, Xp, span))
+    return fail(MF_ERR_ARG, "Xp must be Out itself or not overlap it");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* W = work;
+  double* V = work + op->ndofs * (int64_t)nvec;
+  hipError_t err = launch_scale_rows(op->ndofs, nvec, D, Y, ld, W, s);  // W = D Y
+  if (err != hipSuccess) return hip_fail(err, "row scaling kernel launch");
+  if (int st = mf_apply_constrained(handle, W, V, nvec, nvec, nvec, stream)) return st;
+  err = launch_cheb_combine(op->ndofs, nvec, D, V, Y, Xp, Out, ld, a, b, c, s);
+  if (err != hipSuccess) return hip_fail(err, "Chebyshev combine kernel launch");
   return MF_OK;
 }
 

@@ -203,6 +203,89 @@ hipError_t launch_cheb_init(const Operator& op, const double* Y, const double* X
   return hipGetLastError();
 }
 
+// The same over an explicit map with a det J per cell (refined meshes).
+__global__ void gll_mass_map_kernel(const int32_t* __restrict__ map,
+                                    const double* __restrict__ detj, int np, GllWeights wt,
+                                    double* __restrict__ m) {
+  const int64_t e = blockIdx.x;
+  const int F = np * np * np;
+  const double dj = detj[e];
+  for (int i = threadIdx.x; i < F; i += blockDim.x) {
+    const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
+    const int node = map[e * F + i];
+    if (node >= 0) unsafeAtomicAdd(m + node, wt.w[i1] * wt.w[i2] * wt.w[i3] * dj);
+  }
+}
+
+__global__ void scale_rows_kernel(int64_t n, int nvec, const double* __restrict__ D,
+                                  const double* __restrict__ Y, int64_t ld,
+                                  double* __restrict__ W) {
+  const int64_t total = n * nvec;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / nvec;
+    W[i] = D[r] * Y[r * ld + (i - r * nvec)];
+  }
+}
+
+// Xp may alias Out: each element is read before it is written, by one thread.
+__global__ void cheb_combine_kernel(int64_t n, int nvec, const double* __restrict__ D,
+                                    const double* __restrict__ V, const double* __restrict__ Y,
+                                    const double* Xp, double* Out, int64_t ld, double a, double b,
+                                    double c) {
+  const int64_t total = n * nvec;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / nvec;
+    const int64_t at = r * ld + (i - r * nvec);
+    const double d = D[r];
+    double v = 0.0;
+    if (d != 0.0) {
+      v = a * d * V[i] + b * Y[at];
+      if (Xp) v += c * Xp[at];
+    }
+    Out[at] = v;
+  }
+}
+
+static unsigned grid_1d(int64_t total) {
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  return (unsigned)(blocks < 1 ? 1 : blocks);
+}
+
+hipError_t launch_gll_mass_map(const Operator& op, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(zero_rows_kernel, dim3(grid_1d(op.ndofs)), dim3(256), 0, s, out, op.ndofs, 1,
+                     (int64_t)1);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  GllWeights wt{};
+  for (int i = 0; i < op.np && i <= kMaxP; ++i) wt.w[i] = op.wgll[i];
+  hipLaunchKernelGGL(gll_mass_map_kernel, dim3((unsigned)op.ncells), dim3(256), 0, s, op.d_map,
+                     op.d_detj, op.np, wt, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_inv_sqrt(double* m, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(inv_sqrt_kernel, dim3(grid_1d(n)), dim3(256), 0, s, m, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_rows(int64_t n, int nvec, const double* D, const double* Y, int64_t ld,
+                             double* W, hipStream_t s) {
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_1d(n * nvec)), dim3(256), 0, s, n, nvec, D, Y,
+                     ld, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_cheb_combine(int64_t n, int nvec, const double* D, const double* V,
+                               const double* Y, const double* Xp, double* Out, int64_t ld,
+                               double a, double b, double c, hipStream_t s) {
+  hipLaunchKernelGGL(cheb_combine_kernel, dim3(grid_1d(n * nvec)), dim3(256), 0, s, n, nvec, D, V,
+                     Y, Xp, Out, ld, a, b, c);
+  return hipGetLastError();
+}
+
 hipError_t launch_gll_mass(const Operator& op, int inv_sqrt, double* out, hipStream_t s) {
   const int64_t n = op.ndofs;
   unsigned blocks = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);

@@ -92,6 +92,7 @@ struct Operator {
   int32_t* d_cidx = nullptr;  // slave and master node indices (-1: zero-Dirichlet master)
   double* d_cw = nullptr;     // the W_I, concatenated
   int32_t* d_zrows = nullptr; // rows that are not cell-interior (the map kernel's zero fill)
+  double* d_detj = nullptr;   // det J per cell (refined meshes: cells of two sizes)
   int64_t nzrows = 0;
   // optional per-launch timing (diagnostics): event triples around the zero
   // fill and the fused kernel of each apply, in a ring
@@ -180,6 +181,19 @@ hipError_t launch_constraints_condense(const Operator& op, double* Y, int nvec, 
 // The body of mf_apply / mf_apply_add.
 int apply_dispatch(mf_operator* handle, const double* X, double* Y, int nvec, int64_t ldx,
                    int64_t ldy, int prec, void* stream, bool accumulate);
+// GLL-lumped mass of a refined operator over its map (every cell, hanging
+// rows included; the caller condenses it with C^T).
+hipError_t launch_gll_mass_map(const Operator& op, double* out, hipStream_t s);
+// out[i] := m[i] > 0 ? m[i]^{-1/2} : 0 for i < n.
+hipError_t launch_inv_sqrt(double* m, int64_t n, hipStream_t s);
+// W[i*nvec + j] := D[i] Y[i*ld + j].
+hipError_t launch_scale_rows(int64_t n, int nvec, const double* D, const double* Y, int64_t ld,
+                             double* W, hipStream_t s);
+// Out[i*ld + j] := D[i] == 0 ? 0 : a D[i] V[i*nvec + j] + b Y[i*ld + j] + c Xp[i*ld + j]
+// (Xp may be NULL or Out itself).
+hipError_t launch_cheb_combine(int64_t n, int nvec, const double* D, const double* V,
+                               const double* Y, const double* Xp, double* Out, int64_t ld,
+                               double a, double b, double c, hipStream_t s);
 // Y[rows[i]][0 .. ncols) := 0 for i < n (a kernel, graph-capturable).
 hipError_t launch_zero_listed_rows(double* Y, const int32_t* rows, int64_t n, int ncols, int64_t ld,
                                    hipStream_t s);

@@ -316,6 +316,14 @@ int mf_create_refined_operator(const mf_refined_mesh* mesh, int p, int q, double
   op->ncells = L.ncells;
   op->box = false;  // the general-geometry kernel: explicit map, per-cell factors
   op->refined = true;
+  {
+    const std::vector<double> xg = gll_points(p);
+    for (int i = 0; i <= p; ++i) {
+      double P = 0.0, dP = 0.0, ddP = 0.0;
+      ct::legendre(p, xg[i], P, dP, ddP);
+      op->wgll[i] = 2.0 / (p * (p + 1.0) * P * P);  // GLL weights of the element's nodes
+    }
+  }
   op->nsets = (int64_t)L.sets.size();
   for (const ConstraintSet& cs : L.sets) {
     op->max_slaves = std::max(op->max_slaves, (int)cs.ns);
@@ -331,12 +339,13 @@ int mf_create_refined_operator(const mf_refined_mesh* mesh, int p, int q, double
   // per-cell geometry (eq. sjacobian / eq. mjacobian) for cells of two sizes
   double Lm[9];
   lin_matrix(mesh->coarse, Lm);
-  std::vector<double> geo((size_t)E * 6), vq((size_t)E * nq3);
+  std::vector<double> geo((size_t)E * 6), vq((size_t)E * nq3), detj((size_t)E);
   double hc[3];
   for (int d = 0; d < 3; ++d) hc[d] = (mesh->coarse.hi[d] - mesh->coarse.lo[d]) / mesh->coarse.n[d];
   for (int64_t e = 0; e < E; ++e) {
     const double h[3] = {hc[0] * L.size[e], hc[1] * L.size[e], hc[2] * L.size[e]};
     const double detJ = cell_factor(Lm, h, mu, &geo[(size_t)e * 6]);
+    detj[(size_t)e] = detJ;
     for (int k = 0; k < nq3; ++k) {
       const double v = Vq ? Vq[e * nq3 + k] : 0.0;
       if (!std::isfinite(v)) {
@@ -391,6 +400,7 @@ int mf_create_refined_operator(const mf_refined_mesh* mesh, int p, int q, double
   if (!s) s = alloc_copy((void**)&op->d_cidx, L.cidx.data(), L.cidx.size() * sizeof(int32_t));
   if (!s) s = alloc_copy((void**)&op->d_cw, L.W.data(), L.W.size() * sizeof(double));
   if (!s) s = alloc_copy((void**)&op->d_zrows, zrows.data(), zrows.size() * sizeof(int32_t));
+  if (!s) s = alloc_copy((void**)&op->d_detj, detj.data(), detj.size() * sizeof(double));
   if (s) {
     mf_destroy_operator(reinterpret_cast<mf_operator*>(op));
     return s;

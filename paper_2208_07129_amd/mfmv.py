@@ -41,8 +41,8 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_gll_mass", "mf_cheb_step", "mf_sym_eig",
            # include/mfrefine.h
            "mf_refined_sizes", "mf_refined_layout", "mf_refined_quad_points",
-           "mf_create_refined_operator", "mf_apply_constrained", "mf_constraints_distribute",
-           "mf_constraints_condense")
+           "mf_create_refined_operator", "mf_apply_constrained", "mf_cheb_step_constrained",
+           "mf_constraints_distribute", "mf_constraints_condense")
 
 
 class MfError(RuntimeError):
@@ -125,6 +125,7 @@ def lib() -> ctypes.CDLL:
             "mf_refined_quad_points": (I, [RP, I, P]),
             "mf_create_refined_operator": (I, [RP, I, I, D, P, D, ctypes.POINTER(P)]),
             "mf_apply_constrained": (I, [P, P, P, I, I64, I64, P]),
+            "mf_cheb_step_constrained": (I, [P, P, P, P, P, I, I64, D, D, D, P, P]),
             "mf_constraints_distribute": (I, [P, P, I, I64, P]),
             "mf_constraints_condense": (I, [P, P, I, I64, P]),
         }
@@ -217,6 +218,10 @@ class Operator:
         nd, nc = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().mf_operator_info(self._h, ctypes.byref(nd), ctypes.byref(nc), None, None))
         self.ndofs, self.ncells = nd.value, nc.value
+
+    def constrained_rows(self) -> np.ndarray:
+        """Rows that carry no unknown (zero-Dirichlet), as a boolean host array."""
+        return constrained_mask(self.mesh, self.p).astype(bool)
 
     @classmethod
     def from_workload(cls, w):
@@ -336,6 +341,10 @@ class RefinedOperator(Operator):
                                                 ctypes.byref(self._h)))
         self.ndofs, self.ncells = sz["ndofs"], sz["ncells"]
 
+    def constrained_rows(self) -> np.ndarray:
+        """Rows that carry no unknown (zero-Dirichlet and hanging), as a boolean host array."""
+        return refined_layout(self.mesh, self.p)[1] != 0
+
     @classmethod
     def from_workload(cls, w):
         Vq = w.V(refined_quad_points(w.mesh, w.q)) if w.V is not None else None
@@ -424,6 +433,16 @@ def cheb_step(op: Operator, D, Y, Xp, Out, a: float, b: float, c: float, stream=
         px, nx, kx, ldx = _mv(Xp, "Xp")
         if (nx, kx, ldx) != (n, k, ld):
             raise ValueError("Xp must have the shape and row stride of Y")
+    if isinstance(op, RefinedOperator):
+        # the constrained space: row scaling, mf_apply_constrained, combine (workspace cached)
+        import torch
+        work = getattr(op, "_cheb_work", None)
+        if work is None or work.numel() < 2 * n * k:
+            work = op._cheb_work = torch.empty(2 * n * k, dtype=torch.float64, device=Y.device)
+        _check(lib().mf_cheb_step_constrained(op._h, D.data_ptr(), py, px or None, po, k, ld,
+                                              float(a), float(b), float(c), work.data_ptr(),
+                                              _stream_ptr(stream)))
+        return Out
     _check(lib().mf_cheb_step(op._h, D.data_ptr(), py, px or None, po, k, ld, float(a), float(b),
                               float(c), _stream_ptr(stream)))
     return Out

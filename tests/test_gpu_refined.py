@@ -11,6 +11,10 @@
   interface masters and hanging rows; the closed-form bilinear form of two
   degree-6 polynomials vanishing on the boundary; the adjoint identity
   <C^T Y, Z> = <Y, C Z> over every set; the symmetry of C^T A_u C.
+- The eigenproblem on the constrained space: the row-lumped mass C^T m_u and its
+  inverse square root (1e-13), the Chebyshev step a D C^T A_u C D Y + b Y + c X
+  (Xp absent, separate, in place), and Chebyshev-filtered subspace iteration
+  against a dense eigen-solve of the oracle's standard form.
 - The grid-based calls refuse a refined operator.
 """
 import ctypes
@@ -286,7 +290,6 @@ def test_grid_calls_refuse_refined_operator():
     buf = torch.zeros((op.ndofs, 2), dtype=torch.float64, device=dev())
     p = buf.data_ptr()
     assert L.mf_diagonal(op._h, p, None) == mfmv.MF_ERR_UNSUPPORTED
-    assert L.mf_gll_mass(op._h, 0, p, None) == mfmv.MF_ERR_UNSUPPORTED
     out = torch.zeros_like(buf)
     assert L.mf_cheb_step(op._h, p, p, None, out.data_ptr(), 2, 2, 1.0, 0.0, 0.0,
                           None) == mfmv.MF_ERR_UNSUPPORTED
@@ -298,3 +301,58 @@ def test_grid_calls_refuse_refined_operator():
     b = ctypes.c_void_p()
     assert L.mf_batch_create(1, hs, nv, 0, ctypes.byref(b)) == mfmv.MF_ERR_UNSUPPORTED
     torch.cuda.synchronize()
+
+
+# ------------------------------------------- eigenproblem on the refined mesh (Alg. ChFSi)
+@pytest.mark.parametrize("p,bc", [(3, W.BC_DIRICHLET0), (4, W.BC_NONE), (6, W.BC_DIRICHLET0)])
+def test_lumped_mass_and_cheb_step_on_refined_mesh(p, bc):
+    print(f"refined cheb p={p} bc={bc}", flush=True)
+    rm = W.RefinedMesh((3, 2, 2), LO, HI, (1, 0, 0), (2, 2, 1), bc)
+    q = p + 1
+    op = mfmv.RefinedOperator(rm, p, q, 0.5, vfun(mfmv.refined_quad_points(rm, q)), 0.2)
+    orc = RefinedOracle(rm, p, q, 0.5, vfun, 0.2)
+    m_ref = orc.lumped_mass_constrained()
+    np.testing.assert_allclose(mfmv.gll_mass(op).cpu().numpy(), m_ref, rtol=1e-13, atol=0)
+    D = mfmv.gll_mass(op, inv_sqrt=True)
+    Dr = np.zeros_like(m_ref)
+    Dr[m_ref > 0] = 1.0 / np.sqrt(m_ref[m_ref > 0])
+    np.testing.assert_allclose(D.cpu().numpy(), Dr, rtol=1e-13, atol=0)
+    rng = np.random.default_rng(40 + p)
+    nvec = 6
+    Y = rng.uniform(-1, 1, (orc.ndofs, nvec))
+    Xp = rng.uniform(-1, 1, (orc.ndofs, nvec))
+    a, b, c = 1.3, -0.4, 0.25
+    for xp_mode in ("none", "separate", "in place"):
+        Out = T(Xp.copy()) if xp_mode == "in place" else torch.empty((orc.ndofs, nvec),
+                                                                     dtype=torch.float64,
+                                                                     device=dev())
+        Xd = None if xp_mode == "none" else (Out if xp_mode == "in place" else T(Xp))
+        mfmv.cheb_step(op, D, T(Y), Xd, Out, a, b, c)
+        want = orc.cheb_step_constrained(Dr, Y, None if xp_mode == "none" else Xp, a, b, c)
+        assert colrel(Out.cpu().numpy(), want) <= TOL, xp_mode
+
+
+def test_subspace_iteration_on_refined_mesh():
+    """Chebyshev-filtered subspace iteration on the constrained space of a refined mesh
+    against a dense eigen-solve of the oracle's standard form D C^T A_u C D."""
+    from paper_2208_07129_amd.chebyshev import SubspaceIteration
+    rm = W.RefinedMesh((3, 3, 3), (0, 0, 0), (3.0, 3.0, 3.0), (1, 1, 1), (2, 2, 2),
+                       W.BC_DIRICHLET0)
+    Vf = W.gaussian_wells(8, L=3.0, k=3, width=0.6)
+    op = mfmv.RefinedOperator(rm, 3, 4, 0.5, Vf(mfmv.refined_quad_points(rm, 4)), 0.0)
+    orc = RefinedOracle(rm, 3, 4, 0.5, Vf, 0.0)
+    m = orc.lumped_mass_constrained()
+    free = m > 0
+    Dr = np.zeros_like(m)
+    Dr[free] = 1.0 / np.sqrt(m[free])
+    S = orc.cheb_step_constrained(Dr, np.eye(orc.ndofs)[:, free], None, 1.0, 0.0, 0.0)[free]
+    ref = np.linalg.eigvalsh(0.5 * (S + S.T))
+    k, nev = 16, 10
+    U0 = np.random.default_rng(2).uniform(-1, 1, (orc.ndofs, k))
+    U0[~free] = 0.0
+    si = SubspaceIteration(op, k)
+    out = si.solve(T(U0), nev, degree=12, tol=2e-7, maxit=60)
+    print(out["iterations"], out["residual"])
+    assert out["converged"], out["history"][-5:]
+    np.testing.assert_allclose(out["eigenvalues"], ref[:nev], rtol=0,
+                               atol=1e-9 * max(1.0, abs(ref[:nev]).max()))
