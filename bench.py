@@ -394,6 +394,15 @@ def refined_leg(a) -> dict:
     n32, _z32, k32 = op.timing_read()
     flops = flops_per_cell_vector(w.p, w.q) * op.ncells * nvec
     ach = flops / (ms_kernel * 1e-3) / 1e12
+    # Chebyshev filter on the constrained space (Alg. ChFSi on D C^T A_u C D): degree-10
+    # filters of mf_cheb_step_constrained steps, per step
+    from paper_2208_07129_amd import chebyshev
+    D = mfmv.gll_mass(op, inv_sqrt=True)
+    work = (torch.empty_like(X), torch.empty_like(X))
+    U = X.clone()
+    cheb_deg = 10
+    ms_cheb = timed(lambda: chebyshev.chebyshev_filter(op, D, U, cheb_deg, 0.0, 400.0, 4.0,
+                                                       work=work)) / cheb_deg
     nm = refined_surface_nodes(w.mesh, w.p, fine=False)
     ns = op.nslaves
     row = 8 * nvec
@@ -407,6 +416,7 @@ def refined_leg(a) -> dict:
             "ms_per_step": ms_step, "ms_three_calls": ms_three, "ms_distribute": ms_dist, "ms_apply": ms_apply,
             "ms_apply_kernel": ms_kernel, "ms_zero_fill": z / n, "ms_condense": ms_cond,
             "ms_apply_fp32": ms_apply32, "ms_apply_kernel_fp32": k32 / n32,
+            "ms_cheb_step": ms_cheb,
             "constraints_gbs": {"distribute": bytes_dist / (ms_dist * 1e-3) / 1e9,
                                 "condense": bytes_cond / (ms_cond * 1e-3) / 1e9,
                                 "peak": PEAK_HBM_GBS},
