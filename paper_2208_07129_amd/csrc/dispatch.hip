@@ -217,14 +217,16 @@ __global__ void gll_mass_map_kernel(const int32_t* __restrict__ map,
   }
 }
 
+// Row-major elementwise passes over n rows x nvec columns: one row per
+// wavefront step, lane = column (no per-element division).
 __global__ void scale_rows_kernel(int64_t n, int nvec, const double* __restrict__ D,
                                   const double* __restrict__ Y, int64_t ld,
                                   double* __restrict__ W) {
-  const int64_t total = n * nvec;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / nvec;
-    W[i] = D[r] * Y[r * ld + (i - r * nvec)];
+  const int lane = threadIdx.x % 64;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; r < n; r += waves) {
+    const double d = D[r];
+    for (int j = lane; j < nvec; j += 64) W[r * nvec + j] = d * Y[r * ld + j];
   }
 }
 
@@ -233,18 +235,19 @@ __global__ void cheb_combine_kernel(int64_t n, int nvec, const double* __restric
                                     const double* __restrict__ V, const double* __restrict__ Y,
                                     const double* Xp, double* Out, int64_t ld, double a, double b,
                                     double c) {
-  const int64_t total = n * nvec;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / nvec;
-    const int64_t at = r * ld + (i - r * nvec);
+  const int lane = threadIdx.x % 64;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; r < n; r += waves) {
     const double d = D[r];
-    double v = 0.0;
-    if (d != 0.0) {
-      v = a * d * V[i] + b * Y[at];
-      if (Xp) v += c * Xp[at];
+    for (int j = lane; j < nvec; j += 64) {
+      const int64_t at = r * ld + j;
+      double v = 0.0;
+      if (d != 0.0) {
+        v = a * d * V[r * nvec + j] + b * Y[at];
+        if (Xp) v += c * Xp[at];
+      }
+      Out[at] = v;
     }
-    Out[at] = v;
   }
 }
 
@@ -271,18 +274,24 @@ hipError_t launch_inv_sqrt(double* m, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// four rows per 256-thread workgroup step, at most 65536 workgroups
+static unsigned grid_rows(int64_t n) {
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  return (unsigned)(blocks < 1 ? 1 : blocks);
+}
+
 hipError_t launch_scale_rows(int64_t n, int nvec, const double* D, const double* Y, int64_t ld,
                              double* W, hipStream_t s) {
-  hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_1d(n * nvec)), dim3(256), 0, s, n, nvec, D, Y,
-                     ld, W);
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_rows(n)), dim3(256), 0, s, n, nvec, D, Y, ld, W);
   return hipGetLastError();
 }
 
 hipError_t launch_cheb_combine(int64_t n, int nvec, const double* D, const double* V,
                                const double* Y, const double* Xp, double* Out, int64_t ld,
                                double a, double b, double c, hipStream_t s) {
-  hipLaunchKernelGGL(cheb_combine_kernel, dim3(grid_1d(n * nvec)), dim3(256), 0, s, n, nvec, D, V,
-                     Y, Xp, Out, ld, a, b, c);
+  hipLaunchKernelGGL(cheb_combine_kernel, dim3(grid_rows(n)), dim3(256), 0, s, n, nvec, D, V, Y,
+                     Xp, Out, ld, a, b, c);
   return hipGetLastError();
 }
 
