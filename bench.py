@@ -381,8 +381,8 @@ def refined_leg(a) -> dict:
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    ms_step = timed(lambda: op.apply_constrained(X, Y))
     ms_three = timed(lambda: op.apply_constrained(X, Y, steps=True))
+    ms_step = timed(lambda: op.apply_constrained(X, Y))
     ms_dist = timed(lambda: op.distribute(X))
     ms_cond = timed(lambda: op.condense(Y))
     op.timing(reps)

@@ -53,6 +53,7 @@ def colrel(Y, R):
 
 LO, HI = (0.0, -0.5, 0.25), (1.0, 1.0, 1.5)
 CASES = [  # p, n, rlo, rhi, bc, nvec
+    (1, (3, 3, 3), (1, 1, 1), (2, 2, 2), W.BC_NONE, 130),           # no cell-interior rows
     (2, (3, 3, 3), (1, 1, 1), (2, 2, 2), W.BC_DIRICHLET0, 5),
     (3, (4, 3, 2), (0, 1, 0), (2, 3, 1), W.BC_NONE, 70),
     (4, (3, 3, 2), (1, 0, 0), (3, 2, 1), W.BC_DIRICHLET0, 1),
@@ -304,10 +305,12 @@ def test_grid_calls_refuse_refined_operator():
 
 
 # ------------------------------------------- eigenproblem on the refined mesh (Alg. ChFSi)
-@pytest.mark.parametrize("p,bc", [(3, W.BC_DIRICHLET0), (4, W.BC_NONE), (6, W.BC_DIRICHLET0)])
-def test_lumped_mass_and_cheb_step_on_refined_mesh(p, bc):
-    print(f"refined cheb p={p} bc={bc}", flush=True)
-    rm = W.RefinedMesh((3, 2, 2), LO, HI, (1, 0, 0), (2, 2, 1), bc)
+@pytest.mark.parametrize("p,bc,lin", [(3, W.BC_DIRICHLET0, None), (4, W.BC_NONE, None),
+                                      (6, W.BC_DIRICHLET0, None), (2, W.BC_DIRICHLET0, SHEAR)])
+def test_lumped_mass_and_cheb_step_on_refined_mesh(p, bc, lin):
+    """Axis-aligned cells take the D-scaled map kernel; sheared cells the composed path."""
+    print(f"refined cheb p={p} bc={bc} sheared={lin is not None}", flush=True)
+    rm = W.RefinedMesh((3, 2, 2), LO, HI, (1, 0, 0), (2, 2, 1), bc, lin)
     q = p + 1
     op = mfmv.RefinedOperator(rm, p, q, 0.5, vfun(mfmv.refined_quad_points(rm, q)), 0.2)
     orc = RefinedOracle(rm, p, q, 0.5, vfun, 0.2)
