@@ -68,3 +68,17 @@ def test_argument_errors_without_device_work():
     assert L.mf_constraints_distribute(None, None, 1, 1, None) == mfmv.MF_ERR_ARG
     assert L.mf_constraints_condense(None, None, 1, 1, None) == mfmv.MF_ERR_ARG
     assert L.mf_apply_constrained(None, None, None, 1, 1, 1, None) == mfmv.MF_ERR_ARG
+
+
+@pytest.mark.parametrize("n,rlo,rhi", [((4, 4, 4), (1, 1, 1), (3, 3, 3)), ((5, 3, 2), (0, 1, 0), (2, 3, 2)),
+                                       ((3, 3, 3), (0, 0, 0), (3, 3, 3)), ((6, 2, 4), (2, 0, 1), (5, 1, 3))])
+@pytest.mark.parametrize("p", [2, 5])
+def test_constraint_set_count_closed_form(n, rlo, rhi, p):
+    """One set per coarse face between an unrefined cell and the refined block: for each
+    direction d and side, the block's cross-section if a coarse layer lies beyond it."""
+    rm = RefinedMesh(n, (0, 0, 0), (1, 1, 1), rlo, rhi, BC_NONE)
+    want = 0
+    for d in range(3):
+        area = np.prod([rhi[e] - rlo[e] for e in range(3) if e != d])
+        want += area * ((rlo[d] > 0) + (rhi[d] < n[d]))
+    assert mfmv.refined_sizes(rm, p)["nsets"] == want
