@@ -82,3 +82,13 @@ def test_constraint_set_count_closed_form(n, rlo, rhi, p):
         area = np.prod([rhi[e] - rlo[e] for e in range(3) if e != d])
         want += area * ((rlo[d] > 0) + (rhi[d] < n[d]))
     assert mfmv.refined_sizes(rm, p)["nsets"] == want
+
+
+@pytest.mark.parametrize("n,rlo,rhi", [((4, 4, 4), (1, 1, 1), (3, 3, 3)), ((5, 4, 6), (1, 2, 1), (4, 3, 5))])
+@pytest.mark.parametrize("p", [1, 3, 6])
+def test_hanging_count_closed_form_for_an_interior_block(n, rlo, rhi, p):
+    """A block strictly inside the mesh: every node on its fine-lattice surface hangs."""
+    rm = RefinedMesh(n, (0, 0, 0), (1, 1, 1), rlo, rhi, BC_DIRICHLET0)
+    ext = [2 * (rhi[d] - rlo[d]) * p + 1 for d in range(3)]
+    want = int(np.prod(ext) - np.prod([e - 2 for e in ext]))
+    assert mfmv.refined_sizes(rm, p)["nslaves"] == want
