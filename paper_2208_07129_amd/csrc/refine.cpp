@@ -435,9 +435,8 @@ int mf_apply_constrained(mf_operator* handle, double* X, double* Y, int nvec, in
   const size_t yb = ((op->ndofs - 1) * ldy + nvec) * sizeof(double);
   if (xa < ya + yb && ya < xa + xb) return fail(MF_ERR_ARG, "X and Y overlap");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // C, then mf_apply (zero fill and A_u), then C^T, in stream order; one
-  // launch holding the zero fill and C together measured slower, with the C
-  // items first or last in its grid
+  // C, then mf_apply (zero fill and A_u), then C^T, in stream order (a single
+  // launch holding the zero fill and C together took longer in the trace)
   if (op->nsets > 0) {
     hipError_t err = launch_constraints_distribute(*op, X, nvec, ldx, s);
     if (err != hipSuccess) return hip_fail(err, "constraint kernel launch");
