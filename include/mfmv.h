@@ -136,6 +136,16 @@ void mf_destroy_operator(mf_operator* op);
 /* Sizes of an operator (any output pointer may be NULL). */
 int mf_operator_info(const mf_operator* op, int64_t* ndofs, int64_t* ncells, int* p, int* q);
 
+/* The order in which the fused apply takes the cells of a box-mesh operator
+ * (host output, ncells int32 cell indices, cell index = cx + nx (cy + ny cz)):
+ * eight blocks by recursive bisection, one per XCD, Morton order inside a
+ * block.  Work item i of a launch with t column tiles is (order[i / t], tile
+ * i % t), and XCD x runs the contiguous items [x c, (x+1) c), c = ceil(ncells t
+ * / 8) (eq. AU's sum over cells in an order of the library's choosing).
+ * Diagnostic: it lets a caller find the first and last cells of each XCD's
+ * range.  Errors: MF_ERR_ARG (NULL), MF_ERR_UNSUPPORTED (refined operator). */
+int mf_cell_order(const mf_operator* op, int32_t* order);
+
 /* Y := A X (overwrite, never accumulate), eq. AU with one partition.
  *   X: device, ndofs rows, row stride ldx >= nvec; constrained rows are
  *      ignored (read as zero: the action of C, Sec. 3.2.2).

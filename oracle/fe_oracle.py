@@ -365,6 +365,14 @@ class Oracle:
         out[self.constrained] = 0.0
         return out
 
+    def chebyshev_filter(self, D, U, m, lam_min, lam_max, lam_u):
+        """p_m(H~) U on the standard form H~ = D A D (eq. shep), see chebyshev_filter."""
+        def H(Z):
+            out = D[:, None] * self.apply(D[:, None] * Z)
+            out[self.constrained] = 0.0
+            return out
+        return chebyshev_filter(H, U, m, lam_min, lam_max, lam_u)
+
     def diagonal(self):
         """diag(A) (constrained entries zero), from the element-matrix diagonals."""
         d = np.zeros(self.ndofs)
@@ -372,3 +380,34 @@ class Oracle:
         np.add.at(d, self.map.ravel(), np.einsum("eii->ei", Ae).ravel())
         d[self.constrained] = 0.0
         return d
+
+
+# ----------------------------------------------------------------------------
+# Chebyshev filter of subspace iteration (Alg. ChFSi)
+# ----------------------------------------------------------------------------
+def chebyshev_filter(H, U, m, lam_min, lam_max, lam_u):
+    """p_m(H) U for a symmetric operator H given by its action Z -> H Z.
+
+    p_m is the degree-m Chebyshev polynomial of the first kind mapped so that the
+    unwanted interval [lam_u, lam_max] goes to [-1, 1], normalised to 1 at lam_min
+    (Alg. ChFSi):  p_m(t) = T_m((t - c) / e) / T_m((lam_min - c) / e), with c and e
+    the centre and half-width of [lam_u, lam_max].  Written from the definition:
+    T_0 = 1, T_1(x) = x, T_{k+1}(x) = 2 x T_k(x) - T_{k-1}(x) on the matrix argument
+    L = (H - c) / e, and one division by the scalar T_m at the end (no per-step
+    normalisation)."""
+    if m < 1:
+        raise ValueError("m >= 1")
+    U = np.asarray(U, dtype=np.float64)
+    c = 0.5 * (lam_max + lam_u)
+    e = 0.5 * (lam_max - lam_u)
+
+    def L(Z):
+        return (H(Z) - c * Z) / e
+
+    prev, cur = U, L(U)
+    x0 = (lam_min - c) / e
+    t_prev, t_cur = 1.0, x0
+    for _ in range(2, m + 1):
+        prev, cur = cur, 2.0 * L(cur) - prev
+        t_prev, t_cur = t_cur, 2.0 * x0 * t_cur - t_prev
+    return cur / t_cur

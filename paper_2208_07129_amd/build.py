@@ -64,21 +64,36 @@ def jobs():
     return out
 
 
-def _compile(cc, src, obj, extra):
-    cmd = [cc, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, obj)]
+def _newest_input(src):
+    """Modification time of the newest of the source and every header it may include."""
+    t = os.path.getmtime(os.path.join(CSRC, src))
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for f in os.listdir(d):
+            if f.endswith(".h"):
+                t = max(t, os.path.getmtime(os.path.join(d, f)))
+    return t
+
+
+def _compile(cc, src, obj, extra, incremental=False):
+    out = os.path.join(BUILD, obj)
+    if incremental and os.path.exists(out) and os.path.getmtime(out) >= _newest_input(src):
+        return obj
+    cmd = [cc, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(nproc: int | None = None, verbose: bool = False) -> str:
+def build(nproc: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every translation unit and link.  incremental=True (a developer
+    option) skips objects newer than their source and every header."""
     cc = hipcc()
     os.makedirs(BUILD, exist_ok=True)
     nproc = nproc or min(8, os.cpu_count() or 4)
     objs = []
     with cf.ThreadPoolExecutor(max_workers=nproc) as ex:
-        futs = [ex.submit(_compile, cc, s, o, e) for s, o, e in jobs()]
+        futs = [ex.submit(_compile, cc, s, o, e, incremental) for s, o, e in jobs()]
         for f in futs:
             objs.append(f.result())
             if verbose:
@@ -98,8 +113,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=None)
     ap.add_argument("-v", action="store_true")
+    ap.add_argument("--incremental", action="store_true",
+                    help="recompile only objects older than their source or a header")
     a = ap.parse_args(argv)
-    print(build(a.j, a.v))
+    print(build(a.j, a.v, a.incremental))
 
 
 if __name__ == "__main__":

@@ -281,6 +281,16 @@ int mf_operator_info(const mf_operator* handle, int64_t* ndofs, int64_t* ncells,
   return MF_OK;
 }
 
+int mf_cell_order(const mf_operator* handle, int32_t* order) {
+  if (!handle) return fail(MF_ERR_ARG, "operator is NULL");
+  if (!order) return fail(MF_ERR_ARG, "order is NULL");
+  const Operator* op = reinterpret_cast<const Operator*>(handle);
+  if (op->refined) return fail(MF_ERR_UNSUPPORTED, "a refined operator has no grid cell order");
+  const std::vector<int32_t> o = cell_order(op->grid.n);
+  std::memcpy(order, o.data(), o.size() * sizeof(int32_t));
+  return MF_OK;
+}
+
 static bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
   const char* ca = static_cast<const char*>(a);
   const char* cb = static_cast<const char*>(b);

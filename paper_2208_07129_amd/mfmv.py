@@ -25,7 +25,8 @@ MIXED_MFMA_CFGS = 4  # mixed shapes 0..3 are matrix-core kernels; 4..6 are FP32 
 
 # Every symbol declared in include/mfmv.h.
 EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask", "mf_basis_1d",
-           "mf_create_operator", "mf_destroy_operator", "mf_operator_info", "mf_apply",
+           "mf_create_operator", "mf_destroy_operator", "mf_operator_info", "mf_cell_order",
+           "mf_apply",
            "mf_apply_add", "mf_zero", "mf_set_launch", "mf_set_launch_mixed", "mf_timing",
            "mf_timing_read", "mf_batch_create", "mf_batch_destroy", "mf_batch_set_launch",
            "mf_batch_apply", "mf_batch_capture", "mf_batch_replay", "mf_batch_info",
@@ -83,6 +84,7 @@ def lib() -> ctypes.CDLL:
             "mf_destroy_operator": (None, [P]),
             "mf_operator_info": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(I64),
                                      ctypes.POINTER(I), ctypes.POINTER(I)]),
+            "mf_cell_order": (I, [P, P]),
             "mf_apply": (I, [P, P, P, I, I64, I64, I, P]),
             "mf_apply_add": (I, [P, P, P, I, I64, I64, I, P]),
             "mf_zero": (I, [P, I64, I, I64, P]),
@@ -243,6 +245,12 @@ class Operator:
     def apply_ptr(self, X_ptr: int, Y_ptr: int, nvec: int, ldx: int, ldy: int,
                   prec: int = MF_FP64, stream=None):
         _check(lib().mf_apply(self._h, X_ptr, Y_ptr, nvec, ldx, ldy, prec, _stream_ptr(stream)))
+
+    def cell_order(self) -> np.ndarray:
+        """The order in which the fused apply takes the cells (see mf_cell_order)."""
+        out = np.empty(self.ncells, dtype=np.int32)
+        _check(lib().mf_cell_order(self._h, out.ctypes.data))
+        return out
 
     def set_launch(self, general: bool = False, cfg: int = -1):
         _check(lib().mf_set_launch(self._h, int(general), int(cfg)))

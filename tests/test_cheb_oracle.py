@@ -128,3 +128,56 @@ def test_standard_form_eigenvalues_equal_the_generalised_problem(bc):
     ev = np.linalg.eigvalsh(S)
     ref = sla.eigh(A, np.diag(m), eigvals_only=True)
     np.testing.assert_allclose(ev, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+
+
+def _cheb_closed_form(m, x):
+    """T_m(x) in closed form: cos(m arccos x) on [-1, 1], sign(x)^m cosh(m arccosh |x|)
+    outside."""
+    x = np.asarray(x, dtype=np.float64)
+    inside = np.abs(x) <= 1.0
+    out = np.empty_like(x)
+    out[inside] = np.cos(m * np.arccos(x[inside]))
+    xo = x[~inside]
+    out[~inside] = np.sign(xo) ** m * np.cosh(m * np.arccosh(np.abs(xo)))
+    return out
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 10, 23])
+def test_chebyshev_filter_on_a_diagonal_operator(m):
+    """On H = diag(lam) the filter scales column entries by p_m(lam_i) =
+    T_m((lam_i - c)/e) / T_m((lam_min - c)/e) (Alg. ChFSi), checked against the
+    trigonometric / hyperbolic closed form of T_m: a wrong centre, half-width, sign or a
+    missing normalisation fails."""
+    rng = np.random.default_rng(m)
+    lam_min, lam_u, lam_max = -1.5, 3.0, 40.0
+    lam = np.concatenate([[lam_min, lam_u, lam_max], rng.uniform(lam_min, lam_max, 29)])
+    U = rng.standard_normal((lam.size, 3))
+    got = fo.chebyshev_filter(lambda Z: lam[:, None] * Z, U, m, lam_min, lam_max, lam_u)
+    c, e = (lam_max + lam_u) / 2, (lam_max - lam_u) / 2
+    ref = (_cheb_closed_form(m, (lam - c) / e) / _cheb_closed_form(m, np.array([(lam_min - c) / e]))[0])
+    np.testing.assert_allclose(got, ref[:, None] * U, rtol=1e-11, atol=1e-12 * np.abs(U).max())
+    # normalised to one at lam_min; |p_m| <= 1 / |T_m(x0)| on the damped interval
+    assert abs(got[0, 0] / U[0, 0] - 1.0) <= 1e-12
+    damped = (lam >= lam_u) & (lam <= lam_max)
+    x0 = abs(_cheb_closed_form(m, np.array([(lam_min - c) / e]))[0])
+    assert np.all(np.abs(got[damped] / U[damped]) <= 1.0 / x0 * (1 + 1e-12))
+
+
+def test_chebyshev_filter_on_the_standard_form_commutes_with_its_eigenvectors():
+    """On a tiny mesh, the filter of the oracle's standard-form operator acts on each
+    eigenvector of the dense matrix D A D as multiplication by p_m(eigenvalue)."""
+    mesh = W.BoxMesh(n=(2, 1, 2), lo=(0, 0, 0), hi=(1.0, 0.7, 1.2), bc=W.BC_DIRICHLET0)
+    orc = fo.Oracle(mesh, 3, 4, 0.5, lambda x: np.cos(x[..., 0]) - x[..., 2], 0.0)
+    m = orc.lumped_mass()
+    D = np.zeros_like(m)
+    free = ~orc.constrained
+    D[free] = 1.0 / np.sqrt(m[free])
+    S = D[:, None] * orc.assemble_dense() * D[None, :]
+    w, V = np.linalg.eigh(S[np.ix_(free, free)])
+    U = np.zeros((orc.ndofs, 4))
+    U[free] = V[:, [0, 3, 7, -1]]
+    lam_min, lam_u, lam_max = w[0], w[5], w[-1] * 1.01
+    got = orc.chebyshev_filter(D, U, 9, lam_min, lam_max, lam_u)
+    c, e = (lam_max + lam_u) / 2, (lam_max - lam_u) / 2
+    pm = _cheb_closed_form(9, (w[[0, 3, 7, -1]] - c) / e) / _cheb_closed_form(9, np.array([(lam_min - c) / e]))[0]
+    np.testing.assert_allclose(got, U * pm[None, :], rtol=0, atol=1e-10)

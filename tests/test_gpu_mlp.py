@@ -215,6 +215,51 @@ def test_adam_matches_oracle():
                                       mlp._host_bf16(net.params[i].cpu().numpy()))
 
 
+def test_adam_kernel_three_steps_match_the_hand_derivation():
+    """mf_adam over three steps (moment decay and bias correction at t = 2, 3) against
+    the hand-derived values of tests/golden/adam_three_steps.json, and against the
+    oracle's Adam on a random vector over five steps."""
+    import ctypes
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "adam_three_steps.json")) as f:
+        g = json.load(f)
+    L = mfmv.lib()
+    s = torch.cuda.current_stream().cuda_stream
+    f32 = dict(dtype=torch.float32, device=dev())
+    w = torch.tensor(g["w0"], **f32)
+    m1, m2 = torch.zeros(2, **f32), torch.zeros(2, **f32)
+    wbf = torch.zeros(2, dtype=torch.int16, device=dev())
+    for t, grad in enumerate(g["grads"], start=1):
+        gd = torch.tensor(grad, **f32)
+        assert L.mf_adam(2, w.data_ptr(), gd.data_ptr(), m1.data_ptr(), m2.data_ptr(),
+                         wbf.data_ptr(), ctypes.c_float(g["lr"]), ctypes.c_float(g["b1"]),
+                         ctypes.c_float(g["b2"]), ctypes.c_float(g["eps"]), t, s) == 0
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(w.cpu().numpy(), [g["w_after"][0][t - 1], g["w_after"][1][t - 1]],
+                                   rtol=1e-6, atol=0)
+        bf = (wbf.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+        np.testing.assert_array_equal(bf, mo.bf16_round(w.cpu().numpy()).astype(np.float32))
+    rng = np.random.default_rng(3)
+    n = 1000
+    wh = rng.standard_normal(n).astype(np.float32)
+    w = torch.from_numpy(wh.copy()).to(dev())
+    m1, m2 = torch.zeros(n, **f32), torch.zeros(n, **f32)
+    r1, r2 = np.zeros(n, np.float32), np.zeros(n, np.float32)
+    # the C ABI takes the hyper-parameters as FP32: the oracle gets the same values
+    lr, b1, b2, eps = (float(np.float32(v)) for v in (1e-2, 0.9, 0.999, 1e-8))
+    for t in range(1, 6):
+        gh = rng.standard_normal(n).astype(np.float32) * (0.0 if t == 3 else 1.0)
+        gd = torch.from_numpy(gh).to(dev())
+        assert L.mf_adam(n, w.data_ptr(), gd.data_ptr(), m1.data_ptr(), m2.data_ptr(), None,
+                         ctypes.c_float(lr), ctypes.c_float(b1), ctypes.c_float(b2),
+                         ctypes.c_float(eps), t, s) == 0
+        wh, r1, r2 = mo.adam_step(wh, gh, r1, r2, lr, b1, b2, eps, t)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(w.cpu().numpy(), wh, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(m2.cpu().numpy(), r2, rtol=1e-5, atol=1e-12)
+
+
 def test_training_reduces_loss_and_fits_the_cell_blocks():
     mesh, op = small_op(W.BC_PERIODIC, p=3, n=(4, 4, 4))
     diag = mfmv.diagonal(op)

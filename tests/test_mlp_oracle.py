@@ -112,3 +112,23 @@ def test_adam_first_step_moves_by_lr():
     w, g = np.array([1.0, -2.0]), np.array([0.5, -3.0])
     w1, m1, m2 = mo.adam_step(w, g, np.zeros(2), np.zeros(2), 0.1, 0.9, 0.999, 1e-12, 1)
     np.testing.assert_allclose(w1, w - 0.1 * np.sign(g), rtol=1e-6)
+
+
+def _adam_golden():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "adam_three_steps.json")) as f:
+        return json.load(f)
+
+
+def test_adam_three_steps_match_the_hand_derivation():
+    """Moment decay and bias correction at t = 2, 3 (a zero gradient at step 2 or 3),
+    against values derived by hand in exact arithmetic (tests/golden/adam_three_steps.json).
+    A missing bias correction, swapped b1/b2 or a moment that is not decayed fails."""
+    g = _adam_golden()
+    w = np.array(g["w0"])
+    m1, m2 = np.zeros(2), np.zeros(2)
+    for t, grad in enumerate(g["grads"], start=1):
+        w, m1, m2 = mo.adam_step(w, np.array(grad), m1, m2, g["lr"], g["b1"], g["b2"], g["eps"], t)
+        np.testing.assert_allclose(w, [g["w_after"][0][t - 1], g["w_after"][1][t - 1]],
+                                   rtol=2e-7, atol=0)
