@@ -175,6 +175,33 @@ int mf_apply_add(mf_operator* op, const double* X, double* Y, int nvec, int64_t 
  * Errors: MF_ERR_ARG (NULL, nrows < 0, ncols < 1, ld < ncols), MF_ERR_HIP. */
 int mf_zero(double* Y, int64_t nrows, int ncols, int64_t ld, void* stream);
 
+/* Launch-shape tuning, the analogue of the paper's sweep of its GPU kernel's
+ * batch size and thread-block shape (Sec. 4, GPU benchmarks,
+ * tbl:batchsizeStudy).  Every launch shape built for this operator's (p, q) and
+ * precision (FP64: the axis-aligned-cell shapes of mf_set_launch; FP32: the
+ * mixed shapes 0..6; BF16: 0..3) is timed on device buffers of ndofs x nvec
+ * (allocated and freed here: not for use under graph capture), median of 7
+ * event-timed calls after 2 warm-up calls on a stream of its own, and the
+ * fastest is kept for later mf_apply calls of this operator with nvec columns
+ * in this precision (it takes effect unless mf_set_launch(_mixed) sets a shape:
+ * mf_tune clears that setting).
+ *   cache_path: a JSON file (NULL: no cache) of entries
+ *     "<arch>/p<p>q<q>/cells<E>/nvec<nvec>/<fp64|fp32|bf16>":
+ *       {"cfg": <shape>, "ms": [median ms per shape, -1 if not timed]};
+ *   a present entry is used without timing; a new result is added by rewriting
+ *   the file through a temporary file and a rename (concurrent writers from
+ *   several processes may lose each other's entries, never corrupt the file).
+ * Operators with a single kernel shape (general geometry, refined meshes in
+ * FP64) return MF_OK without timing.  Errors: MF_ERR_ARG (NULL, nvec < 1,
+ * cache not writable), MF_ERR_UNSUPPORTED (precision not built for this
+ * operator), MF_ERR_OOM, MF_ERR_HIP. */
+int mf_tune(mf_operator* op, int nvec, int prec, const char* cache_path);
+
+/* The shape mf_tune chose for (nvec, prec) (-1 if none) and, if ms is not
+ * NULL, its median times per shape (nms entries; -1 for shapes not timed,
+ * every entry -1 when the choice came from the cache).  Errors: MF_ERR_ARG. */
+int mf_tune_info(const mf_operator* op, int nvec, int prec, int* cfg, double* ms, int nms);
+
 /* Launch selection (used by the tuner and by tests):
  *   general != 0 forces the general-geometry kernel (full 3x3 factor, three
  *                LDS buffers) even on axis-aligned cells; it cannot be undone
@@ -214,6 +241,11 @@ int mf_set_launch_mixed(mf_operator* op, int cfg);
  * ring.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
 int mf_timing(mf_operator* op, int slots);
 int mf_timing_read(mf_operator* op, int* count, double* zero_ms, double* kernel_ms);
+/* The same events one apply at a time, oldest first: at most cap entries of
+ * the zero-fill and fused-kernel milliseconds of each recorded apply (host
+ * arrays), *count set to the number written; clears the ring.  Errors:
+ * MF_ERR_ARG, MF_ERR_HIP. */
+int mf_timing_samples(mf_operator* op, int cap, double* zero_ms, double* kernel_ms, int* count);
 
 /* ------------------------------------------------------------- batches ---- */
 
@@ -269,6 +301,30 @@ int mf_batch_apply(mf_batch* b, const double* const* X, double* const* Y, const 
 int mf_batch_capture(mf_batch* b, const double* const* X, double* const* Y, const int64_t* ldx,
                      const int64_t* ldy, void* stream);
 int mf_batch_replay(mf_batch* b, void* stream);
+
+/* Choose the batch's launch shape: every shape 0..5 is timed on the caller's
+ * buffers (Y_i overwritten) on `stream`, median of 5 event-timed calls after 2
+ * warm-up calls, and the fastest set (mf_batch_set_launch).  cache_path as
+ * mf_tune, with entries keyed "<arch>/batch/<precision>/" followed by every
+ * operator's p, q, cells and columns in the caller's order; the choice is also
+ * remembered for batches that mf_apply_batched builds in this process.  Host
+ * synchronising; not for use under graph capture.  Errors: as mf_batch_apply,
+ * and MF_ERR_ARG for an unwritable cache. */
+int mf_batch_tune(mf_batch* b, const double* const* X, double* const* Y, const int64_t* ldx,
+                  const int64_t* ldy, const char* cache_path, void* stream);
+
+/* One call for Y_i := A_i X_i, i < nops (ld = nvec[i]; arrays in the caller's
+ * order; the same requirements as mf_batch_create and mf_batch_apply).  The
+ * library keeps the batch it builds for a list of operator handles, column
+ * counts, precision and device (up to 8 such lists, least recently used
+ * dropped; a batch is dropped when one of its operators is destroyed), with
+ * the shape mf_batch_tune chose for the same key in this process, else shape
+ * 0.  The first call for a list allocates the batch's tables (synchronous
+ * copies); later calls only enqueue work, so they may be captured in a graph.
+ * Calls from several host threads are serialised by a lock.  Errors: as
+ * mf_batch_create and mf_batch_apply. */
+int mf_apply_batched(int nops, mf_operator* const* ops, const double* const* X, double* const* Y,
+                     const int* nvec, int prec, void* stream);
 
 /* Work items, launch shape and grid size of the batch (outputs may be NULL). */
 int mf_batch_info(const mf_batch* b, int64_t* items, int* cfg, int* grid);

@@ -41,6 +41,7 @@ def jobs():
     out = [
         ("capi.cpp", "capi.o", []),
         ("capi_batch.cpp", "capi_batch.o", []),
+        ("capi_tune.cpp", "capi_tune.o", []),
         ("host_setup.cpp", "host_setup.o", []),
         ("dispatch.hip", "dispatch.o", []),
         ("solver.hip", "solver.o", []),

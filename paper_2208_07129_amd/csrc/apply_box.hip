@@ -59,23 +59,12 @@ hipError_t launch_box(const ApplyLaunch& a, hipStream_t s) {
   Kern k;
   if constexpr (PERS) k = apply_box_pers_kernel<NP, NQ, B, C, NT, ACCUM>;
   else k = apply_box_kernel<NP, NQ, B, C, NT, ACCUM>;
-  static int per_cu = -1, cus = 0;  // resident capacity, queried once per instantiation
-  if (per_cu < 0) {
-    if (lds > 64 * 1024) {
-      hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (err != hipSuccess) return err;
-    }
-    int dev = 0, n = 0;
-    hipError_t err = hipGetDevice(&dev);
-    if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, NT, lds);
-    if (err != hipSuccess) return err;
-    per_cu = n < 1 ? 1 : n;
-  }
+  KernelFacts f;
+  hipError_t err = kernel_facts(reinterpret_cast<const void*>(k), NT, lds, f);
+  if (err != hipSuccess) return err;
   int64_t blocks = chunk * kXcds;
   if (PERS) {
-    int64_t resident = (int64_t)per_cu * cus;
+    int64_t resident = (int64_t)f.per_cu * f.cus;
     resident -= resident % kXcds;
     if (resident < kXcds) resident = kXcds;
     if (resident < blocks) blocks = resident;

@@ -85,13 +85,9 @@ hipError_t launch_map(const ApplyLaunch& a, hipStream_t s) {
   const int64_t nitems = a.ncells * ntiles;
   const int64_t chunk = (nitems + kXcds - 1) / kXcds;
   auto k = apply_box_map_kernel<NP, NQ, B, NT, ACCUM, T>;
-  static bool attr = false;  // raise the dynamic LDS limit once per instantiation
-  if (!attr && lds > 64 * 1024) {
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (err != hipSuccess) return err;
-  }
-  attr = true;
+  KernelFacts f;  // raises the dynamic LDS limit on this device
+  hipError_t err = kernel_facts(reinterpret_cast<const void*>(k), NT, lds, f);
+  if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k, dim3((unsigned)(chunk * kXcds)), dim3(NT), lds, s, a.map, a.geo, a.vq,
                      a.X, a.Y, a.ldx, a.ldy, a.nvec, ntiles, nitems, chunk);
   return hipGetLastError();

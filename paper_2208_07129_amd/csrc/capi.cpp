@@ -2,7 +2,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <utility>
 
 #include "mf_internal.h"
 #include "sf_common.h"
@@ -20,6 +23,33 @@ int fail(int status, const std::string& msg) {
 int hip_fail(hipError_t err, const char* what) {
   g_last_error = std::string(what) + ": " + hipGetErrorString(err);
   return MF_ERR_HIP;
+}
+
+hipError_t kernel_facts(const void* kernel, int nt, size_t lds, KernelFacts& out) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, KernelFacts> known;
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return err;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = known.find({kernel, dev});
+  if (it != known.end()) {
+    out = it->second;
+    return hipSuccess;
+  }
+  KernelFacts f;
+  if (lds > 64 * 1024) {
+    err = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+  }
+  int n = 0;
+  err = hipDeviceGetAttribute(&f.cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, nt, lds);
+  if (err != hipSuccess) return err;
+  f.per_cu = n < 1 ? 1 : n;
+  known[{kernel, dev}] = f;
+  out = f;
+  return hipSuccess;
 }
 
 static int check_degree(int p) {
@@ -257,6 +287,7 @@ int mf_create_operator(const mf_box_mesh* mesh, int p, int q, double mu, const d
 void mf_destroy_operator(mf_operator* handle) {
   if (!handle) return;
   Operator* op = reinterpret_cast<Operator*>(handle);
+  batch_cache_forget(op);
   if (op->d_map) (void)hipFree(op->d_map);
   if (op->d_order) (void)hipFree(op->d_order);
   for (hipEvent_t e : op->ev) (void)hipEventDestroy(e);
@@ -333,10 +364,15 @@ int mf::apply_dispatch(mf_operator* handle, const double* X, double* Y, int nvec
   a.nvec = nvec;
   a.threads = 256;
   a.vtile = choose_vtile_f64(op->np, op->nq, nvec);
-  if (mixed)
-    a.cfg = op->mcfg >= 0 ? op->mcfg : choose_cfg_mixed(op->np, op->nq, nvec, prec);
-  else
-    a.cfg = op->cfg >= 0 ? op->cfg : choose_cfg_box(op->np, op->nq, nvec);
+  a.cfg = mixed ? op->mcfg : op->cfg;
+  if (a.cfg < 0) {
+    const auto it = op->tuned.find({prec, nvec});
+    if (it != op->tuned.end())
+      a.cfg = it->second;
+    else
+      a.cfg = mixed ? choose_cfg_mixed(op->np, op->nq, nvec, prec)
+                    : choose_cfg_box(op->np, op->nq, nvec);
+  }
   if (mixed && a.cfg >= kMixedMfmaCfgs && !box_pairs_ok(X, Y, nvec, ldx, ldy))
     a.cfg = vec32_cfg_single(a.cfg);
   if (!mixed && op->box && !box_pairs_ok(X, Y, nvec, ldx, ldy))
@@ -441,6 +477,33 @@ int mf_timing_read(mf_operator* handle, int* count, double* zero_ms, double* ker
   if (count) *count = op->ev_count;
   if (zero_ms) *zero_ms = z;
   if (kernel_ms) *kernel_ms = k;
+  op->ev_count = 0;
+  op->ev_next = 0;
+  return MF_OK;
+}
+
+int mf_timing_samples(mf_operator* handle, int cap, double* zero_ms, double* kernel_ms, int* count) {
+  if (!handle || !count) return fail(MF_ERR_ARG, "operator and count must be non-NULL");
+  if (cap < 0 || (cap > 0 && (!zero_ms || !kernel_ms))) return fail(MF_ERR_ARG, "bad output arrays");
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  // the ring holds the last ev_count applies; the oldest is at ev_next when full
+  const int n = op->ev_count;
+  const int first = n < op->ev_slots ? 0 : op->ev_next;
+  int w = 0;
+  for (int i = 0; i < n; ++i) {
+    const int j = (first + i) % op->ev_slots;
+    hipError_t err = hipEventSynchronize(op->ev[3 * j + 2]);
+    float a = 0.f, b = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&a, op->ev[3 * j], op->ev[3 * j + 1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&b, op->ev[3 * j + 1], op->ev[3 * j + 2]);
+    if (err != hipSuccess) return hip_fail(err, "hipEvent timing");
+    if (w < cap) {
+      zero_ms[w] = a;
+      kernel_ms[w] = b;
+      ++w;
+    }
+  }
+  *count = w;
   op->ev_count = 0;
   op->ev_next = 0;
   return MF_OK;

@@ -5,7 +5,9 @@
 // side streams (default priority) and join it back before returning, so every
 // call is ordered on the caller's stream as a whole.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 
@@ -270,6 +272,48 @@ static int enqueue(Batch* b, const BatchPtrs& p, hipStream_t s) {
   return MF_OK;
 }
 
+// Cache key of a batch: architecture, precision and every operator's (p, q,
+// cells, columns) in the caller's order.
+static std::string batch_key(int nops, const Operator* const* ops, const int* nvec, int prec) {
+  std::string k = device_arch() + "/batch/" +
+                  (prec == MF_FP64 ? "fp64" : prec == MF_FP32_MFMA ? "fp32" : "bf16") + "/";
+  char buf[64];
+  for (int i = 0; i < nops; ++i) {
+    std::snprintf(buf, sizeof(buf), "%sp%dq%dc%lldv%d", i ? "_" : "", ops[i]->p, ops[i]->q,
+                  (long long)ops[i]->ncells, nvec[i]);
+    k += buf;
+  }
+  return k;
+}
+
+// Batches that mf_apply_batched built, keyed by the operator handles, column
+// counts, precision and device; at most kBatchCache, least recently used
+// evicted.  Shapes chosen by mf_batch_tune, by batch key, for new batches.
+constexpr int kBatchCache = 8;
+struct CachedBatch {
+  std::vector<const Operator*> ops;
+  std::vector<int> nvec;
+  int prec = 0, device = 0;
+  Batch* b = nullptr;
+  uint64_t used = 0;
+};
+static std::mutex g_cache_mu;
+static std::vector<CachedBatch> g_cache;
+static uint64_t g_cache_clock = 0;
+static std::map<std::string, int> g_batch_tuned;
+
+void batch_cache_forget(const Operator* op) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  for (size_t i = 0; i < g_cache.size();) {
+    if (std::find(g_cache[i].ops.begin(), g_cache[i].ops.end(), op) != g_cache[i].ops.end()) {
+      mf_batch_destroy(reinterpret_cast<mf_batch*>(g_cache[i].b));
+      g_cache.erase(g_cache.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
 }  // namespace mf
 
 using namespace mf;
@@ -423,6 +467,104 @@ int mf_batch_replay(mf_batch* handle, void* stream) {
   hipError_t err = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "hipGraphLaunch");
   return MF_OK;
+}
+
+int mf_batch_tune(mf_batch* handle, const double* const* X, double* const* Y, const int64_t* ldx,
+                  const int64_t* ldy, const char* cache_path, void* stream) {
+  if (!handle) return fail(MF_ERR_ARG, "batch is NULL");
+  Batch* b = reinterpret_cast<Batch*>(handle);
+  BatchPtrs p;
+  if (int s = fill_ptrs(b, X, Y, ldx, ldy, p)) return s;
+  const std::string key = batch_key(b->nops, b->ops.data(), b->nvec.data(), b->prec);
+  int best = cache_lookup(cache_path, key);
+  if (best < 0 || best >= kBatchCfgs) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    std::vector<double> ms(kBatchCfgs, -1.0);
+    int st = err == hipSuccess ? MF_OK : hip_fail(err, "hipEventCreate");
+    best = -1;
+    for (int c = 0; c < kBatchCfgs && !st; ++c) {
+      st = build_table(b, c);
+      for (int w = 0; w < 2 && !st; ++w) st = enqueue(b, p, s);
+      std::vector<double> t;
+      for (int r = 0; r < 5 && !st; ++r) {
+        err = hipEventRecord(e0, s);
+        if (err == hipSuccess) st = enqueue(b, p, s);
+        if (err == hipSuccess && !st) err = hipEventRecord(e1, s);
+        if (err == hipSuccess && !st) err = hipEventSynchronize(e1);
+        float f = 0.f;
+        if (err == hipSuccess && !st) err = hipEventElapsedTime(&f, e0, e1);
+        if (err != hipSuccess) st = hip_fail(err, "batch tuning events");
+        t.push_back(f);
+      }
+      if (st) break;
+      std::sort(t.begin(), t.end());
+      ms[c] = t[t.size() / 2];
+      if (best < 0 || ms[c] < ms[best]) best = c;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) return st;
+    if (int s2 = cache_store(cache_path, key, best, ms)) return s2;
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    g_batch_tuned[key] = best;
+  }
+  return build_table(b, best);
+}
+
+int mf_apply_batched(int nops, mf_operator* const* ops, const double* const* X, double* const* Y,
+                     const int* nvec, int prec, void* stream) {
+  if (nops < 1 || nops > kMaxBatch) return fail(MF_ERR_ARG, "nops must be in [1, 64]");
+  if (!ops || !nvec || !X || !Y) return fail(MF_ERR_ARG, "ops, X, Y and nvec must be non-NULL");
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return hip_fail(err, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  CachedBatch* hit = nullptr;
+  for (auto& c : g_cache) {
+    if (c.prec != prec || c.device != dev || (int)c.ops.size() != nops) continue;
+    bool same = true;
+    for (int i = 0; i < nops && same; ++i)
+      same = c.ops[i] == reinterpret_cast<const Operator*>(ops[i]) && c.nvec[i] == nvec[i];
+    if (same) {
+      hit = &c;
+      break;
+    }
+  }
+  if (!hit) {
+    mf_batch* nb = nullptr;
+    if (int s = mf_batch_create(nops, ops, nvec, prec, &nb)) return s;
+    Batch* b = reinterpret_cast<Batch*>(nb);
+    const auto t = g_batch_tuned.find(batch_key(nops, b->ops.data(), nvec, prec));
+    if (t != g_batch_tuned.end()) {
+      if (int s = build_table(b, t->second)) {
+        mf_batch_destroy(nb);
+        return s;
+      }
+    }
+    if ((int)g_cache.size() >= kBatchCache) {
+      auto lru = std::min_element(g_cache.begin(), g_cache.end(),
+                                  [](const CachedBatch& a, const CachedBatch& c) { return a.used < c.used; });
+      mf_batch_destroy(reinterpret_cast<mf_batch*>(lru->b));
+      g_cache.erase(lru);
+    }
+    CachedBatch c;
+    for (int i = 0; i < nops; ++i) {
+      c.ops.push_back(reinterpret_cast<const Operator*>(ops[i]));
+      c.nvec.push_back(nvec[i]);
+    }
+    c.prec = prec;
+    c.device = dev;
+    c.b = b;
+    g_cache.push_back(std::move(c));
+    hit = &g_cache.back();
+  }
+  hit->used = ++g_cache_clock;
+  return mf_batch_apply(reinterpret_cast<mf_batch*>(hit->b), X, Y, nullptr, nullptr, stream);
 }
 
 int mf_batch_info(const mf_batch* handle, int64_t* items, int* cfg, int* grid) {

@@ -18,6 +18,17 @@ __global__ void zero_rows_kernel(double* __restrict__ Y, int64_t nrows, int ncol
   }
 }
 
+// X[i] := a fixed pseudo-random value in [-1, 1) (an integer hash of i): the
+// input the launch-shape tuner times the kernels on.
+__global__ void fill_pattern_kernel(double* __restrict__ X, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29;
+    X[i] = (double)(h >> 44) * (1.0 / (1 << 19)) - 1.0;
+  }
+}
+
 // One workgroup per node line (gy, gz) of the Nx x Ny x Nz grid.  A line on a
 // cell-face plane (gy or gz a multiple of p) is zeroed whole; otherwise only the
 // rows gx = 0, p, 2p, ... are.  Each wavefront takes rows, lanes take columns,
@@ -448,6 +459,14 @@ hipError_t launch_zero_rows(double* Y, int64_t nrows, int ncols, int64_t ld, hip
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(zero_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, Y, nrows, ncols, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_pattern(double* X, int64_t n, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(fill_pattern_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n);
   return hipGetLastError();
 }
 

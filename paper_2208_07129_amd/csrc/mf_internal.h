@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "mfmv.h"  // from the repository include directory (-I)
@@ -72,8 +74,11 @@ struct Operator {
   int64_t nodes[3] = {0, 0, 0};  // nodes per direction of the full numbering
   GridDesc grid{};
   bool box = false;           // every cell axis-aligned: diagonal 3x3 factor
-  int cfg = 0;                // launch shape of the box kernel (tuned or default)
-  int mcfg = -1;              // launch shape of the mixed-precision kernel
+  int cfg = 0;                // launch shape of the box kernel set by mf_set_launch (-1: none)
+  int mcfg = -1;              // launch shape of the mixed-precision kernel (-1: none)
+  // shapes chosen by mf_tune, per (precision, columns); used when no shape is set
+  std::map<std::pair<int, int>, int> tuned;
+  std::map<std::pair<int, int>, std::vector<double>> tuned_ms;  // median ms per shape (-1: not timed)
   int32_t* d_map = nullptr;   // E x np^3, -1 = constrained
   int32_t* d_order = nullptr; // E: processing order of the cells
   double* d_geo = nullptr;    // E x 6: mu det J (J^-1 J^-T), (00,01,02,11,12,22)
@@ -213,6 +218,18 @@ hipError_t launch_apply_box_map32(const Operator& op, const ApplyLaunch& a, hipS
 
 // FP64 fused apply; returns hipSuccess or the launch error.
 hipError_t launch_apply_f64(const Operator& op, const ApplyLaunch& a, hipStream_t s);
+// X[i] := a fixed pseudo-random value in [-1, 1) for i < n (tuner input).
+hipError_t launch_fill_pattern(double* X, int64_t n, hipStream_t s);
+// Forget (destroy) the library's cached batches of mf_apply_batched that
+// reference this operator; called when the operator is destroyed.
+void batch_cache_forget(const Operator* op);
+// "gfx950"-style architecture name of the current device (no feature suffix).
+std::string device_arch();
+// The JSON launch-shape cache of mf_tune / mf_batch_tune: a flat object of
+// key -> {"cfg": shape, "ms": [...]}.  cache_lookup returns the shape or -1;
+// cache_store rewrites the file (through a temporary file and a rename).
+int cache_lookup(const char* path, const std::string& key);
+int cache_store(const char* path, const std::string& key, int cfg, const std::vector<double>& ms);
 // Zero rows [0, nrows) x columns [0, ncols) of a row-major array with stride ld.
 hipError_t launch_zero_rows(double* Y, int64_t nrows, int ncols, int64_t ld, hipStream_t s);
 // Zero the rows of nodes on cell faces (some grid index a multiple of p) of an
@@ -278,6 +295,17 @@ hipError_t launch_adam(int64_t n, float* w, const float* g, float* m1, float* m2
 hipError_t launch_to_bf16(int64_t n, const float* src, uint16_t* dst, hipStream_t s);
 hipError_t launch_fill_f32(float* v, int64_t n, float x, hipStream_t s);
 
+
+// Launch facts of one kernel on the current device: the dynamic-LDS limit is
+// raised to `lds` when it exceeds 64 KiB, and the resident workgroups per CU
+// (at nt threads and lds bytes) and the CU count are queried.  Cached per
+// (kernel, device) under a lock, so host threads driving different devices or
+// handles see their own device's values.
+struct KernelFacts {
+  int per_cu = 1;
+  int cus = 1;
+};
+hipError_t kernel_facts(const void* kernel, int nt, size_t lds, KernelFacts& out);
 
 // Two-column (16-byte) accesses need even nvec and leading dimensions and
 // 16-byte aligned multivectors.

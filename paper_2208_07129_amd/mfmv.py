@@ -28,8 +28,9 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_create_operator", "mf_destroy_operator", "mf_operator_info", "mf_cell_order",
            "mf_apply",
            "mf_apply_add", "mf_zero", "mf_set_launch", "mf_set_launch_mixed", "mf_timing",
-           "mf_timing_read", "mf_batch_create", "mf_batch_destroy", "mf_batch_set_launch",
+           "mf_timing_read", "mf_timing_samples", "mf_batch_create", "mf_batch_destroy", "mf_batch_set_launch",
            "mf_batch_apply", "mf_batch_capture", "mf_batch_replay", "mf_batch_info",
+           "mf_tune", "mf_tune_info", "mf_batch_tune", "mf_apply_batched",
            "mf_last_error",
            # include/mfsolve.h
            "mf_diagonal", "mf_block_gram", "mf_block_gram_work", "mf_block_update", "mf_col_dots",
@@ -92,6 +93,7 @@ def lib() -> ctypes.CDLL:
             "mf_set_launch_mixed": (I, [P, I]),
             "mf_timing": (I, [P, I]),
             "mf_timing_read": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D)]),
+            "mf_timing_samples": (I, [P, I, P, P, ctypes.POINTER(I)]),
             "mf_last_error": (ctypes.c_char_p, []),
             "mf_batch_create": (I, [I, P, P, I, ctypes.POINTER(P)]),
             "mf_batch_destroy": (None, [P]),
@@ -100,6 +102,10 @@ def lib() -> ctypes.CDLL:
             "mf_batch_capture": (I, [P, P, P, P, P, P]),
             "mf_batch_replay": (I, [P, P]),
             "mf_batch_info": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(I), ctypes.POINTER(I)]),
+            "mf_tune": (I, [P, I, I, ctypes.c_char_p]),
+            "mf_tune_info": (I, [P, I, I, ctypes.POINTER(I), P, I]),
+            "mf_batch_tune": (I, [P, P, P, P, P, ctypes.c_char_p, P]),
+            "mf_apply_batched": (I, [I, P, P, P, P, I, P]),
             "mf_diagonal": (I, [P, P, P]),
             "mf_block_gram": (I, [I64, I, P, I64, P, I64, D, D, P, I, P, I64, P]),
             "mf_block_gram_work": (I64, [I64, I]),
@@ -255,6 +261,16 @@ class Operator:
     def set_launch(self, general: bool = False, cfg: int = -1):
         _check(lib().mf_set_launch(self._h, int(general), int(cfg)))
 
+    def tune(self, nvec: int, precision: str = "fp64", cache_path: Optional[str] = None) -> dict:
+        """Time the launch shapes for nvec columns and keep the fastest (mf_tune); returns
+        {"cfg": chosen shape, "ms": {shape: median ms}} (empty when taken from the cache)."""
+        prec = PRECISIONS[precision]
+        _check(lib().mf_tune(self._h, int(nvec), prec, cache_path.encode() if cache_path else None))
+        cfg = ctypes.c_int()
+        ms = (ctypes.c_double * 16)()
+        _check(lib().mf_tune_info(self._h, int(nvec), prec, ctypes.byref(cfg), ms, 16))
+        return {"cfg": cfg.value, "ms": {str(i): ms[i] for i in range(16) if ms[i] >= 0}}
+
     def set_launch_mixed(self, cfg: int = -1):
         _check(lib().mf_set_launch_mixed(self._h, int(cfg)))
 
@@ -266,6 +282,13 @@ class Operator:
         n, z, k = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
         _check(lib().mf_timing_read(self._h, ctypes.byref(n), ctypes.byref(z), ctypes.byref(k)))
         return n.value, z.value, k.value
+
+    def timing_samples(self, cap: int = 100000):
+        """Per-apply (zero-fill ms, fused-kernel ms) arrays since the last read, oldest first."""
+        z, k = np.empty(cap), np.empty(cap)
+        n = ctypes.c_int()
+        _check(lib().mf_timing_samples(self._h, cap, z.ctypes.data, k.ctypes.data, ctypes.byref(n)))
+        return z[:n.value].copy(), k[:n.value].copy()
 
     def apply_add_ptr(self, X_ptr: int, Y_ptr: int, nvec: int, ldx: int, ldy: int,
                       prec: int = MF_FP64, stream=None):
@@ -622,3 +645,26 @@ class Batch:
 
     def replay(self, stream=None):
         _check(lib().mf_batch_replay(self._h, _stream_ptr(stream)))
+
+    def tune(self, Xs, Ys, cache_path: Optional[str] = None, stream=None):
+        """Time every launch shape on these buffers and keep the fastest (mf_batch_tune)."""
+        xp, yp, lx, ly = self._arrays(Xs, Ys)
+        _check(lib().mf_batch_tune(self._h, xp, yp, lx, ly,
+                                   cache_path.encode() if cache_path else None, _stream_ptr(stream)))
+        return self.info()["cfg"]
+
+
+def apply_batched(ops: Sequence[Operator], Xs, Ys, precision: str = "fp64", stream=None):
+    """Y_i := A_i X_i in one call (mf_apply_batched; ld = nvec_i, contiguous tensors)."""
+    n = len(ops)
+    if len(Xs) != n or len(Ys) != n:
+        raise ValueError("one X and one Y per operator")
+    for X, Y, op in zip(Xs, Ys, ops):
+        if X.dim() != 2 or X.shape != Y.shape or X.shape[0] != op.ndofs or not X.is_contiguous() \
+                or not Y.is_contiguous():
+            raise ValueError("X_i, Y_i must be contiguous (ndofs_i, nvec_i)")
+    handles = (ctypes.c_void_p * n)(*[o._h.value for o in ops])
+    xp = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs])
+    yp = (ctypes.c_void_p * n)(*[Y.data_ptr() for Y in Ys])
+    nv = (ctypes.c_int * n)(*[int(X.shape[1]) for X in Xs])
+    _check(lib().mf_apply_batched(n, handles, xp, yp, nv, PRECISIONS[precision], _stream_ptr(stream)))
