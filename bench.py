@@ -632,6 +632,8 @@ def main(argv=None):
     ap.add_argument("--nvec", type=int, default=None)
     ap.add_argument("--legs", default="all",
                     help="comma-separated subset of " + ",".join(LEGS) + " (headline always runs)")
+    ap.add_argument("--launch-cfg", type=int, default=None,
+                    help="force this launch shape of the FP64 box kernel (default: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-cells", type=int, default=512)
     ap.add_argument("--cpu-sample-cells-1t", type=int, default=64)
@@ -688,6 +690,8 @@ def main(argv=None):
     w = workload(a.workload, a.nvec)
     prec = mfmv.PRECISIONS[a.precision]
     op = mfmv.Operator.from_workload(w)
+    if a.launch_cfg is not None:
+        op.set_launch(False, a.launch_cfg)
     nvec = w.nvec
     Xh = w.X()
     X = torch.from_numpy(Xh).to(dev)

@@ -55,6 +55,8 @@ def jobs():
     for p in range(1, MAX_P + 1):
         out.append(("apply_f64.hip", f"apply_f64_p{p}.o", [f"-DMF_P={p}"]))
         out.append(("apply_box.hip", f"apply_box_p{p}.o", [f"-DMF_P={p}"]))
+        if p <= 7:
+            out.append(("apply_mfma.hip", f"apply_mfma_p{p}.o", [f"-DMF_P={p}"]))
         out.append(("apply_mixed.hip", f"apply_mixed_p{p}.o", [f"-DMF_P={p}"]))
         out.append(("apply_cheb.hip", f"apply_cheb_p{p}.o", [f"-DMF_P={p}"]))
         out.append(("apply_box_map.hip", f"apply_box_map_p{p}.o", [f"-DMF_P={p}"]))

@@ -397,7 +397,8 @@ int mf::apply_dispatch(mf_operator* handle, const double* X, double* Y, int nvec
   if (ev) (void)hipEventRecord(ev[1], s);
   err = map32   ? launch_apply_box_map32(*op, a, s)
         : mixed ? launch_apply_mixed(*op, a, prec, s)
-              : (op->box       ? launch_apply_box(*op, a, s)
+              : (op->box       ? (a.cfg >= kBoxVecCfgs ? launch_apply_mfma(*op, a, s)
+                                                         : launch_apply_box(*op, a, s))
                  : op->map_box ? launch_apply_box_map(*op, a, s)
                                : launch_apply_f64(*op, a, s));
   if (err != hipSuccess) return hip_fail(err, "apply kernel launch");

@@ -343,6 +343,7 @@ hipError_t launch_apply_cheb(const Operator& op, const double* Y, double* Out, i
 bool apply_box_supported(int p, int q, int cfg) {
   if (p < 1 || p > kMaxP || q < p + 1 || q > p + kMaxQExtra || cfg < 0 || cfg >= kBoxCfgs)
     return false;
+  if (cfg >= kBoxVecCfgs) return q == p + 1 && q <= kMfmaMaxN;
   return box_cfg(p + 1, q, cfg).B > 0;
 }
 
@@ -351,7 +352,7 @@ int choose_cfg_box(int np, int nq, int nvec) {
   const int b0 = box_cfg(np, nq, 0).B;
   if (nvec >= b0) return 0;
   int best = 0, bestB = b0;
-  for (int c = 1; c < kBoxCfgs; ++c) {
+  for (int c = 1; c < kBoxVecCfgs; ++c) {
     const int b = box_cfg(np, nq, c).B;
     if (b >= nvec && b < bestB) {
       best = c;
@@ -417,6 +418,19 @@ hipError_t launch_apply_box(const Operator& op, const ApplyLaunch& a, hipStream_
     case 8: return launch_apply_box_p<8>(op, a, s);
     case 9: return launch_apply_box_p<9>(op, a, s);
     case 10: return launch_apply_box_p<10>(op, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_apply_mfma(const Operator& op, const ApplyLaunch& a, hipStream_t s) {
+  switch (op.p) {
+    case 1: return launch_apply_mfma_p<1>(op, a, s);
+    case 2: return launch_apply_mfma_p<2>(op, a, s);
+    case 3: return launch_apply_mfma_p<3>(op, a, s);
+    case 4: return launch_apply_mfma_p<4>(op, a, s);
+    case 5: return launch_apply_mfma_p<5>(op, a, s);
+    case 6: return launch_apply_mfma_p<6>(op, a, s);
+    case 7: return launch_apply_mfma_p<7>(op, a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -15,7 +15,9 @@ namespace mf {
 
 constexpr int kMaxP = 10;
 constexpr int kMaxQExtra = 3;  // q in [p+1, p+3]
-constexpr int kBoxCfgs = 10;   // launch shapes of the box-cell kernel
+constexpr int kBoxVecCfgs = 10;  // vector-ALU launch shapes of the box-cell kernel
+constexpr int kBoxCfgs = 11;     // ... and 10: the FP64 matrix-core body (q = p + 1 <= 8)
+constexpr int kMfmaMaxN = 8;     // points per direction the matrix-core body handles
 constexpr int kMixedCfgs = 7;  // launch shapes of the mixed-precision apply (4..6: FP32 vector)
 constexpr int kBatchCfgs = 6;  // launch shapes of the batched apply (3..5: one launch per kind)
 constexpr int kMaxBatch = 64;  // operators per batch (operator indices fit in a byte)
@@ -238,6 +240,8 @@ hipError_t launch_zero_shared_rows(double* Y, const int64_t nodes[3], int p, int
                                    hipStream_t s);
 // FP64 fused apply for box cells.
 hipError_t launch_apply_box(const Operator& op, const ApplyLaunch& a, hipStream_t s);
+// FP64 matrix-core body (shape 10: 8 columns per item).
+hipError_t launch_apply_mfma(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 bool apply_box_supported(int p, int q, int cfg);
 // Mixed-precision (FP32 / BF16 matrix-core) apply for box cells.
 hipError_t launch_apply_mixed(const Operator& op, const ApplyLaunch& a, int prec, hipStream_t s);

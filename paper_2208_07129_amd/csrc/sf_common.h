@@ -521,6 +521,8 @@ hipError_t launch_apply_mixed_p(const Operator& op, const ApplyLaunch& a, int pr
 template <int P>
 hipError_t launch_apply_box_p(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 template <int P>
+hipError_t launch_apply_mfma_p(const Operator& op, const ApplyLaunch& a, hipStream_t s);
+template <int P>
 hipError_t launch_cheb_p(const Operator& op, const double* Y, double* Out, int64_t ld, int nvec,
                          const ChebArgs& ca, hipStream_t s);
 
