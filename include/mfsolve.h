@@ -7,7 +7,7 @@
  * `stream` (a hipStream_t, NULL = the default stream), allocates nothing and
  * returns MF_OK or a negative mf_status (message in mf_last_error()).
  * Arguments are checked on the host: NULL pointers, n < 0, k < 1, ld < k
- * give MF_ERR_ARG; a failing HIP or rocBLAS launch gives MF_ERR_HIP.  With
+ * give MF_ERR_ARG; a failing HIP launch gives MF_ERR_HIP.  With
  * n = 0 the multivector pointers may be NULL (no rows to touch).
  */
 #ifndef MFSOLVE_H
@@ -36,10 +36,11 @@ int mf_diagonal(mf_operator* op, double* diag, void* stream);
 /* C := alpha * A^T B + beta * C, the k x k Gram block of two n x k
  * multivectors (block CG: P^T A P, P^T R, (A P)^T Z).  C is row-major with
  * leading dimension ldc >= k, on the device; with beta = 0 its old contents
- * are ignored.  Two stages: partial products of row chunks (plain GEMMs,
- * rocBLAS strided-batched dgemm) into `work` (a caller-owned device array of
- * at least mf_block_gram_work(n, k) doubles, contents undefined afterwards),
- * then the library's reduction of them into C.  C and work must not overlap each other or A, B.
+ * are ignored.  Two stages: partial products of row chunks (FP64 matrix-core
+ * kernel, 16 x 16 x 4 products over 128 x 128 blocks of C) into `work` (a
+ * caller-owned device array of at least mf_block_gram_work(n, k) doubles,
+ * contents undefined afterwards), then their reduction into C in a fixed
+ * order (the result does not depend on scheduling).  C and work must not overlap each other or A, B.
  * Errors: MF_ERR_ARG (also for a short or overlapping work array),
  * MF_ERR_HIP. */
 int mf_block_gram(int64_t n, int k, const double* A, int64_t lda, const double* B, int64_t ldb,
@@ -52,9 +53,9 @@ int64_t mf_block_gram_work(int64_t n, int k);
 
 /* Y := beta * Y + alpha * P M, with P an n x kp multivector (ldp), M a kp x k
  * row-major device matrix (ldm >= k) and Y n x k (ldy).  Y must not overlap P
- * or M.  Block-CG updates X += P alpha, R -= (A P) alpha, Z += P beta.  A
- * plain GEMM, run by rocBLAS dgemm.  Errors: MF_ERR_ARG (also for overlap),
- * MF_ERR_HIP. */
+ * or M.  Block-CG updates X += P alpha, R -= (A P) alpha, Z += P beta.  An
+ * FP64 matrix-core kernel (16 rows x 128 columns of Y per wavefront).
+ * Errors: MF_ERR_ARG (also for overlap), MF_ERR_HIP. */
 int mf_block_update(int64_t n, int k, int kp, double alpha, const double* P, int64_t ldp,
                     const double* M, int ldm, double beta, double* Y, int64_t ldy, void* stream);
 

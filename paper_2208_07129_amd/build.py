@@ -45,6 +45,7 @@ def jobs():
         ("host_setup.cpp", "host_setup.o", []),
         ("dispatch.hip", "dispatch.o", []),
         ("solver.hip", "solver.o", []),
+        ("blas64.hip", "blas64.o", []),
         ("capi_solver.cpp", "capi_solver.o", []),
         ("mlp.hip", "mlp.o", []),
         ("capi_mlp.cpp", "capi_mlp.o", []),
@@ -103,8 +104,7 @@ def build(nproc: int | None = None, verbose: bool = False, incremental: bool = F
                 print("compiled", objs[-1], flush=True)
     tmp = OUT + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
-           *[os.path.join(BUILD, o) for o in objs], f"-L{ROCM_LIB}", "-lrocblas",
-           f"-Wl,-rpath,{ROCM_LIB}"]
+           *[os.path.join(BUILD, o) for o in objs]]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -1,40 +1,12 @@
-// C ABI of the block-CG building blocks (include/mfsolve.h).  Block updates
-// and the partial products of the Gram blocks are plain GEMMs on row-major
-// (dof-major) multivectors and go to rocBLAS dgemm, read as column-major
-// transposes (a k x k result over n >> k rows is split into row chunks, a
-// strided batch, so the library GEMM gets enough output tiles); the
-// reductions and the rest are the library's kernels (solver.hip).
-#include <mutex>
+// C ABI of the block-CG building blocks (include/mfsolve.h).  Gram blocks and
+// block updates are the library's FP64 matrix-core kernels (blas64.hip); the
+// reductions and the rest are the kernels of solver.hip.
 #include <vector>
-
-#include <rocblas/rocblas.h>
 
 #include "mf_internal.h"
 #include "mfsolve.h"
 
 namespace mf {
-
-// One rocBLAS handle per device, created on first use and kept for the life
-// of the process (handles are not thread-safe: calls are serialised).
-static std::mutex g_blas_mutex;
-static std::vector<rocblas_handle> g_blas;
-
-static int blas_handle(rocblas_handle* h) {
-  int dev = 0;
-  hipError_t err = hipGetDevice(&dev);
-  if (err != hipSuccess) return hip_fail(err, "hipGetDevice");
-  if ((int)g_blas.size() <= dev) g_blas.resize(dev + 1, nullptr);
-  if (!g_blas[dev]) {
-    if (rocblas_create_handle(&g_blas[dev]) != rocblas_status_success)
-      return fail(MF_ERR_HIP, "rocblas_create_handle failed");
-  }
-  *h = g_blas[dev];
-  return MF_OK;
-}
-
-static int blas_fail(rocblas_status st, const char* what) {
-  return fail(MF_ERR_HIP, std::string(what) + ": " + rocblas_status_to_string(st));
-}
 
 static bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
   const char* a0 = static_cast<const char*>(a);
@@ -80,41 +52,12 @@ int mf_block_gram(int64_t n, int k, const double* A, int64_t lda, const double* 
       overlaps(work, ws, B, span_bytes(n, k, ldb)))
     return fail(MF_ERR_ARG, "C or work overlaps an operand");
   hipStream_t hs = static_cast<hipStream_t>(stream);
-  {
-    // partial products of row chunks by rocBLAS strided-batched dgemm (column-
-    // major: work_b (k x k) = B_b^T A_b), the tail chunk by one more dgemm, then
-    // the library's reduction into C
-    const int64_t nb = gram_blocks(n);
-    const int64_t chunk = n > 0 ? (n + nb - 1) / nb : 0;
-    const int64_t full = chunk > 0 ? n / chunk : 0;
-    const int64_t tail = n - full * chunk;
-    if (n > INT32_MAX || lda > INT32_MAX || ldb > INT32_MAX)
-      return fail(MF_ERR_UNSUPPORTED, "n and leading dimensions must fit in 32 bits");
-    std::lock_guard<std::mutex> lock(g_blas_mutex);
-    rocblas_handle h;
-    if (int st = blas_handle(&h)) return st;
-    rocblas_set_stream(h, hs);
-    const double one = 1.0, zero = 0.0;
-    if (full > 0) {
-      rocblas_status st = rocblas_dgemm_strided_batched(
-          h, rocblas_operation_none, rocblas_operation_transpose, k, k, (rocblas_int)chunk, &one,
-          B, (rocblas_int)ldb, chunk * ldb, A, (rocblas_int)lda, chunk * lda, &zero, work, k,
-          (int64_t)k * k, (rocblas_int)full);
-      if (st != rocblas_status_success) return blas_fail(st, "rocblas_dgemm_strided_batched");
-    }
-    if (tail > 0) {
-      rocblas_status st = rocblas_dgemm(
-          h, rocblas_operation_none, rocblas_operation_transpose, k, k, (rocblas_int)tail, &one,
-          B + full * chunk * ldb, (rocblas_int)ldb, A + full * chunk * lda, (rocblas_int)lda,
-          &zero, work + full * k * k, k);
-      if (st != rocblas_status_success) return blas_fail(st, "rocblas_dgemm (tail)");
-    }
-    // work_b holds the column-major transpose of the partial: sum of B^T A
-    // read as row-major is A^T B, as wanted
-    hipError_t err = launch_gram_reduce(k, (int)(full + (tail > 0)), work, alpha, beta, C, ldc, hs);
-    if (err != hipSuccess) return hip_fail(err, "Gram reduction launch");
-    return MF_OK;
-  }
+  // partial products of row chunks (matrix-core kernel), then their reduction
+  const int64_t nb = gram_chunks(n);
+  hipError_t err = launch_gram_partial(n, k, A, lda, B, ldb, nb, work, hs);
+  if (err == hipSuccess) err = launch_gram_reduce(k, (int)nb, work, alpha, beta, C, ldc, hs);
+  if (err != hipSuccess) return hip_fail(err, "Gram kernel launch");
+  return MF_OK;
 }
 
 int mf_block_update(int64_t n, int k, int kp, double alpha, const double* P, int64_t ldp,
@@ -123,21 +66,12 @@ int mf_block_update(int64_t n, int k, int kp, double alpha, const double* P, int
   if (!P || !M || !Y) return fail(MF_ERR_ARG, "P, M and Y must be non-NULL");
   if (n < 0 || k < 1 || kp < 1 || ldp < kp || ldm < k || ldy < k)
     return fail(MF_ERR_ARG, "need n >= 0, k, kp >= 1, ldp >= kp, ldm >= k, ldy >= k");
-  if (n > INT32_MAX || ldp > INT32_MAX || ldy > INT32_MAX)
-    return fail(MF_ERR_UNSUPPORTED, "n and leading dimensions must fit in 32 bits");
   const size_t ys = span_bytes(n, k, ldy);
   if (overlaps(Y, ys, P, span_bytes(n, kp, ldp)) || overlaps(Y, ys, M, span_bytes(kp, k, ldm)))
     return fail(MF_ERR_ARG, "Y overlaps P or M");
-  if (n == 0) return MF_OK;
-  std::lock_guard<std::mutex> lock(g_blas_mutex);
-  rocblas_handle h;
-  if (int s = blas_handle(&h)) return s;
-  rocblas_set_stream(h, static_cast<hipStream_t>(stream));
-  // column-major: Y^T (k x n) = beta Y^T + alpha M^T (k x kp) P^T (kp x n)
-  rocblas_status st =
-      rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, k, (rocblas_int)n, kp,
-                    &alpha, M, ldm, P, (rocblas_int)ldp, &beta, Y, (rocblas_int)ldy);
-  if (st != rocblas_status_success) return blas_fail(st, "rocblas_dgemm (update)");
+  hipError_t err = launch_block_update(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy,
+                                       static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "block update kernel launch");
   return MF_OK;
 }
 

@@ -255,6 +255,16 @@ hipError_t launch_col_dots(int64_t n, int k, const double* A, int64_t lda, const
 hipError_t launch_axpby(int64_t n, int k, double a, const double* X, int64_t ldx, double b,
                         double* Y, int64_t ldy, hipStream_t s);
 int64_t gram_blocks(int64_t n);
+// Row chunks of a Gram block on the matrix cores (gram_blocks(n), <= 512),
+// the chunk length, and the launches: partial products work[b][i k + j] of the
+// rows of chunk b, and Y := beta Y + alpha P M (blas64.hip).
+int64_t gram_chunks(int64_t n);
+int64_t gram_partial_rows(int64_t n, int64_t nb);
+hipError_t launch_gram_partial(int64_t n, int k, const double* A, int64_t lda, const double* B,
+                               int64_t ldb, int64_t nb, double* work, hipStream_t s);
+hipError_t launch_block_update(int64_t n, int k, int kp, double alpha, const double* P,
+                               int64_t ldp, const double* M, int ldm, double beta, double* Y,
+                               int64_t ldy, hipStream_t s);
 hipError_t launch_gram_reduce(int k, int nb, const double* work, double alpha, double beta,
                               double* C, int ldc, hipStream_t s);
 hipError_t launch_jacobi(int64_t n, int k, const double* diag, const double* R, int64_t ldr,

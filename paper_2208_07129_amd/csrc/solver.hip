@@ -1,7 +1,7 @@
 // Kernels of the block-CG building blocks: the operator diagonal (Jacobi),
 // column dot products, Y := aX + bY, the Jacobi scaling and the small SPD
-// solve of the k x k block step.  The Gram blocks and block updates are plain GEMMs and
-// go to rocBLAS (capi_solver.cpp).
+// solve of the k x k block step.  The Gram blocks' partial products and the
+// block updates are matrix-core kernels of their own (blas64.hip).
 #include <cmath>
 
 #include "mf_internal.h"
@@ -112,8 +112,8 @@ col_dots_kernel(int64_t n, int k, const double* __restrict__ A, int64_t lda,
 }
 
 // Gram block C = alpha A^T B + beta C in two stages: partial products of row
-// chunks (rocBLAS strided-batched dgemm, capi_solver.cpp) into work[b], then
-// their sum into C here.  Chunks of at least 2048 rows, at most 512 of them.
+// chunks (blas64.hip) into work[b], then their sum into C here, in chunk order.
+// The work array holds up to 512 chunks of at least 2048 rows.
 constexpr int kGramRows = 2048, kGramMaxBlocks = 512;
 
 // C[i][j] := alpha sum_b work[b][i][j] + beta C[i][j] (beta = 0: C not read).

@@ -52,7 +52,7 @@ def test_diagonal_matches_oracle(bc, p, q, lin):
 
 
 @pytest.mark.parametrize("n,k,kp", [(0, 3, 3), (1, 1, 1), (997, 7, 5), (5000, 64, 64),
-                                    (3001, 128, 128), (2049, 300, 17)])
+                                    (3001, 128, 128), (2049, 300, 17), (600011, 128, 130)])
 def test_dense_blocks_match_numpy(n, k, kp):
     rng = np.random.default_rng(n + k)
     A = rng.standard_normal((n, k))
@@ -74,6 +74,29 @@ def test_dense_blocks_match_numpy(n, k, kp):
     np.testing.assert_array_equal(mfmv.axpby(3.0, T(A), 0.0, Yn).cpu().numpy(), 3.0 * A)
     diag = rng.uniform(0.5, 2.0, n)
     np.testing.assert_array_equal(mfmv.jacobi(T(diag), T(A)).cpu().numpy(), A / diag[:, None])
+
+
+def test_dense_blocks_strided_and_symmetric():
+    """Leading dimensions larger than k (column blocks of wider arrays), a Gram block of a
+    multivector with itself (symmetric to rounding), and beta = 0 with a NaN-filled C."""
+    rng = np.random.default_rng(9)
+    n, k = 40000, 96
+    W = rng.standard_normal((n, 2 * k + 3))
+    A, B = W[:, 1:k + 1], W[:, k + 3:2 * k + 3]
+    Wd = T(W)
+    Ad, Bd = Wd[:, 1:k + 1], Wd[:, k + 3:2 * k + 3]
+    C = torch.full((k, k), float("nan"), dtype=torch.float64, device=dev())
+    C = mfmv.block_gram(Ad, Bd, C, alpha=1.0, beta=0.0).cpu().numpy()
+    np.testing.assert_allclose(C, A.T @ B, rtol=0, atol=1e-12 * n ** 0.5 * 10)
+    G = mfmv.block_gram(Ad, Ad).cpu().numpy()
+    np.testing.assert_allclose(G, A.T @ A, rtol=0, atol=1e-12 * n ** 0.5 * 10)
+    assert np.abs(G - G.T).max() <= 1e-12 * np.abs(G).max()
+    M = rng.standard_normal((k, k))
+    Yw = torch.zeros((n, 2 * k + 3), dtype=torch.float64, device=dev())
+    Yv = Yw[:, 2:k + 2]
+    mfmv.block_update(Ad, T(M), Yv, alpha=2.0, beta=0.0)
+    np.testing.assert_allclose(Yv.cpu().numpy(), 2.0 * A @ M, rtol=0, atol=1e-12 * k * 10)
+    assert float(Yw[:, :2].abs().max()) == 0.0 and float(Yw[:, k + 2:].abs().max()) == 0.0
 
 
 def test_dense_blocks_reject_bad_arguments():
