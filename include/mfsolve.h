@@ -47,6 +47,18 @@ int mf_block_gram(int64_t n, int k, const double* A, int64_t lda, const double* 
                   double alpha, double beta, double* C, int ldc, double* work, int64_t work_len,
                   void* stream);
 
+/* mf_block_gram without a work array, for callers that cannot allocate
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * allocation): the partial products go to a device array of the library's
+ * own (512 chunks x 128 x 128 doubles, 64 MiB, held on every GPU the library
+ * runs on until the process ends).  k <= 128.  No allocation and no host
+ * synchronisation; calls that overlap in time on one GPU share the array and
+ * race.  Same result as mf_block_gram (same kernels, same chunking).
+ * Errors: MF_ERR_ARG (NULL, n < 0, k < 1, ld < k, C overlapping A or B),
+ * MF_ERR_UNSUPPORTED (k > 128), MF_ERR_HIP. */
+int mf_block_gram_noalloc(int64_t n, int k, const double* A, int64_t lda, const double* B,
+                          int64_t ldb, double alpha, double beta, double* C, int ldc, void* stream);
+
 /* Number of doubles the work array of mf_block_gram needs for n rows and k
  * columns (at most 512 k^2), or -1 for n < 0 or k < 1. */
 int64_t mf_block_gram_work(int64_t n, int k);

@@ -5,6 +5,7 @@
 // Lane layout of v_mfma_f64_16x16x4f64 (one wavefront, D = A B + C with A
 // 16 x 4, B 4 x 16): A[i][c] in lane i + 16 c, B[c][j] in lane j + 16 c, and
 // D[i][j] in lane j + 16 (i mod 4), accumulator register i / 4.
+#include <mutex>
 
 #include "mf_internal.h"
 
@@ -293,4 +294,67 @@ hipError_t launch_block_update(int64_t n, int k, int kp, double alpha, const dou
   return hipGetLastError();
 }
 
+// ------------------------------------------------ allocation-free Gram block
+// The partial products of mf_block_gram_noalloc live in a file-scope device
+// array: kScratchChunks chunks of up to kScratchMaxK^2 doubles (64 MiB), held
+// by every GPU the library runs on until the process ends.  Every element a
+// call reads was written by the same call's partial-product kernel first, so
+// nothing needs clearing; calls that overlap in time on one GPU race.
+constexpr int kScratchMaxK = 128;
+constexpr int64_t kScratchChunks = 512;
+static __device__ __align__(256) double scratch[kScratchChunks * kScratchMaxK * kScratchMaxK];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (the array's name is
+// a host-side stand-in that must not reach a kernel).
+int scratch_address(double** out) {
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return hip_fail(err, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(MF_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (err != hipSuccess) return hip_fail(err, "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch[dev];
+  return MF_OK;
+}
+
 }  // namespace mf
+
+using namespace mf;
+
+extern "C" int mf_block_gram_noalloc(int64_t n, int k, const double* A, int64_t lda,
+                                     const double* B, int64_t ldb, double alpha, double beta,
+                                     double* C, int ldc, void* stream) {
+  if (!C || (n > 0 && (!A || !B))) return fail(MF_ERR_ARG, "A, B and C must be non-NULL");
+  if (n < 0 || k < 1 || lda < k || ldb < k || ldc < k)
+    return fail(MF_ERR_ARG, "need n >= 0, k >= 1, lda, ldb, ldc >= k");
+  if (k > kScratchMaxK)
+    return fail(MF_ERR_UNSUPPORTED,
+                "mf_block_gram_noalloc takes k <= 128 (its scratch holds 512 partial blocks of "
+                "128 x 128); use mf_block_gram with a work array");
+  const int64_t nb = gram_chunks(n);  // <= 512 = kScratchChunks
+  const char* c0 = reinterpret_cast<const char*>(C);
+  const size_t cs = ((size_t)(k - 1) * ldc + k) * sizeof(double);
+  auto overlaps = [&](const double* X, int64_t ld) {
+    if (n == 0) return false;
+    const char* x0 = reinterpret_cast<const char*>(X);
+    const size_t xs = ((size_t)(n - 1) * ld + k) * sizeof(double);
+    return c0 < x0 + xs && x0 < c0 + cs;
+  };
+  if (overlaps(A, lda) || overlaps(B, ldb)) return fail(MF_ERR_ARG, "C overlaps A or B");
+  double* work = nullptr;
+  if (int st = scratch_address(&work)) return st;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  hipError_t err = launch_gram_partial(n, k, A, lda, B, ldb, nb, work, hs);
+  if (err == hipSuccess) err = launch_gram_reduce(k, (int)nb, work, alpha, beta, C, ldc, hs);
+  if (err != hipSuccess) return hip_fail(err, "Gram kernel launch");
+  return MF_OK;
+}

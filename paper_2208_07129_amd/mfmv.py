@@ -34,7 +34,8 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_tune", "mf_tune_info", "mf_batch_tune", "mf_apply_batched",
            "mf_last_error",
            # include/mfsolve.h
-           "mf_diagonal", "mf_block_gram", "mf_block_gram_work", "mf_block_update", "mf_col_dots",
+           "mf_diagonal", "mf_block_gram", "mf_block_gram_noalloc", "mf_block_gram_work",
+           "mf_block_update", "mf_col_dots",
            "mf_axpby",
            "mf_jacobi", "mf_spd_solve",
            # include/mfmlp.h
@@ -110,6 +111,7 @@ def lib() -> ctypes.CDLL:
             "mf_diagonal": (I, [P, P, P]),
             "mf_block_gram": (I, [I64, I, P, I64, P, I64, D, D, P, I, P, I64, P]),
             "mf_block_gram_work": (I64, [I64, I]),
+            "mf_block_gram_noalloc": (I, [I64, I, P, I64, P, I64, D, D, P, I, P]),
             "mf_block_update": (I, [I64, I, I, D, P, I64, P, I, D, P, I64, P]),
             "mf_col_dots": (I, [I64, I, P, I64, P, I64, P, P]),
             "mf_axpby": (I, [I64, I, D, P, I64, D, P, I64, P]),
