@@ -42,19 +42,31 @@ int mf_gll_mass(mf_operator* op, int inv_sqrt, double* out, void* stream);
 int mf_cheb_step(mf_operator* op, const double* D, const double* Y, const double* Xp, double* Out,
                  int nvec, int64_t ld, double a, double b, double c, void* stream);
 
-/* Symmetric eigen-decomposition of a k x k block (the Rayleigh-Ritz and
- * orthogonalisation steps of Alg. ChFSi): A = V diag(w) V^T with w ascending
- * and V's columns orthonormal, by the cyclic Jacobi method in one workgroup.
+/* Symmetric eigen-decomposition of a k x k block, 1 <= k <= 2048 (the
+ * Rayleigh-Ritz and orthogonalisation steps of Alg. ChFSi, whose block holds
+ * the wanted vectors plus a buffer: Sec. 4 runs a thousand and more):
+ * A = V diag(w) V^T with w ascending and V's columns orthonormal.  k <= 64: the
+ * cyclic Jacobi method in one workgroup (work unused, may be NULL).  k > 64:
+ * the two-sided block Jacobi method (blocks of 32, k padded to a multiple of
+ * 64; each round one Jacobi sweep per block pair, then the pairs' rotations
+ * applied to the whole block and to V), in `work`, a caller-owned device
+ * array of at least mf_sym_eig_work(k) doubles (contents undefined after).
+ * The whole run is enqueued on the stream; the host never waits.
  * A: row-major k x k (lda >= k), only read; w: k entries; V: row-major k x k
  * (ldv >= k), V[i*ldv + j] = component i of eigenvector j.  With vpow != 0
  * every column j is scaled by w_j^vpow (vpow = -1/2: V diag(w)^{-1/2}, the
  * orthonormalising factor of a Gram block).  *status (device int): 0
  * converged (off-diagonal norm <= 1e-14 of the block's); 1 not converged in
  * 40 sweeps (results are the last iterate); 2 vpow != 0 and some w_j <= 0.
- * w and V must not overlap A or each other.  Errors: MF_ERR_ARG (NULL,
- * ld < k, overlap), MF_ERR_UNSUPPORTED (k < 1 or k > 64), MF_ERR_HIP. */
+ * w, V and work must not overlap A or each other.  Errors: MF_ERR_ARG (NULL,
+ * ld < k, overlap, short work), MF_ERR_UNSUPPORTED (k < 1 or k > 2048),
+ * MF_ERR_HIP. */
 int mf_sym_eig(int k, const double* A, int64_t lda, double* w, double* V, int64_t ldv,
-               double vpow, int* status, void* stream);
+               double vpow, int* status, double* work, int64_t work_len, void* stream);
+
+/* Doubles of work mf_sym_eig needs for a k x k block (0 for k <= 64), or -1
+ * for k outside 1..2048.  About 2 k^2. */
+int64_t mf_sym_eig_work(int k);
 
 #ifdef __cplusplus
 }

@@ -46,6 +46,7 @@ def jobs():
         ("dispatch.hip", "dispatch.o", []),
         ("solver.hip", "solver.o", []),
         ("blas64.hip", "blas64.o", []),
+        ("eig.hip", "eig.o", []),
         ("capi_solver.cpp", "capi_solver.o", []),
         ("mlp.hip", "mlp.o", []),
         ("capi_mlp.cpp", "capi_mlp.o", []),

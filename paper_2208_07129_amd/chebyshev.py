@@ -67,7 +67,7 @@ def standard_form_bounds(op: mfmv.Operator, D, steps: int = 60, seed: int = 0) -
 
 class SubspaceIteration:
     """Chebyshev-filtered subspace iteration (Alg. ChFSi) for the lowest
-    eigenpairs of H~ = M^{-1/2} A M^{-1/2} (eq. shep) on a block of k <= 64
+    eigenpairs of H~ = M^{-1/2} A M^{-1/2} (eq. shep) on a block of k <= 2048
     vectors: filter, orthonormalise (Gram block, its eigen-decomposition,
     X V diag(w)^{-1/2}), Rayleigh-Ritz (projected block, its eigen-decomposition,
     rotation), residual norms.  Every step is a library call; the host reads
@@ -87,6 +87,7 @@ class SubspaceIteration:
         self.st = torch.zeros(1, dtype=torch.int32, device="cuda")
         self.rn2 = torch.empty(k, dtype=torch.float64, device="cuda")
         self.gwork = mfmv.block_gram_work(n, k)
+        self.ework = mfmv.sym_eig_work(k)
 
     def rayleigh_ritz(self, B) -> tuple:
         """U, HU := the Ritz vectors of span(B) and H~ U; returns (Ritz values,
@@ -96,13 +97,14 @@ class SubspaceIteration:
         import numpy as np
         op, D = self.op, self.D
         mfmv.block_gram(B, B, self.G, work=self.gwork)                 # B^T B
-        mfmv.sym_eig(self.G, self.w, self.M, self.st, vpow=-0.5)        # V diag(w)^{-1/2}
+        mfmv.sym_eig(self.G, self.w, self.M, self.st, vpow=-0.5,
+                     work=self.ework)                                   # V diag(w)^{-1/2}
         if int(self.st.item()) != 0:
             raise RuntimeError("the filtered block lost rank (Gram block not positive definite)")
         mfmv.block_update(B, self.M, self.Xo, 1.0, 0.0)                 # orthonormal basis
         mfmv.cheb_step(op, D, self.Xo, None, self.HX, 1.0, 0.0, 0.0)   # H~ Xo
         mfmv.block_gram(self.Xo, self.HX, self.Hp, work=self.gwork)     # Xo^T H~ Xo
-        mfmv.sym_eig(self.Hp, self.theta, self.Q, self.st)
+        mfmv.sym_eig(self.Hp, self.theta, self.Q, self.st, work=self.ework)
         mfmv.block_update(self.Xo, self.Q, self.U, 1.0, 0.0)
         mfmv.block_update(self.HX, self.Q, self.HU, 1.0, 0.0)
         th = self.theta.cpu().numpy()

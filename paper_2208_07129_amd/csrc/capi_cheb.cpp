@@ -85,19 +85,36 @@ int mf_cheb_step_constrained(mf_operator* handle, const double* D, const double*
   return MF_OK;
 }
 
+int64_t mf_sym_eig_work(int k) {
+  if (k < 1 || k > eig_blocked_max_k()) return -1;
+  return k <= eig_max_k() ? 0 : sym_eig_blocked_work(k);
+}
+
 int mf_sym_eig(int k, const double* A, int64_t lda, double* w, double* V, int64_t ldv,
-               double vpow, int* status, void* stream) {
+               double vpow, int* status, double* work, int64_t work_len, void* stream) {
   if (!A || !w || !V || !status) return fail(MF_ERR_ARG, "A, w, V and status must be non-NULL");
-  if (k < 1 || k > eig_max_k()) return fail(MF_ERR_UNSUPPORTED, "need 1 <= k <= 64");
+  if (k < 1 || k > eig_blocked_max_k()) return fail(MF_ERR_UNSUPPORTED, "need 1 <= k <= 2048");
   if (lda < k || ldv < k) return fail(MF_ERR_ARG, "need lda, ldv >= k");
   const size_t as = (size_t)((k - 1) * lda + k) * sizeof(double);
   const size_t vs = (size_t)((k - 1) * ldv + k) * sizeof(double);
   const size_t ws = (size_t)k * sizeof(double);
   if (overlaps(V, vs, A, as) || overlaps(w, ws, A, as) || overlaps(w, ws, V, vs))
     return fail(MF_ERR_ARG, "w and V must not overlap A or each other");
-  hipError_t err = launch_sym_eig(k, A, lda, w, V, ldv, vpow, status,
-                                  static_cast<hipStream_t>(stream));
-  if (err != hipSuccess) return hip_fail(err, "eigen-decomposition kernel launch");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (k <= eig_max_k()) {
+    hipError_t err = launch_sym_eig(k, A, lda, w, V, ldv, vpow, status, s);
+    if (err != hipSuccess) return hip_fail(err, "eigen-decomposition kernel launch");
+    return MF_OK;
+  }
+  const int64_t need = sym_eig_blocked_work(k);
+  if (!work || work_len < need)
+    return fail(MF_ERR_ARG, "k > 64 needs a work array of mf_sym_eig_work(k) doubles");
+  const size_t wks = (size_t)need * sizeof(double);
+  if (overlaps(work, wks, A, as) || overlaps(work, wks, V, vs) || overlaps(work, wks, w, ws) ||
+      overlaps(work, wks, status, sizeof(int)))
+    return fail(MF_ERR_ARG, "work must not overlap A, w, V or status");
+  hipError_t err = launch_sym_eig_blocked(k, A, lda, w, V, ldv, vpow, status, work, s);
+  if (err != hipSuccess) return hip_fail(err, "block Jacobi kernel launch");
   return MF_OK;
 }
 

@@ -275,6 +275,12 @@ int spd_max_k();
 int eig_max_k();
 hipError_t launch_sym_eig(int k, const double* A, int64_t lda, double* w, double* V, int64_t ldv,
                           double vpow, int* status, hipStream_t s);
+// block Jacobi for 64 < k <= eig_blocked_max_k() (eig.hip)
+int eig_blocked_max_k();
+int64_t sym_eig_blocked_work(int k);
+hipError_t launch_sym_eig_blocked(int k, const double* A, int64_t lda, double* w, double* V,
+                                  int64_t ldv, double vpow, int* status, double* work,
+                                  hipStream_t s);
 // learned-preconditioner kernels (mlp.hip)
 struct GemmEpi {  // epilogue of the BF16 matrix-core GEMM (see mfmlp.h)
   const float* bias;

@@ -42,7 +42,7 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_mlp_gemm", "mf_cell_gather", "mf_cell_scatter", "mf_mse_grad", "mf_row_sums",
            "mf_adam", "mf_symmetrize", "mf_to_bf16", "mf_fill_f32",
            # include/mfcheb.h
-           "mf_gll_mass", "mf_cheb_step", "mf_sym_eig",
+           "mf_gll_mass", "mf_cheb_step", "mf_sym_eig", "mf_sym_eig_work",
            # include/mfrefine.h
            "mf_refined_sizes", "mf_refined_layout", "mf_refined_quad_points",
            "mf_create_refined_operator", "mf_apply_constrained", "mf_cheb_step_constrained",
@@ -129,7 +129,8 @@ def lib() -> ctypes.CDLL:
             "mf_fill_f32": (I, [I64, P, F32, P]),
             "mf_gll_mass": (I, [P, I, P, P]),
             "mf_cheb_step": (I, [P, P, P, P, P, I, I64, D, D, D, P]),
-            "mf_sym_eig": (I, [I, P, I64, P, P, I64, D, P, P]),
+            "mf_sym_eig": (I, [I, P, I64, P, P, I64, D, P, P, I64, P]),
+            "mf_sym_eig_work": (I64, [I]),
             "mf_refined_sizes": (I, [RP, I, ctypes.POINTER(I64), ctypes.POINTER(I64),
                                      ctypes.POINTER(I64), ctypes.POINTER(I64)]),
             "mf_refined_layout": (I, [RP, I, P, P]),
@@ -482,9 +483,18 @@ def cheb_step(op: Operator, D, Y, Xp, Out, a: float, b: float, c: float, stream=
     return Out
 
 
-def sym_eig(A, w=None, V=None, status=None, vpow: float = 0.0, stream=None):
+def sym_eig_work(k: int, device="cuda"):
+    """A work array for sym_eig on k x k blocks (None when k <= 64 needs none)."""
+    import torch
+    n = int(lib().mf_sym_eig_work(k))
+    if n < 0:
+        raise ValueError(f"sym_eig takes 1 <= k <= 2048, got {k}")
+    return None if n == 0 else torch.empty(n, dtype=torch.float64, device=device)
+
+
+def sym_eig(A, w=None, V=None, status=None, vpow: float = 0.0, work=None, stream=None):
     """(w ascending, V columns scaled by w^vpow, status) of a symmetric k x k float64
-    device block (k <= 64)."""
+    device block (k <= 2048; k > 64 takes a work array, allocated here if not given)."""
     import torch
     pa, k, k2, lda = _mv(A, "A")
     if k != k2:
@@ -495,8 +505,11 @@ def sym_eig(A, w=None, V=None, status=None, vpow: float = 0.0, stream=None):
         V = torch.empty(k, k, dtype=torch.float64, device=A.device)
     if status is None:
         status = torch.zeros(1, dtype=torch.int32, device=A.device)
+    if work is None and k > 64 and 0 < k <= 2048:
+        work = sym_eig_work(k, A.device)
     _check(lib().mf_sym_eig(k, pa, lda, w.data_ptr(), V.data_ptr(), V.stride(0), float(vpow),
-                            status.data_ptr(), _stream_ptr(stream)))
+                            status.data_ptr(), None if work is None else work.data_ptr(),
+                            0 if work is None else work.numel(), _stream_ptr(stream)))
     return w, V, status
 
 
