@@ -343,10 +343,12 @@ def solve_leg(a) -> dict:
     losses = mlp.train(net, diag, steps=a.train_steps, k=16, refresh=a.train_refresh)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    floor_status = net.floor_skip()   # the deployed linear preconditioner is SPD
     verdict = mlp.judge(net, diag, k=16)
     fit = mlp.local_fit(net, diag, k=16)
     out["training"] = {"seconds": t_train, "steps": a.train_steps, "loss_first": losses[0],
                        "loss_last": float(np.mean(losses[-10:])), "judge": verdict,
+                       "skip_floor_status": floor_status,
                        "local_fit": fit}
     print(json.dumps({"training": out["training"]}), file=sys.stderr, flush=True)
     use_net = bool(verdict["ratio"] < 1.0)

@@ -52,23 +52,50 @@ int mf_mlp_gemm(int M, int N, int K, int ta, int tb, const uint16_t* A, int64_t 
  * E[node_i][j] sqrt(dscale[node_i]) / rho (FP32; no partition weight): the
  * training target for the pair (R, E).  R and E are ndofs x k multivectors
  * (ldr, lde >= k); X0t and Tt are Fp x (ncells k) with leading dimension
- * ldx >= ncells k; rho has ncells k entries.  Fp >= F, multiple of 8.
- * Errors: MF_ERR_ARG, MF_ERR_HIP. */
+ * ldx >= ncells k; rho has ncells k entries, or is NULL: then rho = 1 (no
+ * normalisation, one pass over R; for a linear cell map, where the scale
+ * cancels).  Fp >= F, multiple of 8.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
 int mf_cell_gather(mf_operator* op, int k, const double* R, int64_t ldr, const double* E,
                    int64_t lde, int Fp, uint16_t* X0t, float* Tt, int64_t ldx, float* rho,
                    int pou_sqrt, const double* dscale, void* stream);
 
 /* Z := Z0 + sum_e Q_e^T W_e (rho * Yt): the partition-of-unity assembly of
  * the network outputs Yt (FP32, first F rows used, ldy >= ncells k) scaled
- * back by rho, with W_e the weights w_i (or sqrt(w_i) when pou_sqrt != 0:
- * with the same weighting of the input, a symmetric cell map then gives a
- * symmetric preconditioner), divided by sqrt(dscale[node]) when dscale !=
- * NULL, on top of Z0 = R / diag row-wise (the Jacobi term) when diag != NULL,
- * else Z0 = 0.  Z (ndofs x k, ldz >= k) is overwritten; it must not be R.
- * Errors: MF_ERR_ARG, MF_ERR_HIP. */
+ * back by rho (1 when rho is NULL), with W_e the weights w_i (or sqrt(w_i)
+ * when pou_sqrt != 0: with the same weighting of the input, a symmetric cell
+ * map then gives a symmetric preconditioner), divided by sqrt(dscale[node])
+ * when dscale != NULL, on top of Z0 = R / diag row-wise (the Jacobi term)
+ * when diag != NULL, else Z0 = 0.  Taken node by node (each Z element summed
+ * by one thread over the node's cells in a fixed order, no atomics), so the
+ * result is bitwise reproducible.  Z (ndofs x k, ldz >= k) is overwritten;
+ * it must not be R.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
 int mf_cell_scatter(mf_operator* op, int k, const float* Yt, int64_t ldy, const float* rho,
                     const double* diag, const double* R, int64_t ldr, double* Z, int64_t ldz,
                     int pou_sqrt, const double* dscale, void* stream);
+
+/* Eigenvalue floor of the symmetric skip block S of the cell network, the
+ * step that makes the deployed linear preconditioner
+ *   z = D^-1 r + sum_e Q_e^T W_e^1/2 D^-1/2 S D^-1/2 W_e^1/2 Q_e r
+ * symmetric positive definite: with the partition of unity sum_e Q_e^T W_e
+ * Q_e = I on the free nodes this is D^-1/2 [sum_e Q_e^T W_e^1/2 (I + S)
+ * W_e^1/2 Q_e] D^-1/2, whose smallest eigenvalue is at least that of I + S
+ * (relative to D^-1).  S (F x F, FP32, row-major, ld lds) is symmetrised,
+ * decomposed (mf_sym_eig: S = V diag(w) V^T) and rebuilt with its eigenvalues
+ * raised to at least floor = -1 + margin + 2^-8 (||w||_2 + sqrt(F)): the
+ * rebuilt block has Frobenius norm at most ||w||_2 + sqrt(F), so its BF16
+ * copy differs from it by at most 2^-9 of that in 2-norm, and I + S stays
+ * definite, with smallest eigenvalue above margin, after the rounding.  The
+ * result, exactly symmetric, is written over S and, rounded to BF16, over Sbf
+ * (ld ldsb).  work: a device array of at least mf_skip_floor_work(F) doubles;
+ * *status (device int): that of mf_sym_eig.  margin >= 0.  Errors: MF_ERR_ARG
+ * (NULL, ld < F, short work, margin < 0), MF_ERR_UNSUPPORTED (F < 1 or
+ * F > 2048), MF_ERR_HIP. */
+int mf_skip_floor(int F, float* S, int64_t lds, uint16_t* Sbf, int64_t ldsb, double margin,
+                  double* work, int64_t work_len, int* status, void* stream);
+
+/* Doubles of work mf_skip_floor needs for an F x F skip block (-1 outside
+ * 1..2048). */
+int64_t mf_skip_floor_work(int F);
 
 /* Weighted squared error over rows and the first F features, w = roww[n]
  * (FP32 per row; NULL means 1):

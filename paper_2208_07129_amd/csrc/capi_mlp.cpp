@@ -2,6 +2,7 @@
 #include <cstdint>
 
 #include "mf_internal.h"
+#include "mfcheb.h"
 #include "mfmlp.h"
 
 namespace mf {
@@ -40,7 +41,7 @@ int mf_mlp_gemm(int M, int N, int K, int ta, int tb, const uint16_t* A, int64_t 
 int mf_cell_gather(mf_operator* handle, int k, const double* R, int64_t ldr, const double* E,
                    int64_t lde, int Fp, uint16_t* X0t, float* Tt, int64_t ldx, float* rho,
                    int pou_sqrt, const double* dscale, void* stream) {
-  if (!handle || !R || !X0t || !rho) return fail(MF_ERR_ARG, "operator, R, X0t, rho non-NULL");
+  if (!handle || !R || !X0t) return fail(MF_ERR_ARG, "operator, R, X0t non-NULL");
   Operator* op = reinterpret_cast<Operator*>(handle);
   if (op->refined) return fail(MF_ERR_UNSUPPORTED, "cell gather/scatter are built for uniform box meshes");
   const int F = op->np * op->np * op->np;
@@ -58,7 +59,7 @@ int mf_cell_gather(mf_operator* handle, int k, const double* R, int64_t ldr, con
 int mf_cell_scatter(mf_operator* handle, int k, const float* Yt, int64_t ldy, const float* rho,
                     const double* diag, const double* R, int64_t ldr, double* Z, int64_t ldz,
                     int pou_sqrt, const double* dscale, void* stream) {
-  if (!handle || !Yt || !rho || !Z) return fail(MF_ERR_ARG, "operator, Yt, rho, Z non-NULL");
+  if (!handle || !Yt || !Z) return fail(MF_ERR_ARG, "operator, Yt, Z non-NULL");
   Operator* op = reinterpret_cast<Operator*>(handle);
   if (op->refined) return fail(MF_ERR_UNSUPPORTED, "cell gather/scatter are built for uniform box meshes");
   if (k < 1 || ldz < k) return fail(MF_ERR_ARG, "need k >= 1, ldz >= k");
@@ -68,6 +69,33 @@ int mf_cell_scatter(mf_operator* handle, int k, const float* Yt, int64_t ldy, co
   hipError_t err = launch_cell_scatter(*op, k, Yt, ldy, rho, diag, R, ldr, Z, ldz, pou_sqrt,
                                        dscale, static_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "cell scatter launch");
+  return MF_OK;
+}
+
+int64_t mf_skip_floor_work(int F) {
+  const int64_t eig = mf_sym_eig_work(F);
+  if (eig < 0) return -1;
+  return 2 * (int64_t)F * F + ((F + 7) / 8) * 8 + eig;
+}
+
+int mf_skip_floor(int F, float* S, int64_t lds, uint16_t* Sbf, int64_t ldsb, double margin,
+                  double* work, int64_t work_len, int* status, void* stream) {
+  if (!(margin >= 0.0)) return fail(MF_ERR_ARG, "margin must be >= 0");
+  if (!S || !Sbf || !work || !status) return fail(MF_ERR_ARG, "S, Sbf, work, status non-NULL");
+  const int64_t need = mf_skip_floor_work(F);
+  if (need < 0) return fail(MF_ERR_UNSUPPORTED, "need 1 <= F <= 2048");
+  if (lds < F || ldsb < F) return fail(MF_ERR_ARG, "need lds, ldsb >= F");
+  if (work_len < need) return fail(MF_ERR_ARG, "work shorter than mf_skip_floor_work(F)");
+  double* A = work;                        // F x F, the symmetrised block
+  double* V = A + (int64_t)F * F;          // F x F, eigenvectors
+  double* w = V + (int64_t)F * F;          // F eigenvalues (padded to 8)
+  double* ew = w + ((F + 7) / 8) * 8;      // mf_sym_eig's own work
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t err = launch_skip_sym(F, S, lds, A, s);
+  if (err != hipSuccess) return hip_fail(err, "skip symmetrise launch");
+  if (int st = mf_sym_eig(F, A, F, w, V, F, 0.0, status, ew, need - (ew - work), stream)) return st;
+  err = launch_skip_rebuild(F, V, w, margin, S, lds, Sbf, ldsb, s);
+  if (err != hipSuccess) return hip_fail(err, "skip rebuild launch");
   return MF_OK;
 }
 

@@ -275,6 +275,11 @@ int spd_max_k();
 int eig_max_k();
 hipError_t launch_sym_eig(int k, const double* A, int64_t lda, double* w, double* V, int64_t ldv,
                           double vpow, int* status, hipStream_t s);
+// the skip block's eigenvalue floor (mlp.hip): A = (S + S^T) / 2 in FP64, and
+// S = Sbf = V max(w, floor) V^T, floor = -1 + margin + 2^-8 (||w|| + sqrt(F))
+hipError_t launch_skip_sym(int F, const float* S, int64_t lds, double* A, hipStream_t s);
+hipError_t launch_skip_rebuild(int F, const double* V, const double* w, double margin, float* S,
+                               int64_t lds, uint16_t* Sbf, int64_t ldsb, hipStream_t s);
 // block Jacobi for 64 < k <= eig_blocked_max_k() (eig.hip)
 int eig_blocked_max_k();
 int64_t sym_eig_blocked_work(int k);

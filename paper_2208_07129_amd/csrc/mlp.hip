@@ -188,23 +188,26 @@ cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int6
   const int cx = e % g.n[0], cy = (e / g.n[0]) % g.n[1], cz = e / (g.n[0] * g.n[1]);
   cell_node_factors(g, np, cx, cy, cz, pou_sqrt, dsc, snode, sfin, sdh);
   __syncthreads();
-  double ss = 0.0;
-  if (j < k)
-    for (int i = ph; i < F; i += 4) {
-      const int node = snode[i];
-      if (node >= 0) {
-        const double x = R[(int64_t)node * ldr + j] * sfin[i];
-        ss = fma(x, x, ss);
+  double s = 1.0;  // without rho: no normalisation
+  if (rho) {
+    double ss = 0.0;
+    if (j < k)
+      for (int i = ph; i < F; i += 4) {
+        const int node = snode[i];
+        if (node >= 0) {
+          const double x = R[(int64_t)node * ldr + j] * sfin[i];
+          ss = fma(x, x, ss);
+        }
       }
-    }
-  part[t] = ss;
-  __syncthreads();
-  double tot = part[jj] + part[jj + 64] + part[jj + 128] + part[jj + 192];
-  const double r = sqrt(tot / F);
-  const double s = r > 0.0 ? 1.0 / r : 0.0;
+    part[t] = ss;
+    __syncthreads();
+    double tot = part[jj] + part[jj + 64] + part[jj + 128] + part[jj + 192];
+    const double r = sqrt(tot / F);
+    s = r > 0.0 ? 1.0 / r : 0.0;
+    if (j < k && ph == 0) rho[(int64_t)e * k + j] = (float)r;
+  }
   const int64_t row = (int64_t)e * k + j;
   if (j >= k) return;
-  if (ph == 0) rho[row] = (float)r;
   for (int i = ph; i < Fp; i += 4) {
     double x = 0.0, y = 0.0;
     if (i < F) {
@@ -219,42 +222,79 @@ cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int6
   }
 }
 
-// Z[node][j] += w(node) rho[row] Yt[i][row] over the cell's free nodes
-// (partition-of-unity average of the cell-local predictions; w or sqrt(w),
-// divided by sqrt(dsc[node])), the per-node factors formed once in LDS.
-__global__ void __launch_bounds__(256)
-cell_scatter_kernel(GridDesc g, int np, int k, const float* __restrict__ Yt, int64_t ldy,
-                    const float* __restrict__ rho, double* __restrict__ Z, int64_t ldz,
-                    int pou_sqrt, const double* __restrict__ dsc) {
-  __shared__ int snode[kMaxCellNodes];
-  __shared__ double sfac[kMaxCellNodes];
-  const int e = blockIdx.x;
-  const int j0 = blockIdx.y * kCols;
-  const int t = threadIdx.x, jj = t % kCols, ph = t / kCols;
-  const int j = j0 + jj;
-  const int F = np * np * np;
-  const int cx = e % g.n[0], cy = (e / g.n[0]) % g.n[1], cz = e / (g.n[0] * g.n[1]);
-  for (int i = t; i < F; i += blockDim.x) {
-    const int i1 = i % np, i2 = (i / np) % np, i3 = i / (np * np);
-    const int node = grid_node(g, cx, cy, cz, i1, i2, i3);
-    double w = 0.0;
-    if (node >= 0) {
-      const double pw = pou_weight(g, i1, i2, i3, cx, cy, cz);
-      w = pou_sqrt ? sqrt(pw) : pw;
-      if (dsc) w /= sqrt(dsc[node]);
-    }
-    snode[i] = node;
-    sfac[i] = w;
+// The incidences of grid node g (0 <= g < N) along one direction: the cells
+// c[0..cnt) holding it and its local index l[] there, with the
+// partition-of-unity factor of the direction (1/2 when two cells share the
+// node, 1 otherwise, as pou_weight).  Periodic directions have N = n p (node
+// n p is node 0); with n = 1 a vertex node meets the one cell twice.
+__device__ inline int node_incidences(int g, int n, int N, int p, int* c, int* l, double* w) {
+  const bool periodic = N == n * p;
+  const int cq = g / p, r = g - cq * p;
+  if (r != 0) {
+    c[0] = cq;
+    l[0] = r;
+    *w = 1.0;
+    return 1;
   }
-  __syncthreads();
-  if (j >= k) return;
-  const int64_t row = (int64_t)e * k + j;
-  const double r = rho[row];
-  for (int i = ph; i < F; i += 4) {
-    const int node = snode[i];
-    if (node < 0) continue;
-    unsafeAtomicAdd(Z + (int64_t)node * ldz + j, sfac[i] * r * (double)Yt[(int64_t)i * ldy + row]);
+  int cnt = 0;
+  if (cq < n) {  // the cell starting at the node
+    c[cnt] = cq;
+    l[cnt++] = 0;
   }
+  if (cq > 0 || periodic) {  // the cell ending at the node
+    c[cnt] = cq > 0 ? cq - 1 : n - 1;
+    l[cnt++] = p;
+  }
+  *w = cnt == 2 ? 0.5 : 1.0;
+  return cnt;
+}
+
+// Z[node][j] = (R[node][j] / diag[node] or 0) + sum over the node's
+// incidences (cell e, local node i) of w^[1/2] rho[e k + j] Yt[i][e k + j]
+// (divided by sqrt(dsc[node])): the partition-of-unity assembly taken node by
+// node, so every Z element is written once by one lane, with a fixed order of
+// its up to eight terms (no atomics; bitwise reproducible).  One wavefront per
+// (node, 64 columns): lanes over the columns, so the loads of Yt, rho, R and
+// the store of Z are contiguous runs.  Constrained nodes get only the Jacobi
+// term, as the scattered form never adds to them.
+constexpr int kAsmNodes = 4;  // nodes (wavefronts) per workgroup
+__global__ void __launch_bounds__(64 * kAsmNodes)
+node_assemble_kernel(GridDesc g, int np, int k, int64_t nnodes, const float* __restrict__ Yt,
+                     int64_t ldy, const float* __restrict__ rho, const double* __restrict__ diag,
+                     const double* __restrict__ R, int64_t ldr, double* __restrict__ Z,
+                     int64_t ldz, int pou_sqrt, const double* __restrict__ dsc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t node = (int64_t)blockIdx.x * kAsmNodes + (threadIdx.x >> 6);
+  const int j = blockIdx.y * 64 + lane;
+  if (node >= nnodes || j >= k) return;
+  const int gx = (int)(node % g.N[0]), gy = (int)((node / g.N[0]) % g.N[1]);
+  const int gz = (int)(node / ((int64_t)g.N[0] * g.N[1]));
+  double z = diag ? R[node * ldr + j] / diag[node] : 0.0;
+  const bool constrained =
+      g.dirichlet && (gx == 0 || gx == g.N[0] - 1 || gy == 0 || gy == g.N[1] - 1 || gz == 0 ||
+                      gz == g.N[2] - 1);
+  if (!constrained) {
+    int cx[2], cy[2], cz[2], lx[2], ly[2], lz[2];
+    double wx, wy, wz;
+    const int nx = node_incidences(gx, g.n[0], g.N[0], g.p, cx, lx, &wx);
+    const int ny = node_incidences(gy, g.n[1], g.N[1], g.p, cy, ly, &wy);
+    const int nz = node_incidences(gz, g.n[2], g.N[2], g.p, cz, lz, &wz);
+    const double pw = wx * wy * wz;
+    double f = pou_sqrt ? sqrt(pw) : pw;
+    if (dsc) f /= sqrt(dsc[node]);
+    double acc = 0.0;
+    for (int c = 0; c < nz; ++c)
+      for (int b = 0; b < ny; ++b)
+        for (int a = 0; a < nx; ++a) {
+          const int64_t e = cx[a] + (int64_t)g.n[0] * (cy[b] + (int64_t)g.n[1] * cz[c]);
+          const int i = lx[a] + np * (ly[b] + np * lz[c]);
+          const int64_t row = e * k + j;
+          const double y = (double)Yt[(int64_t)i * ldy + row];
+          acc = fma(rho ? (double)rho[row] : 1.0, y, acc);
+        }
+    z = fma(f, acc, z);
+  }
+  Z[node * ldz + j] = z;
 }
 
 // dYt = 2 scale w[n] (Yt - Tt) for features < F (0 for the padding), as
@@ -354,15 +394,39 @@ __global__ void fill_f32_kernel(float* __restrict__ v, int64_t n, float x) {
     v[i] = x;
 }
 
-// Z := R / diag row-wise, or 0 when diag is null (start of the assembly).
-__global__ void init_z_kernel(double* __restrict__ Z, int64_t rows, int cols, int64_t ldz,
-                              const double* __restrict__ diag, const double* __restrict__ R,
-                              int64_t ldr) {
-  // a wavefront per row, lanes over the columns (no per-element index division)
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int64_t r = (int64_t)blockIdx.x * nw + w; r < rows; r += (int64_t)gridDim.x * nw) {
-    const double d = diag ? diag[r] : 1.0;
-    for (int c = lane; c < cols; c += 64) Z[r * ldz + c] = diag ? R[r * ldr + c] / d : 0.0;
+// A[i][j] = (S[i][j] + S[j][i]) / 2 in FP64.
+__global__ void skip_sym_kernel(int F, const float* __restrict__ S, int64_t lds,
+                                double* __restrict__ A) {
+  const int64_t total = (int64_t)F * F;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / F), j = (int)(idx - (int64_t)i * F);
+    A[idx] = 0.5 * ((double)S[(int64_t)i * lds + j] + (double)S[(int64_t)j * lds + i]);
+  }
+}
+
+// S[i][j] = sum_r V[i][r] max(w_r, floor) V[j][r], written to S (FP32) and
+// Sbf (BF16), floor = -1 + margin + 2^-8 (||w||_2 + sqrt(F)) (every thread
+// forms it in the same order).  The product V[i][r] V[j][r] is formed first,
+// so (i, j) and (j, i) take identical operations: exactly symmetric.
+__global__ void skip_rebuild_kernel(int F, const double* __restrict__ V,
+                                    const double* __restrict__ w, double margin,
+                                    float* __restrict__ S, int64_t lds, uint16_t* __restrict__ Sbf,
+                                    int64_t ldsb) {
+  double n2 = 0.0;
+  for (int r = 0; r < F; ++r) n2 = fma(w[r], w[r], n2);
+  const double floor = -1.0 + margin + 0.00390625 * (sqrt(n2) + sqrt((double)F));
+  const int64_t total = (int64_t)F * F;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / F), j = (int)(idx - (int64_t)i * F);
+    double acc = 0.0;
+    for (int r = 0; r < F; ++r) {
+      const double lam = w[r] > floor ? w[r] : floor;
+      acc = fma(V[(int64_t)i * F + r] * V[(int64_t)j * F + r], lam, acc);
+    }
+    S[(int64_t)i * lds + j] = (float)acc;
+    Sbf[(int64_t)i * ldsb + j] = f32_to_bf16((float)acc);
   }
 }
 
@@ -402,17 +466,26 @@ hipError_t launch_cell_gather(const Operator& op, int k, const double* R, int64_
   return hipGetLastError();
 }
 
+hipError_t launch_skip_sym(int F, const float* S, int64_t lds, double* A, hipStream_t s) {
+  hipLaunchKernelGGL(skip_sym_kernel, dim3(blocks_for((int64_t)F * F)), dim3(256), 0, s, F, S, lds,
+                     A);
+  return hipGetLastError();
+}
+
+hipError_t launch_skip_rebuild(int F, const double* V, const double* w, double margin, float* S,
+                               int64_t lds, uint16_t* Sbf, int64_t ldsb, hipStream_t s) {
+  hipLaunchKernelGGL(skip_rebuild_kernel, dim3(blocks_for((int64_t)F * F)), dim3(256), 0, s, F, V,
+                     w, margin, S, lds, Sbf, ldsb);
+  return hipGetLastError();
+}
+
 hipError_t launch_cell_scatter(const Operator& op, int k, const float* Yt, int64_t ldy,
                                const float* rho, const double* diag, const double* R, int64_t ldr,
                                double* Z, int64_t ldz, int pou_sqrt, const double* dsc,
                                hipStream_t s) {
-  hipLaunchKernelGGL(init_z_kernel, dim3(blocks_for(op.ndofs * 64)), dim3(256), 0, s, Z,
-                     op.ndofs, k, ldz, diag, R, ldr);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  dim3 grid((unsigned)op.ncells, (k + kCols - 1) / kCols);
-  hipLaunchKernelGGL(cell_scatter_kernel, grid, dim3(256), 0, s, op.grid, op.np, k, Yt, ldy, rho,
-                     Z, ldz, pou_sqrt, dsc);
+  dim3 grid((unsigned)((op.ndofs + kAsmNodes - 1) / kAsmNodes), (unsigned)((k + 63) / 64));
+  hipLaunchKernelGGL(node_assemble_kernel, grid, dim3(64 * kAsmNodes), 0, s, op.grid, op.np, k,
+                     (int64_t)op.ndofs, Yt, ldy, rho, diag, R, ldr, Z, ldz, pou_sqrt, dsc);
   return hipGetLastError();
 }
 

@@ -40,7 +40,8 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_jacobi", "mf_spd_solve",
            # include/mfmlp.h
            "mf_mlp_gemm", "mf_cell_gather", "mf_cell_scatter", "mf_mse_grad", "mf_row_sums",
-           "mf_adam", "mf_symmetrize", "mf_to_bf16", "mf_fill_f32",
+           "mf_adam", "mf_symmetrize", "mf_to_bf16", "mf_fill_f32", "mf_skip_floor",
+           "mf_skip_floor_work",
            # include/mfcheb.h
            "mf_gll_mass", "mf_cheb_step", "mf_sym_eig", "mf_sym_eig_work",
            # include/mfrefine.h
@@ -122,6 +123,8 @@ def lib() -> ctypes.CDLL:
             "mf_cell_gather": (I, [P, I, P, I64, P, I64, I, P, P, I64, P, I, P, P]),
             "mf_cell_scatter": (I, [P, I, P, I64, P, P, P, I64, P, I64, I, P, P]),
             "mf_symmetrize": (I, [I, P, I64, P, P]),
+            "mf_skip_floor": (I, [I, P, I64, P, I64, D, P, I64, P, P]),
+            "mf_skip_floor_work": (I64, [I]),
             "mf_mse_grad": (I, [I, I, I64, P, P, I64, P, F32, P, P, P]),
             "mf_row_sums": (I, [I, I64, P, I64, P, I, P]),
             "mf_adam": (I, [I64, P, P, P, P, P, F32, F32, F32, F32, I, P]),

@@ -136,6 +136,23 @@ def test_cell_gather_and_scatter_match_oracle(bc):
                                        pou_sqrt=bool(sq), dscale=None if ds is None else diag)
                 np.testing.assert_allclose(Z.cpu().numpy(), ref, rtol=0,
                                            atol=1e-10 * np.abs(ref).max())
+    # the assembly is taken node by node in a fixed order: bitwise reproducible
+    Z2 = torch.empty_like(Z)
+    mfmv._check(mfmv.lib().mf_cell_scatter(
+        op._h, k, b["Y"].data_ptr(), b["ld"], b["rho"].data_ptr(), dd.data_ptr(), Rd.data_ptr(),
+        k, Z2.data_ptr(), k, 1, dd.data_ptr(), None))
+    assert torch.equal(Z, Z2)
+    # without rho: the gather does not normalise and the assembly takes rho = 1
+    b1 = net.gather(Rt, pou_sqrt=True, normalise=False)
+    x1 = (b1["X0"].cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    U = Xs * rhos[:, None]
+    assert np.all(np.abs(x1.astype(np.float64)[:F, :rows].T - U) <= np.abs(U) * 2 ** -8 + 1e-30)
+    mfmv._check(mfmv.lib().mf_cell_scatter(
+        op._h, k, b["Y"].data_ptr(), b["ld"], None, dd.data_ptr(), Rd.data_ptr(), k,
+        Z.data_ptr(), k, 1, dd.data_ptr(), None))
+    ref = mo.cell_assemble(mesh, p, Y[:F, :rows].T.astype(np.float64), np.ones(rows), k, R, diag,
+                           pou_sqrt=True, dscale=diag)
+    np.testing.assert_allclose(Z.cpu().numpy(), ref, rtol=0, atol=1e-10 * np.abs(ref).max())
     # diagonally scaled network inputs and targets
     net.dscale = dd
     bd = net.gather(Rt, Et, pou_sqrt=True)
@@ -145,6 +162,93 @@ def test_cell_gather_and_scatter_match_oracle(bc):
     assert np.all(np.abs(xd.astype(np.float64)[:F, :rows].T - Xd) <= np.abs(Xd) * 2 ** -8 + 1e-30)
     np.testing.assert_allclose(bd["T"].cpu().numpy()[:F, :rows].T, Td, rtol=1e-6,
                                atol=1e-6 * np.abs(Td).max())
+
+
+@pytest.mark.parametrize("n", [(1, 3, 2), (1, 1, 1)])
+def test_node_assembly_with_one_cell_periodic_directions(n):
+    """A one-cell periodic direction: the vertex nodes meet the same cell twice
+    (local 0 and local p), each incidence with weight 1/2."""
+    mesh, op = small_op(W.BC_PERIODIC, p=2, n=n)
+    k, F = 5, 27
+    net = mlp.CellMLP(op, hidden=8, seed=2)
+    b = net._buffers(k)
+    rows = op.ncells * k
+    rng = np.random.default_rng(11)
+    Y = rng.standard_normal((net.Fp, b["ld"])).astype(np.float32)
+    b["Y"].copy_(torch.from_numpy(Y))
+    rho = rng.uniform(0.5, 2.0, b["ld"]).astype(np.float32)
+    b["rho"].copy_(torch.from_numpy(rho))
+    R = rng.standard_normal((op.ndofs, k))
+    diag = rng.uniform(1.0, 2.0, op.ndofs)
+    Rd, dd = torch.from_numpy(R).to(dev()), torch.from_numpy(diag).to(dev())
+    Z = torch.empty_like(Rd)
+    for sq in (0, 1):
+        mfmv._check(mfmv.lib().mf_cell_scatter(
+            op._h, k, b["Y"].data_ptr(), b["ld"], b["rho"].data_ptr(), dd.data_ptr(),
+            Rd.data_ptr(), k, Z.data_ptr(), k, sq, dd.data_ptr(), None))
+        ref = mo.cell_assemble(mesh, op.p, Y[:F, :rows].T.astype(np.float64),
+                               rho[:rows].astype(np.float64), k, R, diag, pou_sqrt=bool(sq),
+                               dscale=diag)
+        np.testing.assert_allclose(Z.cpu().numpy(), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_skip_floor_rebuilds_the_spectrum():
+    """mf_skip_floor on a random symmetric skip block with eigenvalues below -1:
+    the rebuilt block has the eigenvalues max(w, floor) (floor from the block's
+    own norm), is exactly symmetric, and its BF16 copy is its rounding."""
+    mesh, op = small_op(W.BC_PERIODIC, p=3, n=(2, 2, 2))
+    net = mlp.CellMLP(op, hidden=16, seed=3)
+    H, F = net.H, net.F
+    rng = np.random.default_rng(4)
+    Q, _ = np.linalg.qr(rng.standard_normal((F, F)))
+    w = np.linspace(-3.0, 2.0, F)
+    S = ((Q * w) @ Q.T).astype(np.float32)
+    with torch.no_grad():
+        net.params[4][:F, H:H + F] = torch.from_numpy(S).to(dev())
+    assert net.floor_skip(margin=0.05) == 0
+    Sd = net.params[4][:F, H:H + F].cpu().numpy()
+    assert np.array_equal(Sd, Sd.T)
+    S64 = (S.astype(np.float64) + S.T.astype(np.float64)) / 2
+    ws = np.linalg.eigvalsh(S64)
+    floor = -1.0 + 0.05 + 2.0 ** -8 * (np.sqrt((ws ** 2).sum()) + np.sqrt(F))
+    np.testing.assert_allclose(np.linalg.eigvalsh(Sd.astype(np.float64)), np.maximum(ws, floor),
+                               rtol=0, atol=2e-6 * np.abs(ws).max())
+    bf = net.wbf[4][:F, H:H + F].cpu().numpy()
+    assert np.array_equal(bf, mlp._host_bf16(Sd))
+    # the rest of the last layer is untouched
+    assert np.all(net.params[4][:F, :H].cpu().numpy() == 0.0)
+
+
+def test_floored_skip_gives_a_positive_definite_preconditioner():
+    """The linear preconditioner with S = -4 I is indefinite; after the floor it
+    is D^-1/2 (1 + floor) D^-1/2 (partition of unity), positive definite.  Built
+    densely by applying it to the unit vectors (up to the BF16 rounding of its
+    input, so the symmetric part is judged)."""
+    mesh, op = small_op(W.BC_PERIODIC, p=2, n=(2, 2, 2))
+    diag = mfmv.diagonal(op)
+    net = mlp.CellMLP(op, hidden=8, seed=1, dscale=diag)
+    H, F, n = net.H, net.F, op.ndofs
+    with torch.no_grad():
+        net.params[4].zero_()
+        net.params[4][:F, H:H + F] = -4.0 * torch.eye(F, device=dev())
+        net.wbf[4].copy_(torch.from_numpy(mlp._host_bf16(net.params[4].cpu().numpy())))
+    I = torch.eye(n, dtype=torch.float64, device=dev())
+    Z = torch.empty_like(I)
+    dh = np.sqrt(diag.cpu().numpy())
+
+    def scaled_sym():
+        net.precondition(I, Z, diag, linear=True)
+        M = Z.cpu().numpy()
+        M = dh[:, None] * M * dh[None, :]
+        return np.linalg.eigvalsh((M + M.T) / 2)
+
+    assert scaled_sym().min() < -1.0
+    assert net.floor_skip(margin=0.02) == 0
+    floor = -1.0 + 0.02 + 2.0 ** -8 * (4.0 * np.sqrt(F) + np.sqrt(F))
+    ev = scaled_sym()
+    assert ev.min() > 0.0
+    # BF16 rounding of the floored block (2^-9 of 0.88) and of the input
+    np.testing.assert_allclose(ev, 1.0 + floor, rtol=0.03)
 
 
 def test_forward_backward_match_oracle():
