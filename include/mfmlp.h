@@ -9,7 +9,9 @@
  *
  * Batches are feature-major: an activation block is features x rows with row
  * = e * k + j for cell e and column j of a k-column multivector, element
- * (i, row) at V[i * ld + row].  BF16 data are passed as uint16_t (the upper
+ * (i, row) at V[i * ld + row].  The cell-blocked layout (where a call takes
+ * it) keeps each cell's features x k block contiguous: element (i, e k + j)
+ * at V[e * ld + i * k + j], ld the block stride (>= features * k).  BF16 data are passed as uint16_t (the upper
  * half of an IEEE single, round to nearest even).  Every call is
  * stream-ordered on `stream` (hipStream_t, NULL = default), allocates nothing
  * and returns MF_OK or a negative mf_status (message in mf_last_error()).
@@ -35,12 +37,16 @@ extern "C" {
  * A, B 16-byte aligned.  kchunk > 0 splits K into ceil(K / kchunk) ranges run
  * by separate workgroups (use with atomic != 0, no bias or ReLU, on a zeroed
  * out_f32); kchunk <= 0 takes K whole.  bias (FP32, M), mask (BF16, ldmask),
- * out_f32 and out_bf16 may be NULL (at least one output).  Errors:
- * MF_ERR_ARG, MF_ERR_HIP. */
+ * out_f32 and out_bf16 may be NULL (at least one output).  kb > 0 (a
+ * multiple of 8 dividing N): B (tb = 0) and the outputs are in the
+ * cell-blocked layout with blocks of kb columns, ldb, ld_f32, ld_bf16 being
+ * the block strides (>= K kb, M kb, M kb); no mask then.  Workgroups take the
+ * output tiles M-tile first, so the tiles sharing a slice of B run together.
+ * Errors: MF_ERR_ARG, MF_ERR_HIP. */
 int mf_mlp_gemm(int M, int N, int K, int ta, int tb, const uint16_t* A, int64_t lda,
                 const uint16_t* B, int64_t ldb, int kchunk, const float* bias, int relu,
                 const uint16_t* mask, int64_t ldmask, float* out_f32, int64_t ld_f32, int atomic,
-                uint16_t* out_bf16, int64_t ld_bf16, void* stream);
+                uint16_t* out_bf16, int64_t ld_bf16, int kb, void* stream);
 
 /* Network input of every (cell, column): u_i = R[node_i][j], times sqrt(w_i)
  * (the square root of node i's partition-of-unity weight) when pou_sqrt != 0
@@ -54,10 +60,12 @@ int mf_mlp_gemm(int M, int N, int K, int ta, int tb, const uint16_t* A, int64_t 
  * (ldr, lde >= k); X0t and Tt are Fp x (ncells k) with leading dimension
  * ldx >= ncells k; rho has ncells k entries, or is NULL: then rho = 1 (no
  * normalisation, one pass over R; for a linear cell map, where the scale
- * cancels).  Fp >= F, multiple of 8.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+ * cancels).  Fp >= F, multiple of 8.  blocked != 0: X0t and Tt in the
+ * cell-blocked layout, ldx the block stride (>= Fp k).  Errors: MF_ERR_ARG,
+ * MF_ERR_HIP. */
 int mf_cell_gather(mf_operator* op, int k, const double* R, int64_t ldr, const double* E,
                    int64_t lde, int Fp, uint16_t* X0t, float* Tt, int64_t ldx, float* rho,
-                   int pou_sqrt, const double* dscale, void* stream);
+                   int pou_sqrt, const double* dscale, int blocked, void* stream);
 
 /* Z := Z0 + sum_e Q_e^T W_e (rho * Yt): the partition-of-unity assembly of
  * the network outputs Yt (FP32, first F rows used, ldy >= ncells k) scaled
@@ -67,11 +75,12 @@ int mf_cell_gather(mf_operator* op, int k, const double* R, int64_t ldr, const d
  * when dscale != NULL, on top of Z0 = R / diag row-wise (the Jacobi term)
  * when diag != NULL, else Z0 = 0.  Taken node by node (each Z element summed
  * by one thread over the node's cells in a fixed order, no atomics), so the
- * result is bitwise reproducible.  Z (ndofs x k, ldz >= k) is overwritten;
- * it must not be R.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+ * result is bitwise reproducible.  blocked != 0: Yt in the cell-blocked
+ * layout, ldy the block stride (>= np^3 k).  Z (ndofs x k, ldz >= k) is
+ * overwritten; it must not be R.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
 int mf_cell_scatter(mf_operator* op, int k, const float* Yt, int64_t ldy, const float* rho,
                     const double* diag, const double* R, int64_t ldr, double* Z, int64_t ldz,
-                    int pou_sqrt, const double* dscale, void* stream);
+                    int pou_sqrt, const double* dscale, int blocked, void* stream);
 
 /* Eigenvalue floor of the symmetric skip block S of the cell network, the
  * step that makes the deployed linear preconditioner

@@ -18,20 +18,30 @@ extern "C" {
 int mf_mlp_gemm(int M, int N, int K, int ta, int tb, const uint16_t* A, int64_t lda,
                 const uint16_t* B, int64_t ldb, int kchunk, const float* bias, int relu,
                 const uint16_t* mask, int64_t ldmask, float* out_f32, int64_t ld_f32, int atomic,
-                uint16_t* out_bf16, int64_t ld_bf16, void* stream) {
+                uint16_t* out_bf16, int64_t ld_bf16, int kb, void* stream) {
   if (!A || !B) return fail(MF_ERR_ARG, "A and B must be non-NULL");
   if (!out_f32 && !out_bf16) return fail(MF_ERR_ARG, "no output");
   if (M < 1 || N < 1 || K < 1 || M % 8 || N % 8 || K % 8)
     return fail(MF_ERR_ARG, "M, N, K must be positive multiples of 8");
   if (lda % 8 || ldb % 8 || !aligned16(A) || !aligned16(B))
     return fail(MF_ERR_ARG, "lda, ldb must be multiples of 8 and A, B 16-byte aligned");
-  if (lda < (ta ? M : K) || ldb < (tb ? K : N)) return fail(MF_ERR_ARG, "leading dimension too small");
-  if ((out_f32 && ld_f32 < N) || (out_bf16 && ld_bf16 < N) || (mask && ldmask < N))
-    return fail(MF_ERR_ARG, "output leading dimension < N");
+  if (kb < 0 || kb % 8) return fail(MF_ERR_ARG, "kb must be 0 or a positive multiple of 8");
+  if (kb > 0) {  // cell-blocked B and outputs: N in blocks of kb, block strides ldb, ld_f32, ld_bf16
+    if (tb || mask) return fail(MF_ERR_ARG, "the blocked layout takes neither tb nor a mask");
+    if (N % kb) return fail(MF_ERR_ARG, "N must be a multiple of kb");
+    if (lda < (ta ? M : K) || ldb < (int64_t)K * kb || (out_f32 && ld_f32 < (int64_t)M * kb) ||
+        (out_bf16 && ld_bf16 < (int64_t)M * kb))
+      return fail(MF_ERR_ARG, "block stride below (rows of the block) x kb");
+  } else {
+    if (lda < (ta ? M : K) || ldb < (tb ? K : N))
+      return fail(MF_ERR_ARG, "leading dimension too small");
+    if ((out_f32 && ld_f32 < N) || (out_bf16 && ld_bf16 < N) || (mask && ldmask < N))
+      return fail(MF_ERR_ARG, "output leading dimension < N");
+  }
   if (atomic && !out_f32) return fail(MF_ERR_ARG, "atomic needs out_f32");
   if (kchunk > 0 && (bias || relu || mask || out_bf16 || !atomic))
     return fail(MF_ERR_ARG, "a split K range needs atomic FP32 output without epilogue ops");
-  GemmEpi ep{bias, relu, mask, ldmask, out_f32, ld_f32, atomic, out_bf16, ld_bf16};
+  GemmEpi ep{bias, relu, mask, ldmask, out_f32, ld_f32, atomic, out_bf16, ld_bf16, kb};
   hipError_t err = launch_gemm_bf16(M, N, K, ta != 0, tb != 0, A, lda, B, ldb, kchunk, ep,
                                     static_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "MLP GEMM launch");
@@ -40,7 +50,7 @@ int mf_mlp_gemm(int M, int N, int K, int ta, int tb, const uint16_t* A, int64_t 
 
 int mf_cell_gather(mf_operator* handle, int k, const double* R, int64_t ldr, const double* E,
                    int64_t lde, int Fp, uint16_t* X0t, float* Tt, int64_t ldx, float* rho,
-                   int pou_sqrt, const double* dscale, void* stream) {
+                   int pou_sqrt, const double* dscale, int blocked, void* stream) {
   if (!handle || !R || !X0t) return fail(MF_ERR_ARG, "operator, R, X0t non-NULL");
   Operator* op = reinterpret_cast<Operator*>(handle);
   if (op->refined) return fail(MF_ERR_UNSUPPORTED, "cell gather/scatter are built for uniform box meshes");
@@ -48,26 +58,29 @@ int mf_cell_gather(mf_operator* handle, int k, const double* R, int64_t ldr, con
   if (k < 1 || ldr < k || (E && lde < k)) return fail(MF_ERR_ARG, "need k >= 1, ld >= k");
   if (E && !Tt) return fail(MF_ERR_ARG, "E needs Tt");
   if (Fp < F || Fp % 8) return fail(MF_ERR_ARG, "Fp must be >= np^3 and a multiple of 8");
-  if (ldx < op->ncells * k) return fail(MF_ERR_ARG, "ldx < ncells * k");
+  if (!blocked && ldx < op->ncells * k) return fail(MF_ERR_ARG, "ldx < ncells * k");
+  if (blocked && ldx < (int64_t)Fp * k) return fail(MF_ERR_ARG, "blocked: ldx < Fp * k");
   if (op->ncells * k >= ((int64_t)1 << 31)) return fail(MF_ERR_UNSUPPORTED, "batch too large");
   hipError_t err = launch_cell_gather(*op, k, R, ldr, E, lde, Fp, X0t, Tt, ldx, rho, pou_sqrt,
-                                      dscale, static_cast<hipStream_t>(stream));
+                                      dscale, blocked, static_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "cell gather launch");
   return MF_OK;
 }
 
 int mf_cell_scatter(mf_operator* handle, int k, const float* Yt, int64_t ldy, const float* rho,
                     const double* diag, const double* R, int64_t ldr, double* Z, int64_t ldz,
-                    int pou_sqrt, const double* dscale, void* stream) {
+                    int pou_sqrt, const double* dscale, int blocked, void* stream) {
   if (!handle || !Yt || !Z) return fail(MF_ERR_ARG, "operator, Yt, Z non-NULL");
   Operator* op = reinterpret_cast<Operator*>(handle);
   if (op->refined) return fail(MF_ERR_UNSUPPORTED, "cell gather/scatter are built for uniform box meshes");
   if (k < 1 || ldz < k) return fail(MF_ERR_ARG, "need k >= 1, ldz >= k");
-  if (ldy < op->ncells * k) return fail(MF_ERR_ARG, "ldy < ncells * k");
+  const int F = op->np * op->np * op->np;
+  if (!blocked && ldy < op->ncells * k) return fail(MF_ERR_ARG, "ldy < ncells * k");
+  if (blocked && ldy < (int64_t)F * k) return fail(MF_ERR_ARG, "blocked: ldy < np^3 * k");
   if (diag && (!R || ldr < k)) return fail(MF_ERR_ARG, "diag needs R with ldr >= k");
   if (R && R == Z) return fail(MF_ERR_ARG, "Z must not be R");
   hipError_t err = launch_cell_scatter(*op, k, Yt, ldy, rho, diag, R, ldr, Z, ldz, pou_sqrt,
-                                       dscale, static_cast<hipStream_t>(stream));
+                                       dscale, blocked, static_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "cell scatter launch");
   return MF_OK;
 }

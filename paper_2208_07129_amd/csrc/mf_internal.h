@@ -297,6 +297,7 @@ struct GemmEpi {  // epilogue of the BF16 matrix-core GEMM (see mfmlp.h)
   int atomic;
   uint16_t* out_bf16;
   int64_t ld_bf16;
+  int kb;  // > 0: B and the outputs in the cell-blocked layout of block width kb
 };
 hipError_t launch_gemm_bf16(int M, int N, int K, bool ta, bool tb, const uint16_t* A, int64_t lda,
                             const uint16_t* B, int64_t ldb, int kchunk, const GemmEpi& ep,
@@ -304,11 +305,11 @@ hipError_t launch_gemm_bf16(int M, int N, int K, bool ta, bool tb, const uint16_
 hipError_t launch_cell_gather(const Operator& op, int k, const double* R, int64_t ldr,
                               const double* E, int64_t lde, int Fp, uint16_t* X0t, float* Tt,
                               int64_t ldx, float* rho, int pou_sqrt, const double* dsc,
-                              hipStream_t s);
+                              int blocked, hipStream_t s);
 hipError_t launch_cell_scatter(const Operator& op, int k, const float* Yt, int64_t ldy,
                                const float* rho, const double* diag, const double* R, int64_t ldr,
                                double* Z, int64_t ldz, int pou_sqrt, const double* dsc,
-                               hipStream_t s);
+                               int blocked, hipStream_t s);
 hipError_t launch_symmetrize(int n, float* S, int64_t ld, uint16_t* Sbf, hipStream_t s);
 hipError_t launch_mse_grad(int F, int Fp, int64_t nrows, const float* Yt, const float* Tt,
                            int64_t ld, const float* roww, float scale, uint16_t* dYt, double* loss,

@@ -4,7 +4,10 @@
 // Batch layout is feature-major: an activation block is [features][rows],
 // row = e * k + j for cell e and column j, so a layer is C = W^T X with the
 // long batch dimension as the GEMM's N and the weights as the row-major A
-// operand.  The GEMM runs on the gfx950 matrix cores
+// operand.  The cell-blocked variant stores each cell's features x columns
+// block contiguously (element (i, e k + j) at e * ld + i * k + j): the cell
+// gather and the node assembly then stream whole cells instead of 256-byte
+// pieces a batch row apart.  The GEMM runs on the gfx950 matrix cores
 // (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation): one 64 x 64
 // output tile per 256-thread workgroup, 2 x 2 waves of 32 x 32, K staged
 // through LDS in steps of 32 with k contiguous per lane, so every fragment is
@@ -13,6 +16,7 @@
 // backward pass and the BF16 conversion; weight gradients split the batch
 // dimension across workgroups and add FP32 partial tiles atomically.
 #include <cmath>
+#include <type_traits>
 
 #include "mf_internal.h"
 #include "sf_common.h"
@@ -36,14 +40,17 @@ constexpr int kTile = 64, kKStep = 32, kPad = 40;  // LDS rows of 80 bytes
 // C (M x N) = op(A) (M x K) * op(B) (K x N).  A: row-major M x K (lda), or,
 // with TA, stored K x M.  B: row-major K x N (ldb), or, with TB, stored N x K.
 // M, N, K multiples of 8 (8-element, 16-byte staging chunks).  blockIdx.z
-// takes the K range [z kchunk, (z+1) kchunk).
+// takes the K range [z kchunk, (z+1) kchunk).  blockIdx.x enumerates the
+// output tiles with the M tile fastest: the few workgroups that share an N
+// slice of B (the long batch operand) run together and read it from HBM once.
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256)
 gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A, int64_t lda,
                  const uint16_t* __restrict__ B, int64_t ldb, int kchunk, GemmEpi ep) {
   __shared__ __attribute__((aligned(16))) uint16_t As[kTile][kPad];  // [m][k]
   __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile][kPad];  // [n][k]
-  const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
+  const int mtiles = (M + kTile - 1) / kTile;
+  const int m0 = (int)(blockIdx.x % mtiles) * kTile, n0 = (int)(blockIdx.x / mtiles) * kTile;
   const int kb = blockIdx.z * kchunk;
   const int ke = min(K, kb + kchunk);
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -71,7 +78,7 @@ gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A, int64_t ld
 #pragma unroll
       for (int i = 0; i < 8; ++i) As[m + i][kk] = e[i];
     }
-    if constexpr (TB) {
+    if constexpr (TB) {  // (not in the blocked layout)
       const int n = t >> 2, kk = (t & 3) * 8;
       uint4 v = zero;
       if (n0 + n < N && k0 + kk < ke)
@@ -80,8 +87,12 @@ gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A, int64_t ld
     } else {
       const int kk = t >> 3, n = (t & 7) * 8;
       uint4 v = zero;
-      if (k0 + kk < ke && n0 + n < N)
-        v = *reinterpret_cast<const uint4*>(B + (int64_t)(k0 + kk) * ldb + n0 + n);
+      if (k0 + kk < ke && n0 + n < N) {
+        const int nn = n0 + n;  // 8 columns inside one block (kb multiple of 8)
+        const int64_t off = ep.kb > 0 ? (int64_t)(nn / ep.kb) * ldb + (int64_t)(k0 + kk) * ep.kb + nn % ep.kb
+                                      : (int64_t)(k0 + kk) * ldb + nn;
+        v = *reinterpret_cast<const uint4*>(B + off);
+      }
       const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
 #pragma unroll
       for (int i = 0; i < 8; ++i) Bs[n + i][kk] = e[i];
@@ -115,12 +126,16 @@ gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A, int64_t ld
         if (ep.bias) v += ep.bias[m];
         if (ep.relu) v = v > 0.f ? v : 0.f;
         if (ep.mask && !(bf16_to_f32(ep.mask[(int64_t)m * ep.ldmask + n]) > 0.f)) v = 0.f;
+        const int64_t nb = ep.kb > 0 ? (int64_t)(n / ep.kb) : 0, nr = ep.kb > 0 ? n % ep.kb : n;
         if (ep.out_f32) {
-          float* o = ep.out_f32 + (int64_t)m * ep.ld_f32 + n;
+          float* o = ep.out_f32 + (ep.kb > 0 ? nb * ep.ld_f32 + (int64_t)m * ep.kb + nr
+                                             : (int64_t)m * ep.ld_f32 + n);
           if (ep.atomic) unsafeAtomicAdd(o, v);
           else *o = v;
         }
-        if (ep.out_bf16) ep.out_bf16[(int64_t)m * ep.ld_bf16 + n] = f32_to_bf16(v);
+        if (ep.out_bf16)
+          ep.out_bf16[ep.kb > 0 ? nb * ep.ld_bf16 + (int64_t)m * ep.kb + nr
+                                : (int64_t)m * ep.ld_bf16 + n] = f32_to_bf16(v);
       }
 }
 
@@ -176,7 +191,7 @@ __global__ void __launch_bounds__(256)
 cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int64_t ldr,
                    const double* __restrict__ E, int64_t lde, int Fp, uint16_t* __restrict__ X0t,
                    float* __restrict__ Tt, int64_t ldx, float* __restrict__ rho, int pou_sqrt,
-                   const double* __restrict__ dsc) {
+                   const double* __restrict__ dsc, int blocked) {
   __shared__ double part[256];
   __shared__ int snode[kMaxCellNodes];
   __shared__ double sfin[kMaxCellNodes], sdh[kMaxCellNodes];
@@ -208,6 +223,8 @@ cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int6
   }
   const int64_t row = (int64_t)e * k + j;
   if (j >= k) return;
+  // element (i, row) at i * istep + base
+  const int64_t base = blocked ? (int64_t)e * ldx + j : row, istep = blocked ? k : ldx;
   for (int i = ph; i < Fp; i += 4) {
     double x = 0.0, y = 0.0;
     if (i < F) {
@@ -217,8 +234,8 @@ cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int6
         if (E) y = E[(int64_t)node * lde + j] * s * sdh[i];
       }
     }
-    X0t[(int64_t)i * ldx + row] = f32_to_bf16((float)x);
-    if (Tt) Tt[(int64_t)i * ldx + row] = (float)y;
+    X0t[i * istep + base] = f32_to_bf16((float)x);
+    if (Tt) Tt[i * istep + base] = (float)y;
   }
 }
 
@@ -250,51 +267,168 @@ __device__ inline int node_incidences(int g, int n, int N, int p, int* c, int* l
 }
 
 // Z[node][j] = (R[node][j] / diag[node] or 0) + sum over the node's
-// incidences (cell e, local node i) of w^[1/2] rho[e k + j] Yt[i][e k + j]
+// incidences (cell e, local node i) of w^[1/2] rho[e k + j] Yt(i, e k + j)
 // (divided by sqrt(dsc[node])): the partition-of-unity assembly taken node by
 // node, so every Z element is written once by one lane, with a fixed order of
-// its up to eight terms (no atomics; bitwise reproducible).  One wavefront per
-// (node, 64 columns): lanes over the columns, so the loads of Yt, rho, R and
-// the store of Z are contiguous runs.  Constrained nodes get only the Jacobi
-// term, as the scattered form never adds to them.
-constexpr int kAsmNodes = 4;  // nodes (wavefronts) per workgroup
-__global__ void __launch_bounds__(64 * kAsmNodes)
-node_assemble_kernel(GridDesc g, int np, int k, int64_t nnodes, const float* __restrict__ Yt,
-                     int64_t ldy, const float* __restrict__ rho, const double* __restrict__ diag,
-                     const double* __restrict__ R, int64_t ldr, double* __restrict__ Z,
-                     int64_t ldz, int pou_sqrt, const double* __restrict__ dsc) {
-  const int lane = threadIdx.x & 63;
-  const int64_t node = (int64_t)blockIdx.x * kAsmNodes + (threadIdx.x >> 6);
-  const int j = blockIdx.y * 64 + lane;
-  if (node >= nnodes || j >= k) return;
-  const int gx = (int)(node % g.N[0]), gy = (int)((node / g.N[0]) % g.N[1]);
-  const int gz = (int)(node / ((int64_t)g.N[0] * g.N[1]));
-  double z = diag ? R[node * ldr + j] / diag[node] : 0.0;
-  const bool constrained =
-      g.dirichlet && (gx == 0 || gx == g.N[0] - 1 || gy == 0 || gy == g.N[1] - 1 || gz == 0 ||
-                      gz == g.N[2] - 1);
-  if (!constrained) {
-    int cx[2], cy[2], cz[2], lx[2], ly[2], lz[2];
-    double wx, wy, wz;
-    const int nx = node_incidences(gx, g.n[0], g.N[0], g.p, cx, lx, &wx);
-    const int ny = node_incidences(gy, g.n[1], g.N[1], g.p, cy, ly, &wy);
-    const int nz = node_incidences(gz, g.n[2], g.N[2], g.p, cz, lz, &wz);
-    const double pw = wx * wy * wz;
-    double f = pou_sqrt ? sqrt(pw) : pw;
-    if (dsc) f /= sqrt(dsc[node]);
-    double acc = 0.0;
-    for (int c = 0; c < nz; ++c)
-      for (int b = 0; b < ny; ++b)
-        for (int a = 0; a < nx; ++a) {
-          const int64_t e = cx[a] + (int64_t)g.n[0] * (cy[b] + (int64_t)g.n[1] * cz[c]);
-          const int i = lx[a] + np * (ly[b] + np * lz[c]);
-          const int64_t row = e * k + j;
-          const double y = (double)Yt[(int64_t)i * ldy + row];
-          acc = fma(rho ? (double)rho[row] : 1.0, y, acc);
-        }
-    z = fma(f, acc, z);
+// its up to eight terms (no atomics; bitwise reproducible).  Constrained nodes
+// get only the Jacobi term, as the scattered form never adds to them.
+//
+// One wavefront per (x-line of a cell, 64 columns): the nodes gx = cx p + l,
+// l = 0 .. p - 1 (and l = p in the last cell of a non-periodic direction), at
+// fixed (gy, gz), lanes over the columns.  Along the line only l = 0 can have
+// a second x-incidence, and the y, z incidences are the same for every node,
+// so with p and their counts as template parameters all the line's loads are
+// independent and in flight together (one node per wavefront left the kernel
+// bound by memory latency).
+constexpr int kAsmLines = 4;  // lines (wavefronts) per workgroup
+
+struct AsmArgs {
+  GridDesc g;
+  int k;
+  const float* Yt;
+  int64_t ldy;
+  const float* rho;
+  const double* diag;
+  const double* R;
+  int64_t ldr;
+  double* Z;
+  int64_t ldz;
+  int pou_sqrt;
+  const double* dsc;
+  int blocked;
+};
+
+// lane l's value of v, as a wave-uniform value
+__device__ __forceinline__ double wave_bcast(double v, int l) {
+  const int2 h = __builtin_bit_cast(int2, v);
+  const int2 r{__builtin_amdgcn_readlane(h.x, l), __builtin_amdgcn_readlane(h.y, l)};
+  return __builtin_bit_cast(double, r);
+}
+
+template <int P, int NY, int NZ, bool BLK, bool RHO, bool DIAG>
+__device__ __forceinline__ void assemble_line(const AsmArgs& a, int cx, int gy, int gz,
+                                              const int* cy, const int* ly, double wy,
+                                              const int* cz, const int* lz, double wz, int j,
+                                              bool jok) {
+  constexpr int NP = P + 1;
+  const GridDesc& g = a.g;
+  const int n0 = g.n[0], N0 = g.N[0];
+  const bool periodic_x = N0 == n0 * P;
+  const bool has_left = periodic_x || cx > 0;   // a cell ends at gx = cx p
+  const bool extra = !periodic_x && cx == n0 - 1;  // node l = p is this line's too
+  const int cxl = cx > 0 ? cx - 1 : n0 - 1;
+  const bool line_constrained =
+      g.dirichlet && (gy == 0 || gy == g.N[1] - 1 || gz == 0 || gz == g.N[2] - 1);
+  int64_t eyz[NY * NZ];
+  int iyz[NY * NZ];
+#pragma unroll
+  for (int c = 0; c < NZ; ++c)
+#pragma unroll
+    for (int b = 0; b < NY; ++b) {
+      eyz[c * NY + b] = (int64_t)n0 * (cy[b] + (int64_t)g.n[1] * cz[c]);
+      iyz[c * NY + b] = NP * (ly[b] + NP * lz[c]);
+    }
+  auto yload = [&](int64_t e, int i) -> float {
+    return BLK ? a.Yt[e * a.ldy + (int64_t)i * a.k + j] : a.Yt[(int64_t)i * a.ldy + e * a.k + j];
+  };
+  auto rload = [&](int64_t e) -> float {
+    if constexpr (RHO) return a.rho[e * a.k + j];
+    return 1.0f;
+  };
+  // all the line's loads first (independent, in flight together), then the sums
+  constexpr int Q = NY * NZ;
+  float yv[P + 2][Q], rv[3][Q];  // rows: l = 0 .. p - 1, the left cell's p, this cell's p
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+#pragma unroll
+    for (int l = 0; l < P; ++l) yv[l][q] = yload(cx + eyz[q], l + iyz[q]);
+    yv[P][q] = yload(cxl + eyz[q], P + iyz[q]);
+    yv[P + 1][q] = yload(cx + eyz[q], P + iyz[q]);
+    rv[0][q] = rload(cx + eyz[q]);
+    rv[1][q] = rload(cxl + eyz[q]);
   }
-  Z[node * ldz + j] = z;
+  double acc[P + 1];
+#pragma unroll
+  for (int l = 0; l < P; ++l) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s += (double)rv[0][q] * (double)yv[l][q];
+    if (l == 0) {  // the cell to the left, local node p (added if it exists)
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) t += (double)rv[1][q] * (double)yv[P][q];
+      s += has_left ? t : 0.0;
+    }
+    acc[l] = s;
+  }
+  acc[P] = 0.0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) acc[P] += (double)rv[0][q] * (double)yv[P + 1][q];
+  if (!extra) acc[P] = 0.0;
+  // per-node factors of the line, one node per lane (lanes 0 .. p), then read
+  // back as wave-uniform values: 1 / diag and w^[1/2] / sqrt(dsc)
+  const double wyz = wy * wz;
+  const int64_t row0 = (int64_t)N0 * (gy + (int64_t)g.N[1] * gz);
+  const int lane = threadIdx.x & 63;
+  double invd = 0.0, fac = 0.0;
+  if (lane <= P) {
+    const int gx = cx * P + (lane < P || extra ? lane : 0);
+    const int64_t node = row0 + gx;
+    if constexpr (DIAG) invd = 1.0 / a.diag[node];
+    const double pw = ((lane == 0 && has_left) ? 0.5 : 1.0) * wyz;
+    fac = a.pou_sqrt ? sqrt(pw) : pw;
+    if (a.dsc) fac /= sqrt(a.dsc[node]);
+  }
+  double rj[P + 1];  // the Jacobi term's R values (l = p: a valid node when not this line's)
+  if constexpr (DIAG) {
+#pragma unroll
+    for (int l = 0; l <= P; ++l) {
+      const int gx = cx * P + (l < P || extra ? l : 0);
+      rj[l] = a.R[(row0 + gx) * a.ldr + j];
+    }
+  }
+#pragma unroll
+  for (int l = 0; l <= P; ++l) {
+    if (l == P && !extra) break;
+    const int gx = cx * P + l;
+    const int64_t node = row0 + gx;
+    const double il = wave_bcast(invd, l), fl = wave_bcast(fac, l);
+    double z = 0.0;
+    if constexpr (DIAG) z = rj[l] * il;
+    const bool constrained = line_constrained || (g.dirichlet && (gx == 0 || gx == N0 - 1));
+    if (!constrained) z = fma(fl, acc[l], z);
+    if (jok) a.Z[node * a.ldz + j] = z;
+  }
+}
+
+// BLK: cell-blocked Yt; RHO: rho given; DIAG: the Jacobi term (compile-time,
+// so that no load sits behind a branch and the line's loads issue together)
+template <int P, bool BLK, bool RHO, bool DIAG>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, 64 * kAsmLines),
+                               amdgpu_waves_per_eu(1, 4)))
+node_assemble_kernel(AsmArgs a, int nlines, int nchunks) {
+  // the column chunk varies fastest, so the halves of a Z row (and of an R
+  // row) are written and read together
+  const int chunk = (int)(blockIdx.x % nchunks);
+  const int line = (int)(blockIdx.x / nchunks) * kAsmLines + (int)(threadIdx.x >> 6);  // < 2^31
+  // every lane stays (lanes 0 .. p form the line's node factors); lanes past
+  // the last column read column k - 1 and store nothing
+  const int jl = chunk * 64 + (threadIdx.x & 63);
+  const bool jok = jl < a.k;
+  const int j = jok ? jl : a.k - 1;
+  if (line >= nlines) return;
+  const GridDesc& g = a.g;
+  const int cx = line % g.n[0];
+  const int rest = line / g.n[0];
+  const int gy = rest % g.N[1], gz = rest / g.N[1];
+  int cy[2], cz[2], ly[2], lz[2];
+  double wy, wz;
+  const int ny = node_incidences(gy, g.n[1], g.N[1], P, cy, ly, &wy);
+  const int nz = node_incidences(gz, g.n[2], g.N[2], P, cz, lz, &wz);
+  if (ny == 1 && nz == 1) assemble_line<P, 1, 1, BLK, RHO, DIAG>(a, cx, gy, gz, cy, ly, wy, cz, lz, wz, j, jok);
+  else if (ny == 2 && nz == 1) assemble_line<P, 2, 1, BLK, RHO, DIAG>(a, cx, gy, gz, cy, ly, wy, cz, lz, wz, j, jok);
+  else if (ny == 1) assemble_line<P, 1, 2, BLK, RHO, DIAG>(a, cx, gy, gz, cy, ly, wy, cz, lz, wz, j, jok);
+  else assemble_line<P, 2, 2, BLK, RHO, DIAG>(a, cx, gy, gz, cy, ly, wy, cz, lz, wz, j, jok);
 }
 
 // dYt = 2 scale w[n] (Yt - Tt) for features < F (0 for the padding), as
@@ -444,7 +578,7 @@ hipError_t launch_gemm_bf16(int M, int N, int K, bool ta, bool tb, const uint16_
   if (kchunk <= 0 || kchunk > K) kchunk = K;
   kchunk = (kchunk + kKStep - 1) / kKStep * kKStep;
   const int kz = (K + kchunk - 1) / kchunk;
-  dim3 grid((N + kTile - 1) / kTile, (M + kTile - 1) / kTile, kz);
+  dim3 grid((unsigned)(((int64_t)N + kTile - 1) / kTile * ((M + kTile - 1) / kTile)), 1, kz);
   if (!ta && !tb)
     hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, kchunk, ep);
   else if (ta && !tb)
@@ -459,10 +593,10 @@ hipError_t launch_gemm_bf16(int M, int N, int K, bool ta, bool tb, const uint16_
 hipError_t launch_cell_gather(const Operator& op, int k, const double* R, int64_t ldr,
                               const double* E, int64_t lde, int Fp, uint16_t* X0t, float* Tt,
                               int64_t ldx, float* rho, int pou_sqrt, const double* dsc,
-                              hipStream_t s) {
+                              int blocked, hipStream_t s) {
   dim3 grid((unsigned)op.ncells, (k + kCols - 1) / kCols);
   hipLaunchKernelGGL(cell_gather_kernel, grid, dim3(256), 0, s, op.grid, op.np, k, R, ldr, E, lde,
-                     Fp, X0t, Tt, ldx, rho, pou_sqrt, dsc);
+                     Fp, X0t, Tt, ldx, rho, pou_sqrt, dsc, blocked);
   return hipGetLastError();
 }
 
@@ -482,10 +616,42 @@ hipError_t launch_skip_rebuild(int F, const double* V, const double* w, double m
 hipError_t launch_cell_scatter(const Operator& op, int k, const float* Yt, int64_t ldy,
                                const float* rho, const double* diag, const double* R, int64_t ldr,
                                double* Z, int64_t ldz, int pou_sqrt, const double* dsc,
-                               hipStream_t s) {
-  dim3 grid((unsigned)((op.ndofs + kAsmNodes - 1) / kAsmNodes), (unsigned)((k + 63) / 64));
-  hipLaunchKernelGGL(node_assemble_kernel, grid, dim3(64 * kAsmNodes), 0, s, op.grid, op.np, k,
-                     (int64_t)op.ndofs, Yt, ldy, rho, diag, R, ldr, Z, ldz, pou_sqrt, dsc);
+                               int blocked, hipStream_t s) {
+  const AsmArgs a{op.grid, k, Yt, ldy, rho, diag, R, ldr, Z, ldz, pou_sqrt, dsc, blocked};
+  const int nlines = (int)((int64_t)op.grid.n[0] * op.grid.N[1] * op.grid.N[2]);  // <= ndofs
+  const int nch = (k + 63) / 64;
+  dim3 grid((unsigned)(((int64_t)nlines + kAsmLines - 1) / kAsmLines * nch));
+  dim3 block(64 * kAsmLines);
+  auto go = [&](auto pc) {
+    constexpr int P = decltype(pc)::value;
+    const int v = (blocked ? 4 : 0) + (rho ? 2 : 0) + (diag ? 1 : 0);
+#define MF_ASM(B, Rh, D) \
+  hipLaunchKernelGGL((node_assemble_kernel<P, B, Rh, D>), grid, block, 0, s, a, nlines, nch)
+    switch (v) {
+      case 0: MF_ASM(false, false, false); break;
+      case 1: MF_ASM(false, false, true); break;
+      case 2: MF_ASM(false, true, false); break;
+      case 3: MF_ASM(false, true, true); break;
+      case 4: MF_ASM(true, false, false); break;
+      case 5: MF_ASM(true, false, true); break;
+      case 6: MF_ASM(true, true, false); break;
+      default: MF_ASM(true, true, true); break;
+    }
+#undef MF_ASM
+  };
+  switch (op.p) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 3: go(std::integral_constant<int, 3>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    case 5: go(std::integral_constant<int, 5>{}); break;
+    case 6: go(std::integral_constant<int, 6>{}); break;
+    case 7: go(std::integral_constant<int, 7>{}); break;
+    case 8: go(std::integral_constant<int, 8>{}); break;
+    case 9: go(std::integral_constant<int, 9>{}); break;
+    case 10: go(std::integral_constant<int, 10>{}); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

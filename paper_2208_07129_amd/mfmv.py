@@ -119,9 +119,9 @@ def lib() -> ctypes.CDLL:
             "mf_jacobi": (I, [I64, I, P, P, I64, P, I64, P]),
             "mf_spd_solve": (I, [I, I, P, P, P, P, P]),
             "mf_mlp_gemm": (I, [I, I, I, I, I, P, I64, P, I64, I, P, I, P, I64, P, I64, I, P, I64,
-                                P]),
-            "mf_cell_gather": (I, [P, I, P, I64, P, I64, I, P, P, I64, P, I, P, P]),
-            "mf_cell_scatter": (I, [P, I, P, I64, P, P, P, I64, P, I64, I, P, P]),
+                                I, P]),
+            "mf_cell_gather": (I, [P, I, P, I64, P, I64, I, P, P, I64, P, I, P, I, P]),
+            "mf_cell_scatter": (I, [P, I, P, I64, P, P, P, I64, P, I64, I, P, I, P]),
             "mf_symmetrize": (I, [I, P, I64, P, P]),
             "mf_skip_floor": (I, [I, P, I64, P, I64, D, P, I64, P, P]),
             "mf_skip_floor_work": (I64, [I]),

@@ -129,7 +129,7 @@ def test_cell_gather_and_scatter_match_oracle(bc):
                 mfmv._check(mfmv.lib().mf_cell_scatter(
                     op._h, k, b["Y"].data_ptr(), b["ld"], b["rho"].data_ptr(),
                     dd.data_ptr() if with_j else None, Rd.data_ptr() if with_j else None, k,
-                    Z.data_ptr(), k, sq, None if ds is None else ds.data_ptr(), None))
+                    Z.data_ptr(), k, sq, None if ds is None else ds.data_ptr(), 0, None))
                 ref = mo.cell_assemble(mesh, p, Y[:F, :rows].T.astype(np.float64),
                                        b["rho"].cpu().numpy()[:rows].astype(np.float64), k,
                                        R if with_j else None, diag if with_j else None,
@@ -140,7 +140,7 @@ def test_cell_gather_and_scatter_match_oracle(bc):
     Z2 = torch.empty_like(Z)
     mfmv._check(mfmv.lib().mf_cell_scatter(
         op._h, k, b["Y"].data_ptr(), b["ld"], b["rho"].data_ptr(), dd.data_ptr(), Rd.data_ptr(),
-        k, Z2.data_ptr(), k, 1, dd.data_ptr(), None))
+        k, Z2.data_ptr(), k, 1, dd.data_ptr(), 0, None))
     assert torch.equal(Z, Z2)
     # without rho: the gather does not normalise and the assembly takes rho = 1
     b1 = net.gather(Rt, pou_sqrt=True, normalise=False)
@@ -149,7 +149,7 @@ def test_cell_gather_and_scatter_match_oracle(bc):
     assert np.all(np.abs(x1.astype(np.float64)[:F, :rows].T - U) <= np.abs(U) * 2 ** -8 + 1e-30)
     mfmv._check(mfmv.lib().mf_cell_scatter(
         op._h, k, b["Y"].data_ptr(), b["ld"], None, dd.data_ptr(), Rd.data_ptr(), k,
-        Z.data_ptr(), k, 1, dd.data_ptr(), None))
+        Z.data_ptr(), k, 1, dd.data_ptr(), 0, None))
     ref = mo.cell_assemble(mesh, p, Y[:F, :rows].T.astype(np.float64), np.ones(rows), k, R, diag,
                            pou_sqrt=True, dscale=diag)
     np.testing.assert_allclose(Z.cpu().numpy(), ref, rtol=0, atol=1e-10 * np.abs(ref).max())
@@ -185,7 +185,7 @@ def test_node_assembly_with_one_cell_periodic_directions(n):
     for sq in (0, 1):
         mfmv._check(mfmv.lib().mf_cell_scatter(
             op._h, k, b["Y"].data_ptr(), b["ld"], b["rho"].data_ptr(), dd.data_ptr(),
-            Rd.data_ptr(), k, Z.data_ptr(), k, sq, dd.data_ptr(), None))
+            Rd.data_ptr(), k, Z.data_ptr(), k, sq, dd.data_ptr(), 0, None))
         ref = mo.cell_assemble(mesh, op.p, Y[:F, :rows].T.astype(np.float64),
                                rho[:rows].astype(np.float64), k, R, diag, pou_sqrt=bool(sq),
                                dscale=diag)
@@ -249,6 +249,50 @@ def test_floored_skip_gives_a_positive_definite_preconditioner():
     assert ev.min() > 0.0
     # BF16 rounding of the floored block (2^-9 of 0.88) and of the input
     np.testing.assert_allclose(ev, 1.0 + floor, rtol=0.03)
+
+
+@pytest.mark.parametrize("bc,k", [(W.BC_PERIODIC, 16), (W.BC_DIRICHLET0, 16), (W.BC_PERIODIC, 9)])
+def test_linear_preconditioner_matches_oracle(bc, k):
+    """The deployed linear map z = D^-1 r + sum_e Q_e^T W^1/2 D^-1/2 S D^-1/2 W^1/2 Q_e r
+    against the oracle's gather and assembly with the same BF16 rounding of the
+    input and of S (k = 16: cell-blocked activations; k = 9: feature-major).  The
+    blocked path equals the feature-major one bitwise."""
+    mesh, op = small_op(bc, p=3, n=(2, 3, 2))
+    diag = mfmv.diagonal(op)
+    net = mlp.CellMLP(op, hidden=16, seed=5, dscale=diag)
+    H, F = net.H, net.F
+    rng = np.random.default_rng(21)
+    Q, _ = np.linalg.qr(rng.standard_normal((F, F)))
+    S = ((Q * rng.uniform(-0.9, 2.0, F)) @ Q.T).astype(np.float32)
+    S = (S + S.T) / 2
+    with torch.no_grad():
+        net.params[4][:F, H:H + F] = torch.from_numpy(S).to(dev())
+        net.wbf[4].copy_(torch.from_numpy(mlp._host_bf16(net.params[4].cpu().numpy())))
+    cons = constrained_mask(mesh, op.p)
+    R = rng.uniform(-1, 1, (op.ndofs, k))
+    R[cons] = 0.0
+    Rt = torch.from_numpy(R).to(dev())
+    Z = torch.empty_like(Rt)
+    net.precondition(Rt, Z, diag, linear=True)
+    dg = diag.cpu().numpy()
+    X, _, rho = mo.cell_inputs(mesh, op.p, R, pou_sqrt=True, dscale=dg)
+    U = mo.bf16_round(X * rho[:, None])
+    Sb = mo.bf16_round(S)
+    ref = mo.cell_assemble(mesh, op.p, U @ Sb.T, np.ones(len(rho)), k, R, dg, pou_sqrt=True,
+                           dscale=dg)
+    bound = mo.cell_assemble(mesh, op.p, np.abs(X * rho[:, None]) @ np.abs(Sb).T,
+                             np.ones(len(rho)), k, pou_sqrt=True, dscale=dg)
+    assert np.all(np.abs(Z.cpu().numpy() - ref) <= 2 ** -8 * np.abs(bound) + 1e-12 * np.abs(ref).max())
+    if k % 8 == 0:  # the same map through the feature-major layout
+        b = net.gather(Rt, pou_sqrt=True, normalise=False, blocked=False)
+        Fp, n = net.Fp, b["ld"]
+        net._gemm(Fp, n, Fp, False, False, net.wbf[4][:, H:], H + Fp, b["X0"], n,
+                  out_f32=b["Y"], ld_f32=n)
+        Z2 = torch.empty_like(Rt)
+        mfmv._check(mfmv.lib().mf_cell_scatter(
+            op._h, k, b["Y"].data_ptr(), n, None, diag.data_ptr(), Rt.data_ptr(), k,
+            Z2.data_ptr(), k, 1, diag.data_ptr(), 0, None))
+        assert torch.equal(Z, Z2)
 
 
 def test_forward_backward_match_oracle():
