@@ -203,40 +203,68 @@ cell_gather_kernel(GridDesc g, int np, int k, const double* __restrict__ R, int6
   const int cx = e % g.n[0], cy = (e / g.n[0]) % g.n[1], cz = e / (g.n[0] * g.n[1]);
   cell_node_factors(g, np, cx, cy, cz, pou_sqrt, dsc, snode, sfin, sdh);
   __syncthreads();
+  // Loads never sit behind a branch: constrained nodes and the padding rows
+  // read a valid element (clamped index) whose value a select then drops, and
+  // lanes past the last column read column k - 1 and store nothing; batches
+  // of kGatherBatch rows are loaded before they are used.
+  const bool jok = j < k;
+  const int jc = jok ? j : k - 1;
+  constexpr int kGatherBatch = 8;
+  const int nrows = (Fp - ph + 3) / 4;  // rows i = ph, ph + 4, ... < Fp of this wavefront
+  auto node_of = [&](int i) { return snode[i < F ? i : F - 1]; };
   double s = 1.0;  // without rho: no normalisation
   if (rho) {
     double ss = 0.0;
-    if (j < k)
-      for (int i = ph; i < F; i += 4) {
-        const int node = snode[i];
-        if (node >= 0) {
-          const double x = R[(int64_t)node * ldr + j] * sfin[i];
-          ss = fma(x, x, ss);
-        }
+    for (int r0 = 0; r0 < nrows; r0 += kGatherBatch) {
+      double xv[kGatherBatch];
+#pragma unroll
+      for (int u = 0; u < kGatherBatch; ++u) {
+        const int node = node_of(ph + 4 * (r0 + u));
+        xv[u] = R[(int64_t)(node >= 0 ? node : 0) * ldr + jc];
       }
+#pragma unroll
+      for (int u = 0; u < kGatherBatch; ++u) {
+        const int i = ph + 4 * (r0 + u);
+        const double f = i < F ? sfin[i] : 0.0;  // 0 for constrained nodes and padding
+        const double x = f != 0.0 ? xv[u] * f : 0.0;
+        ss = fma(x, x, ss);
+      }
+    }
     part[t] = ss;
     __syncthreads();
     double tot = part[jj] + part[jj + 64] + part[jj + 128] + part[jj + 192];
     const double r = sqrt(tot / F);
     s = r > 0.0 ? 1.0 / r : 0.0;
-    if (j < k && ph == 0) rho[(int64_t)e * k + j] = (float)r;
+    if (jok && ph == 0) rho[(int64_t)e * k + j] = (float)r;
   }
+  if (!jok) return;
   const int64_t row = (int64_t)e * k + j;
-  if (j >= k) return;
   // element (i, row) at i * istep + base
   const int64_t base = blocked ? (int64_t)e * ldx + j : row, istep = blocked ? k : ldx;
-  for (int i = ph; i < Fp; i += 4) {
-    double x = 0.0, y = 0.0;
-    if (i < F) {
-      const int node = snode[i];
-      if (node >= 0) {
-        x = R[(int64_t)node * ldr + j] * s * sfin[i];
-        if (E) y = E[(int64_t)node * lde + j] * s * sdh[i];
+  auto rows = [&](auto with_e) {
+    constexpr bool WE = decltype(with_e)::value;
+    for (int r0 = 0; r0 < nrows; r0 += kGatherBatch) {
+      double xv[kGatherBatch], yv[kGatherBatch];
+#pragma unroll
+      for (int u = 0; u < kGatherBatch; ++u) {
+        const int node = node_of(ph + 4 * (r0 + u));
+        const int64_t nc = node >= 0 ? node : 0;
+        xv[u] = R[nc * ldr + j];
+        if constexpr (WE) yv[u] = E[nc * lde + j];
+      }
+#pragma unroll
+      for (int u = 0; u < kGatherBatch; ++u) {
+        if (r0 + u >= nrows) break;  // uniform across the wavefront
+        const int i = ph + 4 * (r0 + u);
+        const double f = i < F ? sfin[i] : 0.0;
+        const double x = f != 0.0 ? xv[u] * s * f : 0.0;
+        X0t[i * istep + base] = f32_to_bf16((float)x);
+        if constexpr (WE) Tt[i * istep + base] = f != 0.0 ? (float)(yv[u] * s * sdh[i]) : 0.0f;
       }
     }
-    X0t[i * istep + base] = f32_to_bf16((float)x);
-    if (Tt) Tt[i * istep + base] = (float)y;
-  }
+  };
+  if (E) rows(std::true_type{});
+  else rows(std::false_type{});
 }
 
 // The incidences of grid node g (0 <= g < N) along one direction: the cells
