@@ -385,6 +385,42 @@ def solve_leg(a) -> dict:
     return out
 
 
+def chfsi_leg(a) -> dict:
+    """Chebyshev-filtered subspace iteration (Alg. ChFSi) at block scale on the
+    config-2 mesh (16^3 cells, p = 6, periodic, 884,736 dofs): a block of
+    --chfsi-block vectors (256), the lowest three quarters wanted (a 25% buffer as in
+    the paper's runs), degree --chfsi-degree filters, residual tolerance 5e-5.  Every
+    step is a library call: fused filter steps, block Gram, the k x k eigen-solver
+    (block Jacobi beyond 64), block updates."""
+    import torch
+    from paper_2208_07129_amd import chebyshev, mfmv
+    w = workload("c2", None)
+    op = mfmv.Operator.from_workload(w)
+    k = a.chfsi_block
+    nev = k * 3 // 4
+    D = mfmv.gll_mass(op, inv_sqrt=True)
+    t_b = time.perf_counter()
+    bounds = chebyshev.standard_form_bounds(op, D, steps=a.lanczos_steps)
+    t_b = time.perf_counter() - t_b
+    si = chebyshev.SubspaceIteration(op, k)
+    U0 = torch.from_numpy(np.random.default_rng(78).uniform(-1, 1, (op.ndofs, k))).cuda()
+    print(f"chfsi k={k} ...", file=sys.stderr, flush=True)
+    res = si.solve(U0, nev=nev, degree=a.chfsi_degree, tol=5e-5, maxit=a.chfsi_maxit,
+                   bounds=bounds)
+    res["bounds_seconds"] = t_b
+    out = {"metric": "ChFSI time to residual 5e-5 (lowest eigenpairs of M^-1/2 A M^-1/2)",
+           "unit": "s", "value": res["seconds"], "higher_is_better": False, "n_gpus": 1,
+           "data": "synthetic", "dtype": "f64",
+           "config": {"workload": w.name, "ndofs": int(op.ndofs), "block": k, "wanted": nev,
+                      "degree": a.chfsi_degree},
+           **{key: v for key, v in res.items() if key not in ("history", "eigenvalues")},
+           "lowest_eigenvalues": res["eigenvalues"][:8], "highest_wanted": res["eigenvalues"][-1],
+           "history": [float(h) for h in res["history"]]}
+    print(json.dumps({"chfsi": {key: v for key, v in out.items() if key != "history"}}),
+          file=sys.stderr, flush=True)
+    return out
+
+
 def chebyshev_leg(a) -> dict:
     """The Chebyshev filter of subspace iteration (Alg. ChFSi) on the standard form
     M^{-1/2} A M^{-1/2} of config 2 (16^3, p = 6, 64 columns): degree-m filters of fused
@@ -621,7 +657,7 @@ def batched_leg(a) -> dict:
     return out
 
 
-LEGS = ("headline", "mixed", "cpu", "config3", "config4", "config5")
+LEGS = ("headline", "mixed", "cpu", "config3", "config4", "config5", "chfsi")
 
 
 def main(argv=None):
@@ -649,6 +685,8 @@ def main(argv=None):
                     help="only the hanging-node constrained apply on the refined mesh")
     ap.add_argument("--cheb-degree", type=int, default=10)
     ap.add_argument("--chfsi-maxit", type=int, default=80)
+    ap.add_argument("--chfsi-block", type=int, default=256,
+                    help="block size of the subspace-iteration leg (wanted: three quarters)")
     ap.add_argument("--chfsi-degree", type=int, default=40)
     ap.add_argument("--solve-maxit", type=int, default=4000)
     ap.add_argument("--train-steps", type=int, default=1000)
@@ -771,6 +809,9 @@ def main(argv=None):
         torch.cuda.empty_cache()
     if "config5" in legs:
         out["config5"] = solve_leg(a)
+        torch.cuda.empty_cache()
+    if "chfsi" in legs:
+        out["chfsi"] = chfsi_leg(a)
         torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
     return 0

@@ -204,11 +204,15 @@ def test_sym_eig_rejects_large_blocks_and_short_work():
     assert e.value.status == mfmv.MF_ERR_ARG
 
 
-@pytest.mark.parametrize("bc", [W.BC_PERIODIC, W.BC_DIRICHLET0])
-def test_subspace_iteration_finds_the_lowest_eigenpairs(bc):
+@pytest.mark.parametrize("bc,k,nev,tol", [(W.BC_PERIODIC, 16, 10, 2e-7),
+                                          (W.BC_DIRICHLET0, 16, 10, 2e-7),
+                                          (W.BC_PERIODIC, 96, 72, 1e-6)])
+def test_subspace_iteration_finds_the_lowest_eigenpairs(bc, k, nev, tol):
     """Chebyshev-filtered subspace iteration against a dense eigen-solve of the
     oracle's standard-form matrix: the nev lowest eigenvalues to 1e-9 once every
-    residual norm is below 2e-7."""
+    residual norm is below tol (k = 96: the block-Jacobi eigen-solver in the
+    orthogonalisation and Rayleigh-Ritz steps; its wanted eigenvalues reach ~50,
+    where the residual estimate resolves ~1e-8 |theta|, hence the looser tol)."""
     from paper_2208_07129_amd.chebyshev import SubspaceIteration
     mesh = W.BoxMesh(n=(3, 3, 3), lo=(0, 0, 0), hi=(3.0, 3.0, 3.0), bc=bc)
     Vf = W.gaussian_wells(8, L=3.0, k=3, width=0.6)
@@ -220,13 +224,12 @@ def test_subspace_iteration_finds_the_lowest_eigenpairs(bc):
     Dr[free] = 1.0 / np.sqrt(m[free])
     S = Dr[:, None] * orc.assemble_dense() * Dr[None, :]
     ref = np.linalg.eigvalsh(S[np.ix_(free, free)])
-    k, nev = 16, 10
     U0 = np.random.default_rng(2).uniform(-1, 1, (orc.ndofs, k))
     U0[orc.constrained] = 0.0
     si = SubspaceIteration(op, k)
     # residual norms come from ||H~ u||^2 - theta^2 (resolution ~1e-8 |theta|); the
     # eigenvalues then carry errors of order residual^2 / gap
-    out = si.solve(T(U0), nev, degree=12, tol=2e-7, maxit=60)
+    out = si.solve(T(U0), nev, degree=12, tol=tol, maxit=60)
     print(out["iterations"], out["residual"])
     assert out["converged"], out["history"][-5:]
     np.testing.assert_allclose(out["eigenvalues"], ref[:nev], rtol=0,
