@@ -146,6 +146,22 @@ int mf_operator_info(const mf_operator* op, int64_t* ndofs, int64_t* ncells, int
  * range.  Errors: MF_ERR_ARG (NULL), MF_ERR_UNSUPPORTED (refined operator). */
 int mf_cell_order(const mf_operator* op, int32_t* order);
 
+/* Deterministic assembly on (on != 0) or off for mf_apply / mf_apply_add of a
+ * box-mesh operator.  The paper's GPU kernel adds the cell contributions to
+ * shared rows with atomics (Sec. 3.2.4), so their summation order, and the
+ * last bits of those rows, vary from run to run.  With this on, the cells are
+ * coloured (per direction cx mod 2, the last cell of an odd periodic
+ * direction a third colour; cells of one colour share no node) and the kernel
+ * runs once per colour in colour order: each shared row then receives at most
+ * one addition per launch and its terms are summed in a fixed order, so
+ * repeated applies give bitwise equal results (for a fixed launch shape and
+ * precision).  Costs up to 27 launches of fewer cells each.  The first call
+ * uploads the colour-sorted cell order (device memory held until
+ * mf_destroy_operator).  Errors: MF_ERR_ARG (NULL), MF_ERR_UNSUPPORTED
+ * (sheared or refined operator, or a periodic direction of one cell, which
+ * meets itself), MF_ERR_OOM, MF_ERR_HIP. */
+int mf_set_deterministic(mf_operator* op, int on);
+
 /* Y := A X (overwrite, never accumulate), eq. AU with one partition.
  *   X: device, ndofs rows, row stride ldx >= nvec; constrained rows are
  *      ignored (read as zero: the action of C, Sec. 3.2.2).

@@ -290,6 +290,7 @@ void mf_destroy_operator(mf_operator* handle) {
   batch_cache_forget(op);
   if (op->d_map) (void)hipFree(op->d_map);
   if (op->d_order) (void)hipFree(op->d_order);
+  if (op->d_colour_order) (void)hipFree(op->d_colour_order);
   for (hipEvent_t e : op->ev) (void)hipEventDestroy(e);
   if (op->d_geo) (void)hipFree(op->d_geo);
   if (op->d_vq) (void)hipFree(op->d_vq);
@@ -319,6 +320,52 @@ int mf_cell_order(const mf_operator* handle, int32_t* order) {
   if (op->refined) return fail(MF_ERR_UNSUPPORTED, "a refined operator has no grid cell order");
   const std::vector<int32_t> o = cell_order(op->grid.n);
   std::memcpy(order, o.data(), o.size() * sizeof(int32_t));
+  return MF_OK;
+}
+
+int mf_set_deterministic(mf_operator* handle, int on) {
+  if (!handle) return fail(MF_ERR_ARG, "operator is NULL");
+  Operator* op = reinterpret_cast<Operator*>(handle);
+  if (!on) {
+    op->deterministic = false;
+    return MF_OK;
+  }
+  if (!op->box)
+    return fail(MF_ERR_UNSUPPORTED,
+                "the deterministic assembly is built for box meshes of axis-aligned cells");
+  if (!op->d_colour_order) {
+    bool periodic[3];
+    for (int d = 0; d < 3; ++d) periodic[d] = op->grid.N[d] == op->grid.n[d] * op->p;
+    const std::vector<int> col = cell_colours(op->grid.n, periodic);
+    if (col.empty())
+      return fail(MF_ERR_UNSUPPORTED,
+                  "a periodic direction with one cell: the cell meets itself (no colouring)");
+    // the processing order, stably sorted by colour
+    const std::vector<int32_t> order = cell_order(op->grid.n);
+    std::vector<int32_t> sorted;
+    sorted.reserve(order.size());
+    std::vector<int64_t> off(1, 0);
+    for (int c = 0; c < 27; ++c) {
+      for (int32_t e : order)
+        if (col[e] == c) sorted.push_back(e);
+      if ((int64_t)sorted.size() > off.back()) off.push_back((int64_t)sorted.size());
+    }
+    const size_t bytes = sorted.size() * sizeof(int32_t);
+    hipError_t err = hipMalloc((void**)&op->d_colour_order, bytes);
+    if (err != hipSuccess) {
+      op->d_colour_order = nullptr;
+      return err == hipErrorOutOfMemory ? fail(MF_ERR_OOM, "hipMalloc (colour order)")
+                                        : hip_fail(err, "hipMalloc");
+    }
+    err = hipMemcpy(op->d_colour_order, sorted.data(), bytes, hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+      (void)hipFree(op->d_colour_order);
+      op->d_colour_order = nullptr;
+      return hip_fail(err, "hipMemcpy (colour order)");
+    }
+    op->coff = off;
+  }
+  op->deterministic = true;
   return MF_OK;
 }
 
@@ -395,12 +442,26 @@ int mf::apply_dispatch(mf_operator* handle, const double* X, double* Y, int nvec
     if (err != hipSuccess) return hip_fail(err, "zero kernel launch");
   }
   if (ev) (void)hipEventRecord(ev[1], s);
-  err = map32   ? launch_apply_box_map32(*op, a, s)
-        : mixed ? launch_apply_mixed(*op, a, prec, s)
-              : (op->box       ? (a.cfg >= kBoxVecCfgs ? launch_apply_mfma(*op, a, s)
-                                                         : launch_apply_box(*op, a, s))
-                 : op->map_box ? launch_apply_box_map(*op, a, s)
-                               : launch_apply_f64(*op, a, s));
+  auto launch = [&]() {
+    return map32   ? launch_apply_box_map32(*op, a, s)
+           : mixed ? launch_apply_mixed(*op, a, prec, s)
+                 : (op->box       ? (a.cfg >= kBoxVecCfgs ? launch_apply_mfma(*op, a, s)
+                                                            : launch_apply_box(*op, a, s))
+                    : op->map_box ? launch_apply_box_map(*op, a, s)
+                                  : launch_apply_f64(*op, a, s));
+  };
+  if (op->deterministic && op->box) {
+    // one launch per colour, in colour order: within a launch every shared row
+    // receives at most one atomic addition per column, so its sum is formed in
+    // a fixed order
+    for (size_t c = 0; c + 1 < op->coff.size() && err == hipSuccess; ++c) {
+      a.order = op->d_colour_order + op->coff[c];
+      a.ncells = op->coff[c + 1] - op->coff[c];
+      err = launch();
+    }
+  } else {
+    err = launch();
+  }
   if (err != hipSuccess) return hip_fail(err, "apply kernel launch");
   if (ev) (void)hipEventRecord(ev[2], s);
   return MF_OK;
@@ -424,9 +485,10 @@ int mf_set_launch(mf_operator* handle, int general, int cfg) {
   if (cfg < -1 || cfg >= kBoxCfgs) return fail(MF_ERR_ARG, "cfg out of range");
   if (cfg >= 0 && !apply_box_supported(op->p, op->q, cfg))
     return fail(MF_ERR_UNSUPPORTED, "launch shape does not fit this (p, q)");
-  if (general) {
+  if (general) {  // the general kernel takes cells in index order: no colour order
     op->box = false;
     op->map_box = false;
+    op->deterministic = false;
   }
   op->cfg = cfg;
   return MF_OK;

@@ -100,6 +100,19 @@ int validate_mesh(const mf_box_mesh* m) {
   return MF_OK;
 }
 
+std::vector<int> cell_colours(const int n[3], const bool periodic[3]) {
+  for (int d = 0; d < 3; ++d)
+    if (periodic[d] && n[d] == 1) return {};
+  const int64_t ne = (int64_t)n[0] * n[1] * n[2];
+  std::vector<int> col(ne);
+  auto c1 = [&](int d, int c) { return (periodic[d] && n[d] % 2 == 1 && c == n[d] - 1) ? 2 : c % 2; };
+  for (int64_t e = 0; e < ne; ++e) {
+    const int cx = (int)(e % n[0]), cy = (int)((e / n[0]) % n[1]), cz = (int)(e / ((int64_t)n[0] * n[1]));
+    col[e] = c1(0, cx) + 3 * (c1(1, cy) + 3 * c1(2, cz));
+  }
+  return col;
+}
+
 std::vector<int32_t> cell_order(const int n[3]) {
   struct Blk {
     int lo[3], hi[3];

@@ -83,6 +83,11 @@ struct Operator {
   std::map<std::pair<int, int>, std::vector<double>> tuned_ms;  // median ms per shape (-1: not timed)
   int32_t* d_map = nullptr;   // E x np^3, -1 = constrained
   int32_t* d_order = nullptr; // E: processing order of the cells
+  // deterministic assembly (mf_set_deterministic): the cells sorted by colour
+  // (cells of one colour share no node), colour c at [coff[c], coff[c+1])
+  bool deterministic = false;
+  int32_t* d_colour_order = nullptr;
+  std::vector<int64_t> coff;
   double* d_geo = nullptr;    // E x 6: mu det J (J^-1 J^-T), (00,01,02,11,12,22)
   double* d_vq = nullptr;     // E x nq^3: det J (V + sigma)
   double* d_dtab = nullptr;   // 1D sums of the diagonal (nq np + 3 np)
@@ -342,6 +347,10 @@ inline bool box_pairs_ok(const double* X, const double* Y, int nvec, int64_t ldx
 // Processing order of the cells: 8 blocks by recursive bisection (one per XCD),
 // Morton order inside each block.
 std::vector<int32_t> cell_order(const int n[3]);
+// Cell colours for the deterministic assembly: per direction cx mod 2, and 2
+// for the last cell of a periodic direction with an odd count n >= 3; colour
+// = c0 + 3 (c1 + 3 c2).  Fails (empty) for a periodic direction with n = 1.
+std::vector<int> cell_colours(const int n[3], const bool periodic[3]);
 bool apply_f64_supported(int p, int q);
 // Vectors per workgroup tile of the FP64 kernel (256 threads, LDS within 64 KiB).
 int choose_vtile_f64(int np, int nq, int nvec);

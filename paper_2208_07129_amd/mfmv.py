@@ -31,7 +31,7 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_apply_add", "mf_zero", "mf_set_launch", "mf_set_launch_mixed", "mf_timing",
            "mf_timing_read", "mf_timing_samples", "mf_batch_create", "mf_batch_destroy", "mf_batch_set_launch",
            "mf_batch_apply", "mf_batch_capture", "mf_batch_replay", "mf_batch_info",
-           "mf_tune", "mf_tune_info", "mf_batch_tune", "mf_apply_batched",
+           "mf_tune", "mf_tune_info", "mf_set_deterministic", "mf_batch_tune", "mf_apply_batched",
            "mf_last_error",
            # include/mfsolve.h
            "mf_diagonal", "mf_block_gram", "mf_block_gram_noalloc", "mf_block_gram_work",
@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
             "mf_operator_info": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(I64),
                                      ctypes.POINTER(I), ctypes.POINTER(I)]),
             "mf_cell_order": (I, [P, P]),
+            "mf_set_deterministic": (I, [P, I]),
             "mf_apply": (I, [P, P, P, I, I64, I64, I, P]),
             "mf_apply_add": (I, [P, P, P, I, I64, I64, I, P]),
             "mf_zero": (I, [P, I64, I, I64, P]),
@@ -264,6 +265,10 @@ class Operator:
         out = np.empty(self.ncells, dtype=np.int32)
         _check(lib().mf_cell_order(self._h, out.ctypes.data))
         return out
+
+    def set_deterministic(self, on: bool = True):
+        """Colour-ordered assembly: bitwise reproducible applies (mf_set_deterministic)."""
+        _check(lib().mf_set_deterministic(self._h, int(bool(on))))
 
     def set_launch(self, general: bool = False, cfg: int = -1):
         _check(lib().mf_set_launch(self._h, int(general), int(cfg)))
