@@ -681,7 +681,7 @@ def batched_leg(a) -> dict:
     return out
 
 
-LEGS = ("headline", "mixed", "cpu", "config3", "config4", "config5", "chfsi")
+LEGS = ("headline", "mixed", "deterministic", "cpu", "config3", "config4", "config5", "chfsi")
 
 
 def main(argv=None):
@@ -817,7 +817,7 @@ def main(argv=None):
     rows = OracleRows(w, 32, 12345)
     out["rel_err_vs_oracle_sampled"] = rows.error(Y, Xh)
     out["oracle_rows_sampled"] = int(rows.rows.size)
-    if a.precision == "fp64" and w.mesh.lin is None:
+    if "deterministic" in legs and a.precision == "fp64" and w.mesh.lin is None:
         out["deterministic_assembly"] = deterministic_leg(op, X, Y, a.steps)
     if "mixed" in legs and a.precision == "fp64":
         out["mixed"] = mixed_leg(op, X, Xh, nvec, a.steps, a.warmup, stream, free, rows,
