@@ -222,13 +222,16 @@ int mf_tune_info(const mf_operator* op, int nvec, int prec, int* cfg, double* ms
  *   general != 0 forces the general-geometry kernel (full 3x3 factor, three
  *                LDS buffers) even on axis-aligned cells; it cannot be undone
  *                on this operator.
- *   cfg          launch shape of the axis-aligned-cell kernel, 0..9, or -1 for
- *                the built-in choice by column count.  Shapes 2 and 4 give
+ *   cfg          launch shape of the axis-aligned-cell kernel, 0..12, or -1
+ *                for the built-in choice by column count.  Shapes 2 and 4 give
  *                every thread two adjacent columns (16-byte accesses); a call
  *                with odd nvec, odd ldx or ldy, or X or Y not 16-byte aligned
  *                runs the one-column shape with the same tile instead.
  *                Shapes 3, 4, 5 and 8 use a persistent grid that prefetches
  *                the next cell's X during the current cell's contractions.
+ *                Shape 10 runs the contractions on the FP64 matrix cores
+ *                (q = p + 1 <= 8).  Shapes 11 and 12 take 1 and 2 columns per
+ *                cell with one and two wavefronts (narrow blocks).
  * Errors: MF_ERR_ARG (NULL, cfg out of range), MF_ERR_UNSUPPORTED (shape does
  * not fit the LDS for this p, q). */
 int mf_set_launch(mf_operator* op, int general, int cfg);

@@ -101,6 +101,8 @@ hipError_t launch_pq(const ApplyLaunch& a, hipStream_t s) {
   if (!done) err = try_cfg<NP, NQ, 7>(a, s, done);
   if (!done) err = try_cfg<NP, NQ, 8>(a, s, done);
   if (!done) err = try_cfg<NP, NQ, 9>(a, s, done);
+  if (!done) err = try_cfg<NP, NQ, 11>(a, s, done);
+  if (!done) err = try_cfg<NP, NQ, 12>(a, s, done);
   return done ? err : hipErrorInvalidValue;
 }
 

@@ -55,7 +55,7 @@ hipError_t launch_apply_mfma_p<MF_P>(const Operator& op, const ApplyLaunch& a, h
   constexpr int N = MF_P + 1;
   if constexpr (N <= kMfmaMaxN) {
     if (op.q != N) return hipErrorInvalidValue;
-    if (a.cfg == kBoxVecCfgs)
+    if (a.cfg == kBoxMfmaCfg)
       return a.accumulate ? launch_mfma<N, true>(a, s) : launch_mfma<N, false>(a, s);
   }
   (void)op;

@@ -445,7 +445,7 @@ int mf::apply_dispatch(mf_operator* handle, const double* X, double* Y, int nvec
   auto launch = [&]() {
     return map32   ? launch_apply_box_map32(*op, a, s)
            : mixed ? launch_apply_mixed(*op, a, prec, s)
-                 : (op->box       ? (a.cfg >= kBoxVecCfgs ? launch_apply_mfma(*op, a, s)
+                 : (op->box       ? (a.cfg == kBoxMfmaCfg ? launch_apply_mfma(*op, a, s)
                                                             : launch_apply_box(*op, a, s))
                     : op->map_box ? launch_apply_box_map(*op, a, s)
                                   : launch_apply_f64(*op, a, s));

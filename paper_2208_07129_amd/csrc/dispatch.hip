@@ -343,7 +343,7 @@ hipError_t launch_apply_cheb(const Operator& op, const double* Y, double* Out, i
 bool apply_box_supported(int p, int q, int cfg) {
   if (p < 1 || p > kMaxP || q < p + 1 || q > p + kMaxQExtra || cfg < 0 || cfg >= kBoxCfgs)
     return false;
-  if (cfg >= kBoxVecCfgs) return q == p + 1 && q <= kMfmaMaxN;
+  if (cfg == kBoxMfmaCfg) return q == p + 1 && q <= kMfmaMaxN;
   return box_cfg(p + 1, q, cfg).B > 0;
 }
 
@@ -352,7 +352,8 @@ int choose_cfg_box(int np, int nq, int nvec) {
   const int b0 = box_cfg(np, nq, 0).B;
   if (nvec >= b0) return 0;
   int best = 0, bestB = b0;
-  for (int c = 1; c < kBoxVecCfgs; ++c) {
+  for (int c = 1; c < kBoxCfgs; ++c) {
+    if (c == kBoxMfmaCfg) continue;
     const int b = box_cfg(np, nq, c).B;
     if (b >= nvec && b < bestB) {
       best = c;

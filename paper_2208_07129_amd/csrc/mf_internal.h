@@ -15,8 +15,10 @@ namespace mf {
 
 constexpr int kMaxP = 10;
 constexpr int kMaxQExtra = 3;  // q in [p+1, p+3]
-constexpr int kBoxVecCfgs = 10;  // vector-ALU launch shapes of the box-cell kernel
-constexpr int kBoxCfgs = 11;     // ... and 10: the FP64 matrix-core body (q = p + 1 <= 8)
+// Launch shapes of the box-cell kernel: 0 .. 9, 11, 12 on the vector ALUs,
+// 10 the FP64 matrix-core body (q = p + 1 <= 8)
+constexpr int kBoxMfmaCfg = 10;
+constexpr int kBoxCfgs = 13;
 constexpr int kMfmaMaxN = 8;     // points per direction the matrix-core body handles
 constexpr int kMixedCfgs = 7;  // launch shapes of the mixed-precision apply (4..6: FP32 vector)
 constexpr int kBatchCfgs = 6;  // launch shapes of the batched apply (3..5: one launch per kind)

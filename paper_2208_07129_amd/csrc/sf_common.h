@@ -357,6 +357,10 @@ constexpr BoxCfg box_cfg_raw(int idx) {
     case 7: return BoxCfg{4, 256, 1, false};
     case 8: return BoxCfg{4, 0, 1, true};
     case 9: return BoxCfg{4, 0, 1, false};
+    // narrow blocks: one (B = 1) or two (B = 2) wavefronts per cell, so the
+    // barriers between the stages are those of one or two wavefronts
+    case 11: return BoxCfg{1, 0, 1, false};
+    case 12: return BoxCfg{2, 0, 1, false};
     default: return BoxCfg{0, 256, 1, false};
   }
 }
@@ -392,13 +396,14 @@ constexpr int box_cfg_single(int np, int nq, int idx) {
 }
 // Workgroups per CU that the LDS allows, and the matching waves per SIMD the
 // register allocation must leave room for.
-constexpr int box_wg_per_cu(int np, int nq, int B) {
+constexpr int box_wg_per_cu(int np, int nq, int B, int NT = 256) {
   const size_t l = box_lds_bytes(np, nq, B);
   int n = (int)(kLdsMax / (l > 0 ? l : 1));
-  return n < 1 ? 1 : (n > 8 ? 8 : n);
+  const int cap = NT <= 128 ? 32 : 8;  // the narrow shapes run many small workgroups
+  return n < 1 ? 1 : (n > cap ? cap : n);
 }
 constexpr int box_waves_per_eu(int np, int nq, int B, int NT) {
-  const int w = (box_wg_per_cu(np, nq, B) * (NT / 64) + 3) / 4;
+  const int w = (box_wg_per_cu(np, nq, B, NT) * (NT / 64) + 3) / 4;
   return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
