@@ -61,9 +61,10 @@ typedef enum {
 } mf_bc;
 
 typedef enum {
-    MF_FP64 = 0,              /* all arithmetic in FP64 */
-    MF_FP32_MFMA = 1,         /* contractions in FP32, FP64 assembly */
-    MF_BF16_MFMA = 2          /* contractions with BF16 operands, FP32 accumulation, FP64 assembly */
+    MF_FP64 = 0,  /* all arithmetic in FP64 */
+    MF_FP32 = 1,  /* contractions in FP32 (vector or matrix-core shapes), FP64 assembly */
+    MF_BF16 = 2   /* contractions on the matrix cores with BF16 operands, FP32 accumulation,
+                     FP64 assembly */
 } mf_precision;
 
 /* Structured hexahedral box mesh: n[d] cells per direction on [lo, hi], then
@@ -168,7 +169,7 @@ int mf_set_deterministic(mf_operator* op, int on);
  *   Y: device, ndofs rows, row stride ldy >= nvec; constrained rows are
  *      written as zero (the action of C^T).  Y must not overlap X.
  *   prec: MF_FP64 evaluates every step in FP64 (FP64 atomic assembly).
- *         MF_FP32_MFMA / MF_BF16_MFMA: cell arrays are FP32 and each (cell,
+ *         MF_FP32 / MF_BF16: cell arrays are FP32 and each (cell,
  *         column) is scaled by a power of two before the conversion and
  *         unscaled before the FP64 assembly; the sum-factorised contractions
  *         run on the matrix cores (FP32 or BF16 operands, FP32 accumulation)

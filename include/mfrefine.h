@@ -40,7 +40,7 @@
  * mf_status (message in mf_last_error()).
  *
  * A refined operator supports mf_apply / mf_apply_add in MF_FP64, and in
- * MF_FP32_MFMA on axis-aligned cells (FP32 cell arrays with power-of-two
+ * MF_FP32 on axis-aligned cells (FP32 cell arrays with power-of-two
  * scaling per cell and column, the FP32 vector contractions, FP64 assembly);
  * mf_gll_mass gives the constrained lumped mass (see
  * mf_cheb_step_constrained); the calls built on the uniform grid

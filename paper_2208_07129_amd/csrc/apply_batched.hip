@@ -98,9 +98,9 @@ struct KindShape {
   static constexpr int B = c.B, NT = c.NT;
   // FP64 and FP32 run the box body (double / float cell arrays), BF16 the
   // matrix-core body
-  static constexpr bool BOX = PREC != MF_BF16_MFMA;
+  static constexpr bool BOX = PREC != MF_BF16;
   static constexpr size_t LDS = PREC == MF_FP64        ? box_lds_bytes(NP, NP, B)
-                                : PREC == MF_FP32_MFMA ? box_lds_bytes_t<float>(NP, NP, B)
+                                : PREC == MF_FP32 ? box_lds_bytes_t<float>(NP, NP, B)
                                                        : mixed_lds_bytes(NP, NP, B);
   static constexpr int WG = (int)(kLdsMax / LDS) < 1 ? 1 : (int)(kLdsMax / LDS);
   static constexpr int W0 = (WG * (NT / 64) + 3) / 4;
@@ -118,7 +118,7 @@ __device__ __forceinline__ void kind_item(double* lds, const BatchOp& op, const 
   if constexpr (PREC == MF_FP64)
     box_cell_tile<NP, NP, B, 1, NT, false>(lds, op.grid, op.geo, op.vq, ptrs.X[o], ptrs.Y[o],
                                            ptrs.ldx[o], ptrs.ldy[o], ptrs.nvec[o], e, v0);
-  else if constexpr (PREC == MF_FP32_MFMA)
+  else if constexpr (PREC == MF_FP32)
     box_cell_tile<NP, NP, B, 1, NT, false, float>(reinterpret_cast<float*>(lds), op.grid, op.geo,
                                                   op.vq, ptrs.X[o], ptrs.Y[o], ptrs.ldx[o],
                                                   ptrs.ldy[o], ptrs.nvec[o], e, v0);

@@ -113,7 +113,7 @@ hipError_t launch_pq(const ApplyLaunch& a, hipStream_t s) {
   if (!done) err = try_cfg<NP, NQ, 1, PREC>(a, s, done);
   if (!done) err = try_cfg<NP, NQ, 2, PREC>(a, s, done);
   if (!done) err = try_cfg<NP, NQ, 3, PREC>(a, s, done);
-  if constexpr (PREC == MF_FP32_MFMA) {
+  if constexpr (PREC == MF_FP32) {
     if (!done) err = try_vec32<NP, NQ, 4>(a, s, done);
     if (!done) err = try_vec32<NP, NQ, 5>(a, s, done);
     if (!done) err = try_vec32<NP, NQ, 6>(a, s, done);
@@ -128,8 +128,8 @@ hipError_t launch_pq(const ApplyLaunch& a, hipStream_t s) {
 
 template <int NP, int NQ>
 hipError_t launch_pq_prec(const ApplyLaunch& a, int prec, hipStream_t s) {
-  if (prec == MF_FP32_MFMA) return launch_pq<NP, NQ, MF_FP32_MFMA>(a, s);
-  if (prec == MF_BF16_MFMA) return launch_pq<NP, NQ, MF_BF16_MFMA>(a, s);
+  if (prec == MF_FP32) return launch_pq<NP, NQ, MF_FP32>(a, s);
+  if (prec == MF_BF16) return launch_pq<NP, NQ, MF_BF16>(a, s);
   return hipErrorInvalidValue;
 }
 

@@ -387,11 +387,11 @@ int mf::apply_dispatch(mf_operator* handle, const double* X, double* Y, int nvec
   const size_t xb = ((op->ndofs - 1) * ldx + nvec) * sizeof(double);
   const size_t yb = ((op->ndofs - 1) * ldy + nvec) * sizeof(double);
   if (overlaps(X, xb, Y, yb)) return fail(MF_ERR_ARG, "X and Y overlap");
-  if (prec != MF_FP64 && prec != MF_FP32_MFMA && prec != MF_BF16_MFMA)
+  if (prec != MF_FP64 && prec != MF_FP32 && prec != MF_BF16)
     return fail(MF_ERR_UNSUPPORTED, "unknown precision");
   const bool mixed = prec != MF_FP64;
   // mixed precision: axis-aligned cells; on a refined map FP32 vector only
-  const bool map32 = mixed && op->map_box && prec == MF_FP32_MFMA;
+  const bool map32 = mixed && op->map_box && prec == MF_FP32;
   if (mixed && !op->box && !map32)
     return fail(MF_ERR_UNSUPPORTED,
                 "mixed precision is built for axis-aligned cells only (FP32 on refined meshes)");

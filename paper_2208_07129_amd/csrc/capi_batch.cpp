@@ -276,7 +276,7 @@ static int enqueue(Batch* b, const BatchPtrs& p, hipStream_t s) {
 // cells, columns) in the caller's order.
 static std::string batch_key(int nops, const Operator* const* ops, const int* nvec, int prec) {
   std::string k = device_arch() + "/batch/" +
-                  (prec == MF_FP64 ? "fp64" : prec == MF_FP32_MFMA ? "fp32" : "bf16") + "/";
+                  (prec == MF_FP64 ? "fp64" : prec == MF_FP32 ? "fp32" : "bf16") + "/";
   char buf[64];
   for (int i = 0; i < nops; ++i) {
     std::snprintf(buf, sizeof(buf), "%sp%dq%dc%lldv%d", i ? "_" : "", ops[i]->p, ops[i]->q,
@@ -325,7 +325,7 @@ int mf_batch_create(int nops, mf_operator* const* ops, const int* nvec, int prec
   *out = nullptr;
   if (nops < 1 || nops > kMaxBatch) return fail(MF_ERR_ARG, "nops must be in [1, 64]");
   if (!ops || !nvec) return fail(MF_ERR_ARG, "ops and nvec must be non-NULL");
-  if (prec != MF_FP64 && prec != MF_FP32_MFMA && prec != MF_BF16_MFMA)
+  if (prec != MF_FP64 && prec != MF_FP32 && prec != MF_BF16)
     return fail(MF_ERR_UNSUPPORTED, "unknown precision");
   Batch* b = new (std::nothrow) Batch();
   if (!b) return fail(MF_ERR_OOM, "host allocation failed");

@@ -31,7 +31,7 @@ std::string device_arch() {
 namespace {
 
 const char* prec_name(int prec) {
-  return prec == MF_FP64 ? "fp64" : prec == MF_FP32_MFMA ? "fp32" : "bf16";
+  return prec == MF_FP64 ? "fp64" : prec == MF_FP32 ? "fp32" : "bf16";
 }
 
 // The cache file: one flat JSON object whose values are objects without
@@ -166,11 +166,11 @@ extern "C" {
 int mf_tune(mf_operator* handle, int nvec, int prec, const char* cache_path) {
   if (!handle) return fail(MF_ERR_ARG, "operator is NULL");
   if (nvec < 1) return fail(MF_ERR_ARG, "nvec must be >= 1");
-  if (prec != MF_FP64 && prec != MF_FP32_MFMA && prec != MF_BF16_MFMA)
+  if (prec != MF_FP64 && prec != MF_FP32 && prec != MF_BF16)
     return fail(MF_ERR_UNSUPPORTED, "unknown precision");
   Operator* op = reinterpret_cast<Operator*>(handle);
   const bool mixed = prec != MF_FP64;
-  if (mixed && !op->box && !(op->map_box && prec == MF_FP32_MFMA))
+  if (mixed && !op->box && !(op->map_box && prec == MF_FP32))
     return fail(MF_ERR_UNSUPPORTED,
                 "mixed precision is built for axis-aligned cells only (FP32 on refined meshes)");
   // candidate shapes; the general-geometry and refined-map kernels have one
@@ -180,7 +180,7 @@ int mf_tune(mf_operator* handle, int nvec, int prec, const char* cache_path) {
     for (int c = 0; c < kBoxCfgs; ++c)
       if (apply_box_supported(op->p, op->q, c)) cand.push_back(c);
   } else if (mixed && op->box) {
-    const int n = prec == MF_FP32_MFMA ? kMixedCfgs : kMixedMfmaCfgs;
+    const int n = prec == MF_FP32 ? kMixedCfgs : kMixedMfmaCfgs;
     for (int c = 0; c < n; ++c)
       if (apply_mixed_supported(op->p, op->q, c)) cand.push_back(c);
   }

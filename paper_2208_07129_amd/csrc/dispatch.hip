@@ -159,8 +159,8 @@ hipError_t launch_batched(int prec, int bcfg, const BatchOp* ops, const uint8_t*
   if (prec == P && bcfg == C)                                                                \
     return launch_batched_kernel<P, C>(ops, item_op, bounds, ptrs, grid, s);
   MF_BATCH_CASE(MF_FP64, 0) MF_BATCH_CASE(MF_FP64, 1) MF_BATCH_CASE(MF_FP64, 2)
-  MF_BATCH_CASE(MF_FP32_MFMA, 0) MF_BATCH_CASE(MF_FP32_MFMA, 1) MF_BATCH_CASE(MF_FP32_MFMA, 2)
-  MF_BATCH_CASE(MF_BF16_MFMA, 0) MF_BATCH_CASE(MF_BF16_MFMA, 1) MF_BATCH_CASE(MF_BF16_MFMA, 2)
+  MF_BATCH_CASE(MF_FP32, 0) MF_BATCH_CASE(MF_FP32, 1) MF_BATCH_CASE(MF_FP32, 2)
+  MF_BATCH_CASE(MF_BF16, 0) MF_BATCH_CASE(MF_BF16, 1) MF_BATCH_CASE(MF_BF16, 2)
 #undef MF_BATCH_CASE
   return hipErrorInvalidValue;
 }
@@ -171,17 +171,17 @@ hipError_t launch_batched_kind_any(int prec, int p, bool loop, const BatchOp* op
                                    hipStream_t s) {
   if (prec == MF_FP64)
     return launch_batched_kind<MF_FP64>(p, loop, ops, item_op, bounds, ptrs, grid, s);
-  if (prec == MF_FP32_MFMA)
-    return launch_batched_kind<MF_FP32_MFMA>(p, loop, ops, item_op, bounds, ptrs, grid, s);
-  if (prec == MF_BF16_MFMA)
-    return launch_batched_kind<MF_BF16_MFMA>(p, loop, ops, item_op, bounds, ptrs, grid, s);
+  if (prec == MF_FP32)
+    return launch_batched_kind<MF_FP32>(p, loop, ops, item_op, bounds, ptrs, grid, s);
+  if (prec == MF_BF16)
+    return launch_batched_kind<MF_BF16>(p, loop, ops, item_op, bounds, ptrs, grid, s);
   return hipErrorInvalidValue;
 }
 
 int batched_kind_blocks_per_cu(int prec, int p) {
   if (prec == MF_FP64) return batched_kind_occupancy<MF_FP64>(p);
-  if (prec == MF_FP32_MFMA) return batched_kind_occupancy<MF_FP32_MFMA>(p);
-  if (prec == MF_BF16_MFMA) return batched_kind_occupancy<MF_BF16_MFMA>(p);
+  if (prec == MF_FP32) return batched_kind_occupancy<MF_FP32>(p);
+  if (prec == MF_BF16) return batched_kind_occupancy<MF_BF16>(p);
   return 0;
 }
 
@@ -189,8 +189,8 @@ int batched_blocks_per_cu(int prec, int bcfg) {
 #define MF_BATCH_CASE(P, C) \
   if (prec == P && bcfg == C) return batched_occupancy<P, C>();
   MF_BATCH_CASE(MF_FP64, 0) MF_BATCH_CASE(MF_FP64, 1) MF_BATCH_CASE(MF_FP64, 2)
-  MF_BATCH_CASE(MF_FP32_MFMA, 0) MF_BATCH_CASE(MF_FP32_MFMA, 1) MF_BATCH_CASE(MF_FP32_MFMA, 2)
-  MF_BATCH_CASE(MF_BF16_MFMA, 0) MF_BATCH_CASE(MF_BF16_MFMA, 1) MF_BATCH_CASE(MF_BF16_MFMA, 2)
+  MF_BATCH_CASE(MF_FP32, 0) MF_BATCH_CASE(MF_FP32, 1) MF_BATCH_CASE(MF_FP32, 2)
+  MF_BATCH_CASE(MF_BF16, 0) MF_BATCH_CASE(MF_BF16, 1) MF_BATCH_CASE(MF_BF16, 2)
 #undef MF_BATCH_CASE
   return 0;
 }
@@ -371,7 +371,7 @@ bool apply_mixed_supported(int p, int q, int cfg) {
 }
 
 int choose_cfg_mixed(int np, int nq, int nvec, int prec) {
-  if (prec == MF_FP32_MFMA) {
+  if (prec == MF_FP32) {
     // FP32: the vector shapes measured fastest (p = 6: 0.42 vs 0.50 ms for the
     // matrix-core shape at nvec 64; p = 8: 0.42 vs 0.61 ms): 16 columns, one per
     // thread, where the workgroup fits, else 8; 8 for narrow multivectors.

@@ -220,7 +220,7 @@ double cell_factor(const double L[9], const double h[3], double mu, double G6[6]
 template <int P>
 hipError_t launch_apply_box_map_p(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 hipError_t launch_apply_box_map(const Operator& op, const ApplyLaunch& a, hipStream_t s);
-// The same with FP32 cell arrays (MF_FP32_MFMA on a refined operator).
+// The same with FP32 cell arrays (MF_FP32 on a refined operator).
 template <int P>
 hipError_t launch_apply_box_map32_p(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 hipError_t launch_apply_box_map32(const Operator& op, const ApplyLaunch& a, hipStream_t s);

@@ -73,7 +73,7 @@ __device__ __forceinline__ short to_bf16(float f) {
 template <int NOUT, int NIN, int PREC>
 struct ARegs;
 template <int NOUT, int NIN>
-struct ARegs<NOUT, NIN, MF_FP32_MFMA> {
+struct ARegs<NOUT, NIN, MF_FP32> {
   static constexpr int G = (NOUT + 3) / 4;
   float a[G][NIN];
   __device__ __forceinline__ void load(const ATable<NOUT, NIN>& t, int r4) {
@@ -84,7 +84,7 @@ struct ARegs<NOUT, NIN, MF_FP32_MFMA> {
   }
 };
 template <int NOUT, int NIN>
-struct ARegs<NOUT, NIN, MF_BF16_MFMA> {
+struct ARegs<NOUT, NIN, MF_BF16> {
   static constexpr int G = (NOUT + 3) / 4;
   static constexpr int KC = (NIN + 3) / 4;
   v4s a[G][KC];
@@ -104,7 +104,7 @@ struct ARegs<NOUT, NIN, MF_BF16_MFMA> {
 // out[r][o] = sum_k M(o, k) in[r][k] for the R pencils of this lane, on the
 // matrix cores.
 template <int NOUT, int NIN, int R>
-__device__ __forceinline__ void mfma_mv(const ARegs<NOUT, NIN, MF_FP32_MFMA>& A,
+__device__ __forceinline__ void mfma_mv(const ARegs<NOUT, NIN, MF_FP32>& A,
                                         const float (&in)[R][NIN], float (&out)[R][NOUT]) {
   constexpr int G = (NOUT + 3) / 4;
   v4f acc[R][G];
@@ -125,7 +125,7 @@ __device__ __forceinline__ void mfma_mv(const ARegs<NOUT, NIN, MF_FP32_MFMA>& A,
     for (int o = 0; o < NOUT; ++o) out[r][o] = acc[r][o / 4][o % 4];
 }
 template <int NOUT, int NIN, int R>
-__device__ __forceinline__ void mfma_mv(const ARegs<NOUT, NIN, MF_BF16_MFMA>& A,
+__device__ __forceinline__ void mfma_mv(const ARegs<NOUT, NIN, MF_BF16>& A,
                                         const float (&in)[R][NIN], float (&out)[R][NOUT]) {
   constexpr int G = (NOUT + 3) / 4, KC = (NIN + 3) / 4;
   v4s b[R][KC];

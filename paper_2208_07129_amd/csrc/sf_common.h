@@ -479,7 +479,7 @@ constexpr BoxCfg batch_kind_shape(int prec, int np, int nq) {
     if (c.NT > 1024) c.NT = 1024;
     return c;
   }
-  if (prec == MF_FP32_MFMA) {  // the FP32 vector shapes, as the single apply's default
+  if (prec == MF_FP32) {  // the FP32 vector shapes, as the single apply's default
     const BoxCfg c = vec32_cfg(np, nq, 6);
     return c.B > 0 ? c : vec32_cfg(np, nq, 5);
   }

@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libmfmv.so")
 
 MF_OK, MF_ERR_ARG, MF_ERR_UNSUPPORTED, MF_ERR_OOM, MF_ERR_HIP = 0, -1, -2, -3, -4
 MF_BC_NONE, MF_BC_DIRICHLET0, MF_BC_PERIODIC = 0, 1, 2
-MF_FP64, MF_FP32_MFMA, MF_BF16_MFMA = 0, 1, 2
-PRECISIONS = {"fp64": MF_FP64, "fp32": MF_FP32_MFMA, "bf16": MF_BF16_MFMA}
+MF_FP64, MF_FP32, MF_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": MF_FP64, "fp32": MF_FP32, "bf16": MF_BF16}
 BOX_CFGS, MIXED_CFGS, BATCH_CFGS = 13, 7, 6
 BOX_MFMA_CFGS = (10,)  # FP64 matrix-core shape (q = p + 1 <= 8)
 MIXED_MFMA_CFGS = 4  # mixed shapes 0..3 are matrix-core kernels; 4..6 are FP32 vector kernels

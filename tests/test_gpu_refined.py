@@ -294,7 +294,7 @@ def test_grid_calls_refuse_refined_operator():
     out = torch.zeros_like(buf)
     assert L.mf_cheb_step(op._h, p, p, None, out.data_ptr(), 2, 2, 1.0, 0.0, 0.0,
                           None) == mfmv.MF_ERR_UNSUPPORTED
-    assert L.mf_apply(op._h, p, out.data_ptr(), 2, 2, 2, mfmv.MF_BF16_MFMA,
+    assert L.mf_apply(op._h, p, out.data_ptr(), 2, 2, 2, mfmv.MF_BF16,
                       None) == mfmv.MF_ERR_UNSUPPORTED
     assert L.mf_apply_constrained(op._h, p, p, 2, 2, 2, None) == mfmv.MF_ERR_ARG  # overlap
     nv = (ctypes.c_int * 1)(2)
