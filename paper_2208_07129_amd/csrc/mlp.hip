@@ -40,17 +40,25 @@ constexpr int kTile = 64, kKStep = 32, kPad = 40;  // LDS rows of 80 bytes
 // C (M x N) = op(A) (M x K) * op(B) (K x N).  A: row-major M x K (lda), or,
 // with TA, stored K x M.  B: row-major K x N (ldb), or, with TB, stored N x K.
 // M, N, K multiples of 8 (8-element, 16-byte staging chunks).  blockIdx.z
-// takes the K range [z kchunk, (z+1) kchunk).  blockIdx.x enumerates the
-// output tiles with the M tile fastest: the few workgroups that share an N
-// slice of B (the long batch operand) run together and read it from HBM once.
+// takes the K range [z kchunk, (z+1) kchunk).  Output tiles are numbered with
+// the M tile fastest, and workgroup b takes tile (b mod 8) c + b / 8 (c =
+// gridDim.x / 8): consecutive workgroups go to different XCDs, so this gives
+// each XCD a contiguous range of tiles and the few tiles that share an N slice
+// of B (the long batch operand) run on one XCD, which reads that slice from
+// HBM once into its L2.
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256)
 gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A, int64_t lda,
                  const uint16_t* __restrict__ B, int64_t ldb, int kchunk, GemmEpi ep) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[kTile][kPad];  // [m][k]
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile][kPad];  // [n][k]
+  // two LDS buffers: step s is staged into buffer s mod 2 while its global
+  // loads for step s + 1 are already in flight (one barrier per step)
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][kTile][kPad];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kTile][kPad];  // [n][k]
   const int mtiles = (M + kTile - 1) / kTile;
-  const int m0 = (int)(blockIdx.x % mtiles) * kTile, n0 = (int)(blockIdx.x / mtiles) * kTile;
+  const int64_t tiles = (int64_t)mtiles * ((N + kTile - 1) / kTile);
+  const int64_t lt = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+  if (lt >= tiles) return;  // the few padding workgroups of the last XCD range
+  const int m0 = (int)(lt % mtiles) * kTile, n0 = (int)(lt / mtiles) * kTile;
   const int kb = blockIdx.z * kchunk;
   const int ke = min(K, kb + kchunk);
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -61,55 +69,70 @@ gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A, int64_t ld
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = kb; k0 < ke; k0 += kKStep) {
-    const uint4 zero = {0u, 0u, 0u, 0u};
-    if constexpr (!TA) {
-      const int m = t >> 2, kk = (t & 3) * 8;
-      uint4 v = zero;
-      if (m0 + m < M && k0 + kk < ke)
-        v = *reinterpret_cast<const uint4*>(A + (int64_t)(m0 + m) * lda + k0 + kk);
-      *reinterpret_cast<uint4*>(&As[m][kk]) = v;
-    } else {
-      const int kk = t >> 3, m = (t & 7) * 8;
-      uint4 v = zero;
-      if (k0 + kk < ke && m0 + m < M)
-        v = *reinterpret_cast<const uint4*>(A + (int64_t)(k0 + kk) * lda + m0 + m);
-      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) As[m + i][kk] = e[i];
+  // This thread's 16-byte staging chunk of each operand.  A transposed operand
+  // is transposed while stored (eight 2-byte stores); the lanes of a
+  // wavefront then span the 32 k rows, so those stores fall on 32 banks.
+  // Loads read clamped (valid) addresses and a select zeroes what lies
+  // outside the operand, so no load sits behind a branch.
+  const uint4 zero = {0u, 0u, 0u, 0u};
+  const int a_kk = TA ? (t & 31) : (t & 3) * 8, a_m = TA ? (t >> 5) * 8 : (t >> 2);
+  const int b_kk = TB ? (t & 3) * 8 : (t & 31), b_n = TB ? (t >> 2) : (t >> 5) * 8;
+  uint4 va, vb;
+  auto gload = [&](int k0) {
+    {
+      const int kk = k0 + a_kk, m = m0 + a_m;
+      const bool ok = kk < ke && m < M;
+      const int kc = ok ? kk : kb, mc = ok ? m : m0;
+      const uint4 v = TA ? *reinterpret_cast<const uint4*>(A + (int64_t)kc * lda + mc)
+                         : *reinterpret_cast<const uint4*>(A + (int64_t)mc * lda + kc);
+      va = ok ? v : zero;
     }
-    if constexpr (TB) {  // (not in the blocked layout)
-      const int n = t >> 2, kk = (t & 3) * 8;
-      uint4 v = zero;
-      if (n0 + n < N && k0 + kk < ke)
-        v = *reinterpret_cast<const uint4*>(B + (int64_t)(n0 + n) * ldb + k0 + kk);
-      *reinterpret_cast<uint4*>(&Bs[n][kk]) = v;
-    } else {
-      const int kk = t >> 3, n = (t & 7) * 8;
-      uint4 v = zero;
-      if (k0 + kk < ke && n0 + n < N) {
-        const int nn = n0 + n;  // 8 columns inside one block (kb multiple of 8)
-        const int64_t off = ep.kb > 0 ? (int64_t)(nn / ep.kb) * ldb + (int64_t)(k0 + kk) * ep.kb + nn % ep.kb
-                                      : (int64_t)(k0 + kk) * ldb + nn;
-        v = *reinterpret_cast<const uint4*>(B + off);
-      }
-      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) Bs[n + i][kk] = e[i];
+    {
+      const int kk = k0 + b_kk, nn = n0 + b_n;
+      const bool ok = kk < ke && nn < N;
+      const int kc = ok ? kk : kb, nc = ok ? nn : n0;
+      int64_t off;
+      if constexpr (TB) off = (int64_t)nc * ldb + kc;
+      else  // 8 columns inside one block (kb multiple of 8)
+        off = ep.kb > 0 ? (int64_t)(nc / ep.kb) * ldb + (int64_t)kc * ep.kb + nc % ep.kb
+                        : (int64_t)kc * ldb + nc;
+      const uint4 v = *reinterpret_cast<const uint4*>(B + off);
+      vb = ok ? v : zero;
     }
+  };
+  auto lstore = [&](int buf) {
+    if constexpr (TA) {
+      const uint16_t* e = reinterpret_cast<const uint16_t*>(&va);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) As[buf][a_m + i][a_kk] = e[i];
+    } else {
+      *reinterpret_cast<uint4*>(&As[buf][a_m][a_kk]) = va;
+    }
+    if constexpr (TB) {
+      *reinterpret_cast<uint4*>(&Bs[buf][b_n][b_kk]) = vb;
+    } else {
+      const uint16_t* e = reinterpret_cast<const uint16_t*>(&vb);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[buf][b_n + i][b_kk] = e[i];
+    }
+  };
+  gload(kb);
+  for (int k0 = kb, step = 0; k0 < ke; k0 += kKStep, ++step) {
+    const int buf = step & 1;
+    lstore(buf);
     __syncthreads();
+    if (k0 + kKStep < ke) gload(k0 + kKStep);
     bf16x8 a[2], b[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + (lane & 15)][(lane >> 4) * 8]);
-      b[i] = *reinterpret_cast<const bf16x8*>(&Bs[wn + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+      a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+      b[i] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + i * 16 + (lane & 15)][(lane >> 4) * 8]);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
   }
 
   // D layout of the 16 x 16 tile: lane -> column lane % 16, rows 4 (lane / 16) + r
@@ -606,7 +629,8 @@ hipError_t launch_gemm_bf16(int M, int N, int K, bool ta, bool tb, const uint16_
   if (kchunk <= 0 || kchunk > K) kchunk = K;
   kchunk = (kchunk + kKStep - 1) / kKStep * kKStep;
   const int kz = (K + kchunk - 1) / kchunk;
-  dim3 grid((unsigned)(((int64_t)N + kTile - 1) / kTile * ((M + kTile - 1) / kTile)), 1, kz);
+  const int64_t tiles = ((int64_t)N + kTile - 1) / kTile * ((M + kTile - 1) / kTile);
+  dim3 grid((unsigned)((tiles + kXcds - 1) / kXcds * kXcds), 1, kz);
   if (!ta && !tb)
     hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, kchunk, ep);
   else if (ta && !tb)
