@@ -63,8 +63,12 @@ typedef enum {
 typedef enum {
     MF_FP64 = 0,  /* all arithmetic in FP64 */
     MF_FP32 = 1,  /* contractions in FP32 (vector or matrix-core shapes), FP64 assembly */
-    MF_BF16 = 2   /* contractions on the matrix cores with BF16 operands, FP32 accumulation,
+    MF_BF16 = 2,  /* contractions on the matrix cores with BF16 operands, FP32 accumulation,
                      FP64 assembly */
+    /* the same two precisions under their names in the original interface
+       description (FP32 runs the vector shapes unless a matrix-core shape is set) */
+    MF_FP32_MFMA = MF_FP32,
+    MF_BF16_MFMA = MF_BF16
 } mf_precision;
 
 /* Structured hexahedral box mesh: n[d] cells per direction on [lo, hi], then
@@ -146,6 +150,14 @@ int mf_operator_info(const mf_operator* op, int64_t* ndofs, int64_t* ncells, int
  * Diagnostic: it lets a caller find the first and last cells of each XCD's
  * range.  Errors: MF_ERR_ARG (NULL), MF_ERR_UNSUPPORTED (refined operator). */
 int mf_cell_order(const mf_operator* op, int32_t* order);
+
+/* Measured FP64 issue rate for the roofline (the analogue of rating kernels
+ * against the machine's peak, Sec. 4): `blocks` workgroups of 256 threads,
+ * each thread running `iters` rounds of 8 independent FP64 FMA chains (16
+ * flops per thread and round, no memory traffic), then writing one double to
+ * out[blocks * 256] (device, caller-owned).  Time it with events; flops =
+ * blocks * 256 * iters * 16.  Errors: MF_ERR_ARG, MF_ERR_HIP. */
+int mf_fma_probe(int blocks, int64_t iters, double* out, void* stream);
 
 /* Deterministic assembly on (on != 0) or off for mf_apply / mf_apply_add of a
  * box-mesh operator.  The paper's GPU kernel adds the cell contributions to

@@ -323,6 +323,14 @@ int mf_cell_order(const mf_operator* handle, int32_t* order) {
   return MF_OK;
 }
 
+int mf_fma_probe(int blocks, int64_t iters, double* out, void* stream) {
+  if (!out) return fail(MF_ERR_ARG, "out is NULL");
+  if (blocks < 1 || iters < 1) return fail(MF_ERR_ARG, "need blocks, iters >= 1");
+  hipError_t err = launch_fma_probe(blocks, iters, out, static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "FMA probe launch");
+  return MF_OK;
+}
+
 int mf_set_deterministic(mf_operator* handle, int on) {
   if (!handle) return fail(MF_ERR_ARG, "operator is NULL");
   Operator* op = reinterpret_cast<Operator*>(handle);

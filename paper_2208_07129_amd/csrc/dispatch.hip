@@ -29,6 +29,24 @@ __global__ void fill_pattern_kernel(double* __restrict__ X, int64_t n) {
   }
 }
 
+// FP64 FMA issue-rate probe: every thread runs `iters` rounds of 8
+// independent FMA chains (no loads), then writes their sum so nothing is
+// dropped.  8 iters x 2 flops per thread and round.
+__global__ void __launch_bounds__(256) fma_probe_kernel(int64_t iters, double seed, double* out) {
+  double v[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) v[c] = seed + c + threadIdx.x * 1e-3;
+  const double a = 0.999999, b = 1e-7;
+#pragma unroll 4
+  for (int64_t i = 0; i < iters; ++i)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = fma(v[c], a, b);
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) s += v[c];
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 // One workgroup per node line (gy, gz) of the Nx x Ny x Nz grid.  A line on a
 // cell-face plane (gy or gz a multiple of p) is zeroed whole; otherwise only the
 // rows gx = 0, p, 2p, ... are.  Each wavefront takes rows, lanes take columns,
@@ -474,6 +492,11 @@ hipError_t launch_zero_rows(double* Y, int64_t nrows, int ncols, int64_t ld, hip
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(zero_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, Y, nrows, ncols, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_fma_probe(int blocks, int64_t iters, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(fma_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, s, iters, 1.0, out);
   return hipGetLastError();
 }
 

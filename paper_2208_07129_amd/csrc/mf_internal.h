@@ -229,6 +229,7 @@ hipError_t launch_apply_box_map32(const Operator& op, const ApplyLaunch& a, hipS
 hipError_t launch_apply_f64(const Operator& op, const ApplyLaunch& a, hipStream_t s);
 // X[i] := a fixed pseudo-random value in [-1, 1) for i < n (tuner input).
 hipError_t launch_fill_pattern(double* X, int64_t n, hipStream_t s);
+hipError_t launch_fma_probe(int blocks, int64_t iters, double* out, hipStream_t s);
 // Forget (destroy) the library's cached batches of mf_apply_batched that
 // reference this operator; called when the operator is destroyed.
 void batch_cache_forget(const Operator* op);

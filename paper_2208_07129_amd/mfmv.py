@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmfmv.so")
 MF_OK, MF_ERR_ARG, MF_ERR_UNSUPPORTED, MF_ERR_OOM, MF_ERR_HIP = 0, -1, -2, -3, -4
 MF_BC_NONE, MF_BC_DIRICHLET0, MF_BC_PERIODIC = 0, 1, 2
 MF_FP64, MF_FP32, MF_BF16 = 0, 1, 2
+MF_FP32_MFMA, MF_BF16_MFMA = MF_FP32, MF_BF16  # names of the original interface description
 PRECISIONS = {"fp64": MF_FP64, "fp32": MF_FP32, "bf16": MF_BF16}
 BOX_CFGS, MIXED_CFGS, BATCH_CFGS = 13, 7, 6
 BOX_MFMA_CFGS = (10,)  # FP64 matrix-core shape (q = p + 1 <= 8)
@@ -31,7 +32,7 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_apply_add", "mf_zero", "mf_set_launch", "mf_set_launch_mixed", "mf_timing",
            "mf_timing_read", "mf_timing_samples", "mf_batch_create", "mf_batch_destroy", "mf_batch_set_launch",
            "mf_batch_apply", "mf_batch_capture", "mf_batch_replay", "mf_batch_info",
-           "mf_tune", "mf_tune_info", "mf_set_deterministic", "mf_batch_tune", "mf_apply_batched",
+           "mf_tune", "mf_tune_info", "mf_set_deterministic", "mf_fma_probe", "mf_batch_tune", "mf_apply_batched",
            "mf_last_error",
            # include/mfsolve.h
            "mf_diagonal", "mf_block_gram", "mf_block_gram_noalloc", "mf_block_gram_work",
@@ -90,6 +91,7 @@ def lib() -> ctypes.CDLL:
                                      ctypes.POINTER(I), ctypes.POINTER(I)]),
             "mf_cell_order": (I, [P, P]),
             "mf_set_deterministic": (I, [P, I]),
+            "mf_fma_probe": (I, [I, I64, P, P]),
             "mf_apply": (I, [P, P, P, I, I64, I64, I, P]),
             "mf_apply_add": (I, [P, P, P, I, I64, I64, I, P]),
             "mf_zero": (I, [P, I64, I, I64, P]),
