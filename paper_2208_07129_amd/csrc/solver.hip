@@ -154,17 +154,25 @@ __global__ void jacobi_kernel(int64_t n, int k, const double* __restrict__ diag,
 
 // X := G^{-1} S (G k x k SPD, S k x m).  One workgroup per panel of 64
 // right-hand-side columns; each forms the lower Cholesky factor of G in LDS
-// itself (packed storage, row r at r(r+1)/2; right-looking, one column per
-// step: the scaled column is also copied to a contiguous vector so the rank-1
-// update reads it without bank conflicts, and its rows are dealt to the 16
-// wavefronts without any integer division), then runs the two triangular
-// solves on its panel: 16 adjacent lanes own a column, split each row's dot
-// product and combine it with lane shuffles, so a column needs no barrier
-// (its lanes are in one wavefront).  The factorisation is repeated per panel
-// rather than shared through global memory: it costs less than a second
+// itself (packed storage, row r at r(r+1)/2) by the blocked right-looking
+// method with blocks of kSpdBlock columns: one wavefront factors the diagonal
+// block (its lanes in step, no workgroup barrier), one thread per row below
+// solves that row's block of the panel, then all threads apply the rank-8
+// update to the trailing triangle, the panel rows staged contiguously in LDS
+// so a row's eight factors are two 32-byte reads (three barriers per block,
+// against three per column for the unblocked method).  Then it runs the two
+// triangular solves on its panel: 16 adjacent lanes own a column, split each
+// row's dot product and combine it with lane shuffles, so a column needs no
+// barrier (its lanes are in one wavefront).  The factorisation is repeated per
+// panel rather than shared through global memory: it costs less than a second
 // launch.
-constexpr int kSpdMaxK = 128, kSpdThreads = 1024, kSpdPanel = 64;
+constexpr int kSpdMaxK = 128, kSpdThreads = 1024, kSpdPanel = 64, kSpdBlock = 8;
 constexpr int kSpdLanes = kSpdThreads / kSpdPanel;  // lanes per right-hand side
+// The panel is held column by column (a column's k values contiguous, so the 16
+// lanes of one dot product read neighbouring words) with a column stride of
+// 144 doubles (= 128 mod 256 bytes): two columns read by one half-wavefront
+// fall on different halves of the banks.
+constexpr int kSpdPS = kSpdMaxK + 16;
 __device__ inline int tri(int r, int c) { return r * (r + 1) / 2 + c; }
 __global__ void __launch_bounds__(kSpdThreads)
 spd_solve_kernel(int k, int m, const double* __restrict__ G, const double* __restrict__ S,
@@ -172,38 +180,68 @@ spd_solve_kernel(int k, int m, const double* __restrict__ G, const double* __res
   extern __shared__ double sh[];
   const int ntri = (k * (k + 1) / 2 + 1) / 2 * 2;    // 16-byte aligned sizes
   double* L = sh;                                   // k(k+1)/2
-  double* Lc = L + ntri;                            // k: the current column
-  double* Dinv = Lc + kSpdMaxK;                     // k: 1 / L(r, r)
-  double* P = Dinv + kSpdMaxK;                      // k x kSpdPanel
+  double* Lc = L + ntri;                            // k x kSpdBlock: the current panel rows
+  double* Dinv = Lc + kSpdMaxK * kSpdBlock;         // k: 1 / L(r, r)
+  double* P = Dinv + kSpdMaxK;                      // kSpdPanel columns of kSpdPS
   __shared__ int bad;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nwaves = kSpdThreads / 64;
   for (int r = wave; r < k; r += nwaves)
     for (int c = lane; c <= r; c += 64) L[tri(r, c)] = G[(int64_t)r * k + c];
   if (t == 0) bad = 0;
   __syncthreads();
-  for (int c = 0; c < k; ++c) {
-    if (t == 0) {
-      const double d = L[tri(c, c)];
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = c + 1;
-      } else {
-        L[tri(c, c)] = sqrt(d);
-        Dinv[c] = 1.0 / sqrt(d);
+  for (int cb = 0; cb < k; cb += kSpdBlock) {
+    const int nb = k - cb < kSpdBlock ? k - cb : kSpdBlock;
+    if (wave == 0) {  // the diagonal block, unblocked, lanes 0 .. nb-1 own its rows
+      for (int j = 0; j < nb; ++j) {
+        const double d = L[tri(cb + j, cb + j)];
+        if (!(d > 0.0) || !isfinite(d)) {
+          if (lane == 0) bad = cb + j + 1;
+          break;  // uniform across the wavefront
+        }
+        const double sd = sqrt(d), id = 1.0 / sd;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == j) {
+          L[tri(cb + j, cb + j)] = sd;
+          Dinv[cb + j] = id;
+        }
+        if (lane > j && lane < nb) L[tri(cb + lane, cb + j)] *= id;
+        __builtin_amdgcn_wave_barrier();
+        if (lane > j && lane < nb) {
+          const double lj = L[tri(cb + lane, cb + j)];
+          for (int i = j + 1; i <= lane; ++i)
+            L[tri(cb + lane, cb + i)] -= lj * L[tri(cb + i, cb + j)];
+        }
+        __builtin_amdgcn_wave_barrier();
       }
     }
     __syncthreads();
     if (bad) break;
-    const double ic = Dinv[c];
-    for (int r = c + 1 + t; r < k; r += kSpdThreads) {
-      const double v = L[tri(r, c)] * ic;
-      L[tri(r, c)] = v;
-      Lc[r] = v;
+    // rows below the block: L(r, block) := L(r, block) D^{-T}, staged in Lc
+    for (int r = cb + nb + t; r < k; r += kSpdThreads) {
+      double v[kSpdBlock];
+#pragma unroll
+      for (int j = 0; j < kSpdBlock; ++j) {
+        if (j >= nb) break;
+        double a = L[tri(r, cb + j)];
+        for (int i = 0; i < j; ++i) a -= v[i] * L[tri(cb + j, cb + i)];
+        v[j] = a * Dinv[cb + j];
+        L[tri(r, cb + j)] = v[j];
+        Lc[r * kSpdBlock + j] = v[j];
+      }
     }
     __syncthreads();
-    for (int r = c + 1 + wave; r < k; r += nwaves) {
-      const double lr = Lc[r];
+    // trailing update: L(r, s) -= sum_j L(r, cb + j) L(s, cb + j), s <= r, both past the block
+    for (int r = cb + nb + wave; r < k; r += nwaves) {
+      double lr[kSpdBlock];
+#pragma unroll
+      for (int j = 0; j < kSpdBlock; ++j) lr[j] = j < nb ? Lc[r * kSpdBlock + j] : 0.0;
       double* row = L + tri(r, 0);
-      for (int s2 = c + 1 + lane; s2 <= r; s2 += 64) row[s2] -= lr * Lc[s2];
+      for (int s2 = cb + nb + lane; s2 <= r; s2 += 64) {
+        double acc = row[s2];
+#pragma unroll
+        for (int j = 0; j < kSpdBlock; ++j) acc -= lr[j] * Lc[s2 * kSpdBlock + j];
+        row[s2] = acc;
+      }
     }
     __syncthreads();
   }
@@ -213,31 +251,31 @@ spd_solve_kernel(int k, int m, const double* __restrict__ G, const double* __res
   const int j0 = blockIdx.x * kSpdPanel;
   const int w = m - j0 < kSpdPanel ? m - j0 : kSpdPanel;
   for (int r = wave; r < k; r += nwaves)
-    P[r * kSpdPanel + lane] = lane < w ? S[(int64_t)r * m + j0 + lane] : 0.0;
+    P[lane * kSpdPS + r] = lane < w ? S[(int64_t)r * m + j0 + lane] : 0.0;
   __syncthreads();
   // L y = s (rows in order)
   for (int r = 0; r < k; ++r) {
     double acc = 0.0;
     const double* lrow = L + tri(r, 0);
-    for (int c = q; c < r; c += kSpdLanes) acc = fma(lrow[c], P[c * kSpdPanel + jc], acc);
+    for (int c = q; c < r; c += kSpdLanes) acc = fma(lrow[c], P[jc * kSpdPS + c], acc);
 #pragma unroll
     for (int off = 1; off < kSpdLanes; off *= 2) acc += __shfl_xor(acc, off);
-    if (q == 0) P[r * kSpdPanel + jc] = (P[r * kSpdPanel + jc] - acc) * Dinv[r];
+    if (q == 0) P[jc * kSpdPS + r] = (P[jc * kSpdPS + r] - acc) * Dinv[r];
     __builtin_amdgcn_wave_barrier();
   }
   // L^T x = y (rows in reverse)
   for (int r = k - 1; r >= 0; --r) {
     double acc = 0.0;
     for (int c = r + 1 + q; c < k; c += kSpdLanes)
-      acc = fma(L[tri(c, r)], P[c * kSpdPanel + jc], acc);
+      acc = fma(L[tri(c, r)], P[jc * kSpdPS + c], acc);
 #pragma unroll
     for (int off = 1; off < kSpdLanes; off *= 2) acc += __shfl_xor(acc, off);
-    if (q == 0) P[r * kSpdPanel + jc] = (P[r * kSpdPanel + jc] - acc) * Dinv[r];
+    if (q == 0) P[jc * kSpdPS + r] = (P[jc * kSpdPS + r] - acc) * Dinv[r];
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   for (int r = wave; r < k; r += nwaves)
-    if (lane < w) X[(int64_t)r * m + j0 + lane] = P[r * kSpdPanel + lane];
+    if (lane < w) X[(int64_t)r * m + j0 + lane] = P[lane * kSpdPS + r];
 }
 
 // Symmetric eigen-decomposition of a k x k block (k <= kEigMaxK) by the
@@ -453,8 +491,8 @@ hipError_t launch_sym_eig(int k, const double* A, int64_t lda, double* w, double
 
 hipError_t launch_spd_solve(int k, int m, const double* G, const double* S, double* X, int* status,
                             hipStream_t s) {
-  const size_t lds = ((size_t)(k * (k + 1) / 2 + 1) / 2 * 2 + 2 * (size_t)kSpdMaxK +
-                      (size_t)k * kSpdPanel) * sizeof(double);
+  const size_t lds = ((size_t)(k * (k + 1) / 2 + 1) / 2 * 2 + (size_t)kSpdMaxK * kSpdBlock +
+                      (size_t)kSpdMaxK + (size_t)kSpdPS * kSpdPanel) * sizeof(double);
   if (lds > 64 * 1024) {
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(spd_solve_kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -113,7 +113,7 @@ def test_dense_blocks_reject_bad_arguments():
     assert e.value.status == mfmv.MF_ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("k,m", [(1, 1), (5, 3), (64, 64), (128, 128), (97, 200)])
+@pytest.mark.parametrize("k,m", [(1, 1), (5, 3), (13, 7), (64, 64), (128, 128), (97, 200)])
 def test_spd_solve(k, m):
     rng = np.random.default_rng(k * 1000 + m)
     Z = rng.standard_normal((k, k))
@@ -123,11 +123,13 @@ def test_spd_solve(k, m):
     assert int(st.item()) == 0
     ref = np.linalg.solve(G, S)
     np.testing.assert_allclose(X.cpu().numpy(), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
-    # an indefinite block reports the first bad pivot
-    Gi = G.copy()
-    Gi[2 % k, 2 % k] = -1.0 - np.abs(G).sum()
-    _, st = mfmv.spd_solve(T(Gi), T(S))
-    assert int(st.item()) == (2 % k) + 1
+    # an indefinite block reports the first bad pivot (in the first and in a later
+    # 8-column block of the blocked factorisation)
+    for piv in sorted({2 % k, 11 % k}):
+        Gi = G.copy()
+        Gi[piv, piv] = -1.0 - np.abs(G).sum()
+        _, st = mfmv.spd_solve(T(Gi), T(S))
+        assert int(st.item()) == piv + 1
 
 
 def small_problem(bc, p=3, n=(3, 3, 3), k=6, seed=7):
