@@ -132,3 +132,43 @@ def test_adam_three_steps_match_the_hand_derivation():
         w, m1, m2 = mo.adam_step(w, np.array(grad), m1, m2, g["lr"], g["b1"], g["b2"], g["eps"], t)
         np.testing.assert_allclose(w, [g["w_after"][0][t - 1], g["w_after"][1][t - 1]],
                                    rtol=2e-7, atol=0)
+
+
+@pytest.mark.parametrize("bc", [W.BC_NONE, W.BC_DIRICHLET0, W.BC_PERIODIC])
+def test_linear_map_is_definite_when_identity_plus_skip_is(bc):
+    """The deployed preconditioner z = D^-1 r + sum_e Q_e^T W^1/2 D^-1/2 S D^-1/2 W^1/2 Q_e r,
+    built densely on the free rows from the oracle's gather and assembly: with the
+    partition of unity it equals D^-1/2 [sum_e Q_e^T W_e^1/2 (I + S) W_e^1/2 Q_e] D^-1/2, so
+    the smallest eigenvalue of D^1/2 M D^1/2 is at least that of I + S (equality for
+    S = s I, where the map is (1 + s) D^-1; s < -1 makes it negative definite).  The
+    condition is sufficient, which is what the eigenvalue floor of the skip block relies
+    on (an S with a direction below -1 that no cell excites, e.g. on constrained local
+    nodes, can still give a definite M)."""
+    mesh = W.BoxMesh(n=(2, 3, 2), bc=bc)
+    p = 2
+    cons = constrained_mask(mesh, p)
+    free = ~cons
+    F = (p + 1) ** 3
+    rng = np.random.default_rng(31)
+    d = rng.uniform(0.5, 2.0, cons.size)
+    Q, _ = np.linalg.qr(rng.standard_normal((F, F)))
+
+    def dense(S):
+        n = cons.size
+        eye = np.eye(n)[:, free]
+        X, _, rho = mo.cell_inputs(mesh, p, eye, pou_sqrt=True, dscale=d)
+        U = X * rho[:, None]                      # the linear map needs no scale
+        Z = mo.cell_assemble(mesh, p, U @ S.T, np.ones(len(rho)), eye.shape[1], R=eye,
+                             diag=d, pou_sqrt=True, dscale=d)
+        M = Z[free]
+        dh = np.sqrt(d[free])
+        return dh[:, None] * M * dh[None, :]
+
+    for lam in (np.linspace(-0.9, 3.0, F), np.linspace(-0.5, 0.5, F)):
+        S = (Q * lam) @ Q.T
+        B = dense(S)
+        np.testing.assert_allclose(B, B.T, rtol=0, atol=1e-12)
+        assert np.linalg.eigvalsh(B).min() >= (1.0 + lam.min()) - 1e-10
+    for s in (-1.5, -0.7, 0.4):
+        ev = np.linalg.eigvalsh(dense(s * np.eye(F)))
+        np.testing.assert_allclose(ev, 1.0 + s, rtol=0, atol=1e-12)
