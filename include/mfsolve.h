@@ -63,6 +63,24 @@ int mf_block_gram_noalloc(int64_t n, int k, const double* A, int64_t lda, const 
  * columns (at most 512 k^2), or -1 for n < 0 or k < 1. */
 int64_t mf_block_gram_work(int64_t n, int k);
 
+/* The two Gram blocks of a block-CG step that share their left operand,
+ * C1 := alpha * A^T B1 + beta * C1 and C2 := alpha * A^T B2 + beta * C2 (P^T (A P)
+ * and P^T R, the blocks of the step length alpha = (P^T A P)^{-1} P^T R), in
+ * one pass over A: each row of A is fetched from HBM once for both products
+ * (one workgroup of eight wavefronts per row chunk, four per product).  Each
+ * product is formed and reduced as by mf_block_gram (fixed summation order);
+ * `work` is a caller-owned device array of at least mf_block_gram2_work(n, k)
+ * doubles, contents undefined afterwards.  C1, C2 and work must not overlap
+ * each other or A, B1, B2.  Errors: MF_ERR_ARG (NULL, n < 0, k < 1, ld < k,
+ * short or overlapping arrays), MF_ERR_HIP. */
+int mf_block_gram2(int64_t n, int k, const double* A, int64_t lda, const double* B1, int64_t ldb1,
+                   const double* B2, int64_t ldb2, double alpha, double beta, double* C1,
+                   int ldc1, double* C2, int ldc2, double* work, int64_t work_len, void* stream);
+
+/* Number of doubles the work array of mf_block_gram2 needs for n rows and k
+ * columns (at most 512 k^2), or -1 for n < 0 or k < 1. */
+int64_t mf_block_gram2_work(int64_t n, int k);
+
 /* Y := beta * Y + alpha * P M, with P an n x kp multivector (ldp), M a kp x k
  * row-major device matrix (ldm >= k) and Y n x k (ldy).  Y must not overlap P
  * or M.  Block-CG updates X += P alpha, R -= (A P) alpha, Z += P beta.  An
@@ -70,6 +88,25 @@ int64_t mf_block_gram_work(int64_t n, int k);
  * Errors: MF_ERR_ARG (also for overlap), MF_ERR_HIP. */
 int mf_block_update(int64_t n, int k, int kp, double alpha, const double* P, int64_t ldp,
                     const double* M, int ldm, double beta, double* Y, int64_t ldy, void* stream);
+
+/* mf_block_update that also returns the squared 2-norms of the columns of the
+ * updated Y: norms2[j] := sum_i Y[i*ldy + j]^2 (block CG: R -= (A P) alpha
+ * together with the residual norms of its convergence test, without a second
+ * pass over R).  The norms are summed from the values as stored, per
+ * workgroup into `work` (a caller-owned device array of at least
+ * mf_block_update_norms_work(n, k) doubles, contents undefined afterwards),
+ * then over the workgroups in a fixed order.  `norms2` is a device array of k
+ * doubles; n = 0 gives zeros.  Y, norms2 and work must not overlap each
+ * other or P, M.  Errors: MF_ERR_ARG (NULL, bad sizes, short or overlapping
+ * arrays), MF_ERR_UNSUPPORTED (k > 128 or kp > 128: use mf_block_update and
+ * mf_col_dots), MF_ERR_HIP. */
+int mf_block_update_norms(int64_t n, int k, int kp, double alpha, const double* P, int64_t ldp,
+                          const double* M, int ldm, double beta, double* Y, int64_t ldy,
+                          double* norms2, double* work, int64_t work_len, void* stream);
+
+/* Number of doubles the work array of mf_block_update_norms needs for n rows
+ * and k columns, or -1 for n < 0 or k < 1. */
+int64_t mf_block_update_norms_work(int64_t n, int k);
 
 /* out[j] := sum_i A[i*lda + j] B[i*ldb + j] for j < k: column dot products
  * (residual norms with A = B, the descent check z_j^T r_j of the learned

@@ -76,7 +76,12 @@ def block_pcg(op: mfmv.Operator, B, X, precond: Callable, tol: float, maxit: int
     alpha = torch.empty(k, k, dtype=torch.float64, device=dev)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
     rn2 = torch.empty(k, dtype=torch.float64, device=dev)
-    work = mfmv.block_gram_work(n, k, dev)
+    # one work array serves the paired Gram blocks and the single ones (it is at
+    # least as long); the residual norms come with the update of R where the
+    # fused kernel takes the block width
+    work = mfmv.block_gram2_work(n, k, dev)
+    fused_norms = k <= 128
+    nwork = mfmv.block_update_norms_work(n, k, dev) if fused_norms else None
 
     it, converged, breakdown = 0, False, False
     active = precond
@@ -98,14 +103,19 @@ def block_pcg(op: mfmv.Operator, B, X, precond: Callable, tol: float, maxit: int
     descent_or_fallback(P)
     while it < maxit:
         op.apply(P, Q, precision=precision)
-        mfmv.block_gram(P, Q, G, work=work)           # P^T A P
-        mfmv.block_gram(P, R, S, work=work)           # P^T R
+        mfmv.block_gram2(P, Q, R, G, S, work=work)    # P^T A P and P^T R, one pass over P
         mfmv.spd_solve(G, S, alpha, st)
         mfmv.block_update(P, alpha, X, 1.0, 1.0)      # X += P alpha
-        mfmv.block_update(Q, alpha, R, -1.0, 1.0)     # R -= Q alpha
+        check = it + 1 == maxit or (it + 1) % check_every == 0
+        if fused_norms:                               # R -= Q alpha, with ||r_j||^2
+            mfmv.block_update_norms(Q, alpha, R, rn2, -1.0, 1.0, work=nwork)
+        else:
+            mfmv.block_update(Q, alpha, R, -1.0, 1.0)
+            if check:
+                mfmv.col_norms2(R, rn2)
         it += 1
-        if it % check_every == 0 or it == maxit:
-            rel = float((np.sqrt(mfmv.col_norms2(R, rn2).cpu().numpy()) / bn).max())  # host sync
+        if check:
+            rel = float((np.sqrt(rn2.cpu().numpy()) / bn).max())  # host sync
             if stats is not None:
                 stats.history.append(rel)
             if int(st.item()) != 0 or not math.isfinite(rel):

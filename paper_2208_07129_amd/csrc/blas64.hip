@@ -25,11 +25,21 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
 // Partial Gram blocks: workgroup (b, t) sums the rows [b R, min(n, (b+1) R)) of
 // A^T B into work[b][i k + j] for the 128 x 128 block t of C (i, j < k).
 // Wave w covers rows 64 (w / 2) .. and columns 64 (w % 2) .. of the block as
-// 4 x 4 tiles of 16 x 16.
-__global__ void __launch_bounds__(kGramThreads)
+// 4 x 4 tiles of 16 x 16.  TWO: two Gram blocks with the same left operand,
+// A^T B into work and A^T B2 into work2, by eight wavefronts (the last four on
+// B2): each row of A is fetched from HBM once for both, the second wavefront
+// that reads it finding it in the caches.
+template <bool TWO>
+__global__ void __launch_bounds__(TWO ? 2 * kGramThreads : kGramThreads)
 gram_partial_kernel(int64_t n, int k, const double* __restrict__ A, int64_t lda,
-                    const double* __restrict__ B, int64_t ldb, int64_t rows, double* __restrict__ work) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                    const double* __restrict__ B1, int64_t ldb1, const double* __restrict__ B2,
+                    int64_t ldb2, int64_t rows, double* __restrict__ work1,
+                    double* __restrict__ work2) {
+  const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) & 3;
+  const bool second = TWO && threadIdx.x >= kGramThreads;
+  const double* __restrict__ B = second ? B2 : B1;
+  const int64_t ldb = second ? ldb2 : ldb1;
+  double* __restrict__ work = second ? work2 : work1;
   const int nbj = (k + kGramBlock - 1) / kGramBlock;
   const int bi = blockIdx.y / nbj, bj = blockIdx.y % nbj;
   const int i0 = bi * kGramBlock + (wave >> 1) * 64, j0 = bj * kGramBlock + (wave & 1) * 64;
@@ -108,11 +118,14 @@ constexpr int kUpdRowsPerWg = 1024;
 // by zero, so the whole strip is one basic block the compiler can schedule.
 // M rows kp .. kp4 - 1 (kp4 = kp rounded up to 4) are zero in LDS.  EXACT:
 // k = 16 KT, so the output columns are fixed offsets from one row pointer.
-template <int KT, bool EXACT>
+// NORMS: also the squared norms of the new Y's columns over the workgroup's
+// rows, into npart[blockIdx.x k + j] (each lane sums its rows, then the four
+// lanes of a column, then the eight wavefronts in order).
+template <int KT, bool EXACT, bool NORMS>
 __global__ void __launch_bounds__(kUpdThreads)
 update_kernel(int64_t n, int k, int kp, double alpha, const double* __restrict__ P, int64_t ldp,
               const double* __restrict__ M, int ldm, double beta, double* __restrict__ Y,
-              int64_t ldy) {
+              int64_t ldy, double* __restrict__ npart) {
   extern __shared__ double mlds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int ldl = update_ld(16 * KT);
@@ -131,6 +144,9 @@ update_kernel(int64_t n, int k, int kp, double alpha, const double* __restrict__
     col[t] = EXACT ? 16 * t + m : (cok[t] ? 16 * t + m : k - 1);
   }
   const bool use_y = beta != 0.0;
+  double sq[KT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) sq[t] = 0.0;
   const int64_t wg0 = (int64_t)blockIdx.x * kUpdRowsPerWg;
   for (int64_t r0 = wg0 + 16 * wave; r0 < wg0 + kUpdRowsPerWg && r0 < n;
        r0 += 16 * (kUpdThreads / 64)) {
@@ -181,16 +197,38 @@ update_kernel(int64_t n, int k, int kp, double alpha, const double* __restrict__
 #pragma unroll
       for (int t = 0; t < KT; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          yrow[q][16 * t] = use_y ? fma(beta, yo[t][q], alpha * acc[t][q]) : alpha * acc[t][q];
+        for (int q = 0; q < 4; ++q) {
+          const double y = use_y ? fma(beta, yo[t][q], alpha * acc[t][q]) : alpha * acc[t][q];
+          yrow[q][16 * t] = y;
+          if (NORMS) sq[t] = fma(y, y, sq[t]);
+        }
     } else {
 #pragma unroll
       for (int t = 0; t < KT; ++t)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (yok[q] && cok[t])
-            yrow[q][EXACT ? 16 * t : col[t]] =
-                use_y ? fma(beta, yo[t][q], alpha * acc[t][q]) : alpha * acc[t][q];
+          if (yok[q] && cok[t]) {
+            const double y = use_y ? fma(beta, yo[t][q], alpha * acc[t][q]) : alpha * acc[t][q];
+            yrow[q][EXACT ? 16 * t : col[t]] = y;
+            if (NORMS) sq[t] = fma(y, y, sq[t]);
+          }
+    }
+  }
+  if constexpr (NORMS) {
+    __shared__ double wsum[kUpdThreads / 64][16 * KT];
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      double v = sq[t];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (lane < 16) wsum[wave][16 * t + lane] = v;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < k; j += kUpdThreads) {
+      double v = wsum[0][j];
+#pragma unroll
+      for (int w = 1; w < kUpdThreads / 64; ++w) v += wsum[w][j];
+      npart[(int64_t)blockIdx.x * k + j] = v;
     }
   }
 }
@@ -243,6 +281,8 @@ update_wide_kernel(int64_t n, int k, int kp, double alpha, const double* __restr
 
 int64_t gram_chunks(int64_t n) { return gram_blocks(n); }
 
+int64_t update_workgroups(int64_t n) { return (n + kUpdRowsPerWg - 1) / kUpdRowsPerWg; }
+
 int64_t gram_partial_rows(int64_t n, int64_t nb) {
   int64_t rows = (n + nb - 1) / nb;
   return rows < 1 ? 1 : rows;
@@ -252,41 +292,60 @@ hipError_t launch_gram_partial(int64_t n, int k, const double* A, int64_t lda, c
                                int64_t ldb, int64_t nb, double* work, hipStream_t s) {
   const int nbk = (k + kGramBlock - 1) / kGramBlock;
   const int64_t rows = gram_partial_rows(n, nb);
-  hipLaunchKernelGGL(gram_partial_kernel, dim3((unsigned)nb, (unsigned)(nbk * nbk)),
-                     dim3(kGramThreads), 0, s, n, k, A, lda, B, ldb, rows, work);
+  hipLaunchKernelGGL(gram_partial_kernel<false>, dim3((unsigned)nb, (unsigned)(nbk * nbk)),
+                     dim3(kGramThreads), 0, s, n, k, A, lda, B, ldb, B, ldb, rows, work, work);
+  return hipGetLastError();
+}
+
+int64_t gram2_chunks(int64_t n) { return (gram_chunks(n) + 1) / 2; }
+
+hipError_t launch_gram2_partial(int64_t n, int k, const double* A, int64_t lda, const double* B1,
+                                int64_t ldb1, const double* B2, int64_t ldb2, int64_t nb,
+                                double* work1, double* work2, hipStream_t s) {
+  const int nbk = (k + kGramBlock - 1) / kGramBlock;
+  const int64_t rows = gram_partial_rows(n, nb);
+  hipLaunchKernelGGL(gram_partial_kernel<true>, dim3((unsigned)nb, (unsigned)(nbk * nbk)),
+                     dim3(2 * kGramThreads), 0, s, n, k, A, lda, B1, ldb1, B2, ldb2, rows, work1,
+                     work2);
   return hipGetLastError();
 }
 
 template <int KT>
 hipError_t launch_update_kt(int64_t n, int k, int kp, double alpha, const double* P, int64_t ldp,
                             const double* M, int ldm, double beta, double* Y, int64_t ldy,
-                            hipStream_t s) {
+                            double* npart, hipStream_t s) {
   const size_t lds = (size_t)((kp + 3) & ~3) * update_ld(16 * KT) * sizeof(double);
-  auto kern = k == 16 * KT ? update_kernel<KT, true> : update_kernel<KT, false>;
+  auto kern = k == 16 * KT ? (npart ? update_kernel<KT, true, true> : update_kernel<KT, true, false>)
+                           : (npart ? update_kernel<KT, false, true> : update_kernel<KT, false, false>);
   KernelFacts f;  // raises the dynamic LDS limit on this device
   hipError_t err = kernel_facts(reinterpret_cast<const void*>(kern), kUpdThreads, lds, f);
   if (err != hipSuccess) return err;
   const int64_t wgs = (n + kUpdRowsPerWg - 1) / kUpdRowsPerWg;
   hipLaunchKernelGGL(kern, dim3((unsigned)wgs), dim3(kUpdThreads), lds, s, n, k, kp, alpha, P, ldp,
-                     M, ldm, beta, Y, ldy);
+                     M, ldm, beta, Y, ldy, npart);
   return hipGetLastError();
+}
+
+bool update_in_lds(int k, int kp) {
+  return k <= 16 * kUpdTiles && (int64_t)((kp + 3) & ~3) * update_ld(k) <= kUpdLds;
 }
 
 hipError_t launch_block_update(int64_t n, int k, int kp, double alpha, const double* P,
                                int64_t ldp, const double* M, int ldm, double beta, double* Y,
-                               int64_t ldy, hipStream_t s) {
-  if (k <= 16 * kUpdTiles && (int64_t)((kp + 3) & ~3) * update_ld(k) <= kUpdLds) {
+                               int64_t ldy, hipStream_t s, double* npart) {
+  if (update_in_lds(k, kp)) {
     switch ((k + 15) / 16) {
-      case 1: return launch_update_kt<1>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, s);
-      case 2: return launch_update_kt<2>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, s);
-      case 3: return launch_update_kt<3>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, s);
-      case 4: return launch_update_kt<4>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, s);
-      case 5: return launch_update_kt<5>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, s);
-      case 6: return launch_update_kt<6>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, s);
-      case 7: return launch_update_kt<7>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, s);
-      default: return launch_update_kt<8>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, s);
+      case 1: return launch_update_kt<1>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, npart, s);
+      case 2: return launch_update_kt<2>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, npart, s);
+      case 3: return launch_update_kt<3>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, npart, s);
+      case 4: return launch_update_kt<4>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, npart, s);
+      case 5: return launch_update_kt<5>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, npart, s);
+      case 6: return launch_update_kt<6>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, npart, s);
+      case 7: return launch_update_kt<7>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, npart, s);
+      default: return launch_update_kt<8>(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, npart, s);
     }
   }
+  if (npart) return hipErrorInvalidValue;  // column norms only on the LDS path
   const int64_t wgs = (n + 63) / 64;
   const int nj = (k + 16 * kUpdTiles - 1) / (16 * kUpdTiles);
   hipLaunchKernelGGL(update_wide_kernel, dim3((unsigned)wgs, (unsigned)nj), dim3(kUpdWideThreads),

@@ -60,6 +60,38 @@ int mf_block_gram(int64_t n, int k, const double* A, int64_t lda, const double* 
   return MF_OK;
 }
 
+int64_t mf_block_gram2_work(int64_t n, int k) {
+  if (n < 0 || k < 1) return -1;
+  return 2 * gram2_chunks(n) * (int64_t)k * k;
+}
+
+int mf_block_gram2(int64_t n, int k, const double* A, int64_t lda, const double* B1, int64_t ldb1,
+                   const double* B2, int64_t ldb2, double alpha, double beta, double* C1,
+                   int ldc1, double* C2, int ldc2, double* work, int64_t work_len, void* stream) {
+  if (!C1 || !C2 || !work || (n > 0 && (!A || !B1 || !B2)))
+    return fail(MF_ERR_ARG, "A, B1, B2, C1, C2 and work must be non-NULL");
+  if (n < 0 || k < 1 || lda < k || ldb1 < k || ldb2 < k || ldc1 < k || ldc2 < k)
+    return fail(MF_ERR_ARG, "need n >= 0, k >= 1, lda, ldb1, ldb2, ldc1, ldc2 >= k");
+  if (work_len < mf_block_gram2_work(n, k))
+    return fail(MF_ERR_ARG, "work_len < mf_block_gram2_work");
+  const size_t c1s = span_bytes(k, k, ldc1), c2s = span_bytes(k, k, ldc2);
+  const size_t ws = (size_t)work_len * sizeof(double);
+  const size_t as = span_bytes(n, k, lda), b1s = span_bytes(n, k, ldb1), b2s = span_bytes(n, k, ldb2);
+  if (overlaps(C1, c1s, C2, c2s) || overlaps(C1, c1s, A, as) || overlaps(C1, c1s, B1, b1s) ||
+      overlaps(C1, c1s, B2, b2s) || overlaps(C2, c2s, A, as) || overlaps(C2, c2s, B1, b1s) ||
+      overlaps(C2, c2s, B2, b2s) || overlaps(work, ws, C1, c1s) || overlaps(work, ws, C2, c2s) ||
+      overlaps(work, ws, A, as) || overlaps(work, ws, B1, b1s) || overlaps(work, ws, B2, b2s))
+    return fail(MF_ERR_ARG, "C1, C2 or work overlaps an operand or each other");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const int64_t nb = gram2_chunks(n);
+  double* work2 = work + nb * (int64_t)k * k;
+  hipError_t err = launch_gram2_partial(n, k, A, lda, B1, ldb1, B2, ldb2, nb, work, work2, hs);
+  if (err == hipSuccess) err = launch_gram_reduce(k, (int)nb, work, alpha, beta, C1, ldc1, hs);
+  if (err == hipSuccess) err = launch_gram_reduce(k, (int)nb, work2, alpha, beta, C2, ldc2, hs);
+  if (err != hipSuccess) return hip_fail(err, "Gram kernel launch");
+  return MF_OK;
+}
+
 int mf_block_update(int64_t n, int k, int kp, double alpha, const double* P, int64_t ldp,
                     const double* M, int ldm, double beta, double* Y, int64_t ldy, void* stream) {
   if (n == 0) return (!M || k < 1 || kp < 1) ? fail(MF_ERR_ARG, "M non-NULL, k, kp >= 1") : MF_OK;
@@ -71,6 +103,41 @@ int mf_block_update(int64_t n, int k, int kp, double alpha, const double* P, int
     return fail(MF_ERR_ARG, "Y overlaps P or M");
   hipError_t err = launch_block_update(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy,
                                        static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "block update kernel launch");
+  return MF_OK;
+}
+
+int64_t mf_block_update_norms_work(int64_t n, int k) {
+  if (n < 0 || k < 1) return -1;
+  const int64_t w = update_workgroups(n);
+  return (w < 1 ? 1 : w) * (int64_t)k;
+}
+
+int mf_block_update_norms(int64_t n, int k, int kp, double alpha, const double* P, int64_t ldp,
+                          const double* M, int ldm, double beta, double* Y, int64_t ldy,
+                          double* norms2, double* work, int64_t work_len, void* stream) {
+  if (!M || !norms2 || !work || (n > 0 && (!P || !Y)))
+    return fail(MF_ERR_ARG, "P, M, Y, norms2 and work must be non-NULL");
+  if (n < 0 || k < 1 || kp < 1 || ldp < kp || ldm < k || ldy < k)
+    return fail(MF_ERR_ARG, "need n >= 0, k, kp >= 1, ldp >= kp, ldm >= k, ldy >= k");
+  if (k > 128 || kp > 128 || !update_in_lds(k, kp))
+    return fail(MF_ERR_UNSUPPORTED, "mf_block_update_norms takes k <= 128 and kp <= 128");
+  if (work_len < mf_block_update_norms_work(n, k))
+    return fail(MF_ERR_ARG, "work_len < mf_block_update_norms_work");
+  const size_t ys = span_bytes(n, k, ldy), ns = (size_t)k * sizeof(double);
+  const size_t ws = (size_t)work_len * sizeof(double);
+  if (overlaps(Y, ys, P, span_bytes(n, kp, ldp)) || overlaps(Y, ys, M, span_bytes(kp, k, ldm)) ||
+      overlaps(norms2, ns, Y, ys) || overlaps(norms2, ns, P, span_bytes(n, kp, ldp)) ||
+      overlaps(norms2, ns, M, span_bytes(kp, k, ldm)) || overlaps(work, ws, Y, ys) ||
+      overlaps(work, ws, P, span_bytes(n, kp, ldp)) || overlaps(work, ws, M, span_bytes(kp, k, ldm)) ||
+      overlaps(work, ws, norms2, ns))
+    return fail(MF_ERR_ARG, "Y, norms2 or work overlaps an operand or each other");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const int64_t nw = update_workgroups(n);
+  hipError_t err = hipSuccess;
+  if (n > 0)
+    err = launch_block_update(n, k, kp, alpha, P, ldp, M, ldm, beta, Y, ldy, hs, work);
+  if (err == hipSuccess) err = launch_chunk_sum(1, k, (int)nw, work, 1.0, 0.0, norms2, k, hs);
   if (err != hipSuccess) return hip_fail(err, "block update kernel launch");
   return MF_OK;
 }

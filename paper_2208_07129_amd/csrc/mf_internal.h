@@ -270,11 +270,26 @@ int64_t gram_chunks(int64_t n);
 int64_t gram_partial_rows(int64_t n, int64_t nb);
 hipError_t launch_gram_partial(int64_t n, int k, const double* A, int64_t lda, const double* B,
                                int64_t ldb, int64_t nb, double* work, hipStream_t s);
+// Two Gram blocks with the same left operand, A^T B1 and A^T B2, in one pass
+// over A (gram2_chunks(n) row chunks, each a workgroup of eight wavefronts).
+int64_t gram2_chunks(int64_t n);
+hipError_t launch_gram2_partial(int64_t n, int k, const double* A, int64_t lda, const double* B1,
+                                int64_t ldb1, const double* B2, int64_t ldb2, int64_t nb,
+                                double* work1, double* work2, hipStream_t s);
+// npart non-NULL: also the per-workgroup squared column norms of the new Y,
+// npart[w k + j] for the update_workgroups(n) workgroups (only where
+// update_in_lds(k, kp); hipErrorInvalidValue otherwise).
 hipError_t launch_block_update(int64_t n, int k, int kp, double alpha, const double* P,
                                int64_t ldp, const double* M, int ldm, double beta, double* Y,
-                               int64_t ldy, hipStream_t s);
+                               int64_t ldy, hipStream_t s, double* npart = nullptr);
+bool update_in_lds(int k, int kp);
+int64_t update_workgroups(int64_t n);
 hipError_t launch_gram_reduce(int k, int nb, const double* work, double alpha, double beta,
                               double* C, int ldc, hipStream_t s);
+// C[i / cols][i % cols] := alpha sum_b work[b rows cols + i] + beta C[..]
+// (i < rows cols), summed in a fixed order (solver.hip).
+hipError_t launch_chunk_sum(int rows, int cols, int nb, const double* work, double alpha,
+                            double beta, double* C, int ldc, hipStream_t s);
 hipError_t launch_jacobi(int64_t n, int k, const double* diag, const double* R, int64_t ldr,
                          double* Z, int64_t ldz, hipStream_t s);
 hipError_t launch_spd_solve(int k, int m, const double* G, const double* S, double* X, int* status,

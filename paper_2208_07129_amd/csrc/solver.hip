@@ -116,14 +116,32 @@ col_dots_kernel(int64_t n, int k, const double* __restrict__ A, int64_t lda,
 // The work array holds up to 512 chunks of at least 2048 rows.
 constexpr int kGramRows = 2048, kGramMaxBlocks = 512;
 
-// C[i][j] := alpha sum_b work[b][i][j] + beta C[i][j] (beta = 0: C not read).
-__global__ void gram_reduce_kernel(int k, int nb, const double* __restrict__ work, double alpha,
-                                   double beta, double* __restrict__ C, int ldc) {
-  const int kk = k * k;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kk; i += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += work[(int64_t)b * kk + i];
-    double* c = C + (int64_t)(i / k) * ldc + i % k;
+// C[i / cols][i % cols] := alpha sum_b work[b len + i] + beta C[..] for the
+// len = rows cols elements (beta = 0: C not read).  A workgroup takes 64
+// consecutive elements; its eight wavefronts sum the chunks b = w, w + 8, ...
+// (coalesced 512-byte rows of the partials), then wavefront 0 adds the eight
+// sums in wavefront order: a fixed order, so the result does not depend on
+// timing.  One thread per element summing all chunks left most CUs idle at
+// k = 128 (64 workgroups).
+constexpr int kRedThreads = 512, kRedElems = 64, kRedGroups = kRedThreads / kRedElems;
+__global__ void __launch_bounds__(kRedThreads)
+chunk_sum_kernel(int rows, int cols, int nb, const double* __restrict__ work, double alpha,
+                 double beta, double* __restrict__ C, int ldc) {
+  __shared__ double part[kRedThreads];
+  const int64_t len = (int64_t)rows * cols;
+  const int e = blockIdx.x * kRedElems + (threadIdx.x & (kRedElems - 1));
+  const int g = threadIdx.x / kRedElems;
+  double s = 0.0;
+  if (e < len) {
+    const double* w = work + e;
+#pragma unroll 8
+    for (int b = g; b < nb; b += kRedGroups) s += w[(int64_t)b * len];
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (g == 0 && e < len) {
+    for (int h = 1; h < kRedGroups; ++h) s += part[h * kRedElems + threadIdx.x];
+    double* c = C + (int64_t)(e / cols) * ldc + e % cols;
     *c = beta == 0.0 ? alpha * s : fma(beta, *c, alpha * s);
   }
 }
@@ -447,9 +465,14 @@ hipError_t launch_col_dots(int64_t n, int k, const double* A, int64_t lda, const
 
 hipError_t launch_gram_reduce(int k, int nb, const double* work, double alpha, double beta,
                               double* C, int ldc, hipStream_t s) {
-  const int kk = k * k;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((kk + 255) / 256), dim3(256), 0, s, k, nb, work, alpha,
-                     beta, C, ldc);
+  return launch_chunk_sum(k, k, nb, work, alpha, beta, C, ldc, s);
+}
+
+hipError_t launch_chunk_sum(int rows, int cols, int nb, const double* work, double alpha,
+                            double beta, double* C, int ldc, hipStream_t s) {
+  const int64_t len = (int64_t)rows * cols;
+  hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)((len + kRedElems - 1) / kRedElems)),
+                     dim3(kRedThreads), 0, s, rows, cols, nb, work, alpha, beta, C, ldc);
   return hipGetLastError();
 }
 

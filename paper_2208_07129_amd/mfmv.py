@@ -36,7 +36,8 @@ EXPORTS = ("mf_num_dofs", "mf_num_cells", "mf_quad_points", "mf_constrained_mask
            "mf_last_error",
            # include/mfsolve.h
            "mf_diagonal", "mf_block_gram", "mf_block_gram_noalloc", "mf_block_gram_work",
-           "mf_block_update", "mf_col_dots",
+           "mf_block_gram2", "mf_block_gram2_work", "mf_block_update", "mf_block_update_norms",
+           "mf_block_update_norms_work", "mf_col_dots",
            "mf_axpby",
            "mf_jacobi", "mf_spd_solve",
            # include/mfmlp.h
@@ -117,6 +118,10 @@ def lib() -> ctypes.CDLL:
             "mf_block_gram_work": (I64, [I64, I]),
             "mf_block_gram_noalloc": (I, [I64, I, P, I64, P, I64, D, D, P, I, P]),
             "mf_block_update": (I, [I64, I, I, D, P, I64, P, I, D, P, I64, P]),
+            "mf_block_gram2": (I, [I64, I, P, I64, P, I64, P, I64, D, D, P, I, P, I, P, I64, P]),
+            "mf_block_gram2_work": (I64, [I64, I]),
+            "mf_block_update_norms": (I, [I64, I, I, D, P, I64, P, I, D, P, I64, P, P, I64, P]),
+            "mf_block_update_norms_work": (I64, [I64, I]),
             "mf_col_dots": (I, [I64, I, P, I64, P, I64, P, P]),
             "mf_axpby": (I, [I64, I, D, P, I64, D, P, I64, P]),
             "mf_jacobi": (I, [I64, I, P, P, I64, P, I64, P]),
@@ -559,6 +564,66 @@ def block_update(P, M, Y, alpha: float = 1.0, beta: float = 1.0, stream=None):
     _check(lib().mf_block_update(n, k, kp, float(alpha), pp, ldp, pm, ldm, float(beta), py, ldy,
                                  _stream_ptr(stream)))
     return Y
+
+
+def block_gram2_work(n: int, k: int, device="cuda"):
+    """A work array for block_gram2 on n x k multivectors."""
+    import torch
+    return torch.empty(max(1, lib().mf_block_gram2_work(n, k)), dtype=torch.float64, device=device)
+
+
+def block_gram2(A, B1, B2, C1=None, C2=None, alpha: float = 1.0, beta: float = 0.0, work=None,
+                stream=None):
+    """(C1, C2) := (alpha A^T B1 + beta C1, alpha A^T B2 + beta C2) in one pass over A;
+    `work` from block_gram2_work (allocated here when not given)."""
+    import torch
+    pa, n, k, lda = _mv(A, "A")
+    pb1, n1, k1, ldb1 = _mv(B1, "B1")
+    pb2, n2, k2, ldb2 = _mv(B2, "B2")
+    if (n1, k1) != (n, k) or (n2, k2) != (n, k):
+        raise ValueError("A, B1 and B2 must have the same shape")
+    if C1 is None:
+        C1 = torch.empty(k, k, dtype=torch.float64, device=A.device)
+    if C2 is None:
+        C2 = torch.empty(k, k, dtype=torch.float64, device=A.device)
+    pc1, r1, c1, ldc1 = _mv(C1, "C1")
+    pc2, r2, c2, ldc2 = _mv(C2, "C2")
+    if (r1, c1) != (k, k) or (r2, c2) != (k, k):
+        raise ValueError("C1 and C2 must be k x k")
+    if work is None:
+        work = block_gram2_work(n, k, A.device)
+    _check(lib().mf_block_gram2(n, k, pa, lda, pb1, ldb1, pb2, ldb2, float(alpha), float(beta),
+                                pc1, ldc1, pc2, ldc2, work.data_ptr(), work.numel(),
+                                _stream_ptr(stream)))
+    return C1, C2
+
+
+def block_update_norms_work(n: int, k: int, device="cuda"):
+    """A work array for block_update_norms on n x k multivectors."""
+    import torch
+    return torch.empty(max(1, lib().mf_block_update_norms_work(n, k)), dtype=torch.float64,
+                       device=device)
+
+
+def block_update_norms(P, M, Y, norms2=None, alpha: float = 1.0, beta: float = 1.0, work=None,
+                       stream=None):
+    """Y := beta Y + alpha P M and norms2[j] := ||Y[:, j]||^2 of the new Y (k, kp <= 128)."""
+    import torch
+    pp, n, kp, ldp = _mv(P, "P")
+    pm, km, k, ldm = _mv(M, "M")
+    py, ny, ky, ldy = _mv(Y, "Y")
+    if km != kp or ny != n or ky != k:
+        raise ValueError("shape mismatch in block_update_norms")
+    if norms2 is None:
+        norms2 = torch.empty(k, dtype=torch.float64, device=Y.device)
+    if norms2.numel() != k or norms2.dtype != torch.float64:
+        raise ValueError("norms2 must hold k float64 values")
+    if work is None:
+        work = block_update_norms_work(n, k, Y.device)
+    _check(lib().mf_block_update_norms(n, k, kp, float(alpha), pp, ldp, pm, ldm, float(beta), py,
+                                       ldy, norms2.data_ptr(), work.data_ptr(), work.numel(),
+                                       _stream_ptr(stream)))
+    return Y, norms2
 
 
 def col_dots(A, B, out=None, stream=None):

@@ -3,8 +3,9 @@ block-CG solve.
 
 - mf_diagonal against the oracle's assembled element-matrix diagonal (1e-12,
   every boundary condition, box and sheared cells).
-- Gram, block update, column dots, axpby, Jacobi and the small SPD solve
-  against numpy in FP64 on seeded inputs with ragged sizes.
+- Gram, paired Gram, block update (also with the column norms of its
+  result), column dots, axpby, Jacobi and the small SPD solve against numpy
+  in FP64 on seeded inputs with ragged sizes.
 - Block PCG (Jacobi) on small meshes: the true FP64 residual reaches 1e-10 in
   every column and the solution agrees with a dense direct solve of the
   oracle's assembled matrix to within cond(A) * 1e-10; the mixed-precision
@@ -74,6 +75,89 @@ def test_dense_blocks_match_numpy(n, k, kp):
     np.testing.assert_array_equal(mfmv.axpby(3.0, T(A), 0.0, Yn).cpu().numpy(), 3.0 * A)
     diag = rng.uniform(0.5, 2.0, n)
     np.testing.assert_array_equal(mfmv.jacobi(T(diag), T(A)).cpu().numpy(), A / diag[:, None])
+
+
+@pytest.mark.parametrize("n,k,kp", [(0, 3, 3), (1, 1, 1), (997, 7, 5), (5000, 64, 64),
+                                    (3001, 128, 128), (2049, 300, 17), (600011, 128, 120),
+                                    (70001, 100, 33)])
+def test_paired_gram_and_update_with_norms_match_numpy(n, k, kp):
+    """block_gram2 (A^T B1 and A^T B2 in one pass over A) and block_update_norms
+    (Y := beta Y + alpha P M with the squared column norms of the new Y) against
+    numpy in FP64, over ragged row counts (partial chunks, partial 16-row strips),
+    k not a multiple of 16 and k above one 128-column block."""
+    rng = np.random.default_rng(7 * n + k)
+    A = rng.standard_normal((n, k))
+    B1 = rng.standard_normal((n, k))
+    B2 = rng.uniform(-3, 1, (n, k))
+    C10 = rng.standard_normal((k, k))
+    C20 = rng.standard_normal((k, k))
+    tol = 1e-12 * max(1, n) ** 0.5
+    C1 = torch.full((k, k), float("nan"), dtype=torch.float64, device=dev())
+    C1, C2 = mfmv.block_gram2(T(A), T(B1), T(B2), C1, T(C20), alpha=-0.75, beta=0.0)
+    np.testing.assert_allclose(C1.cpu().numpy(), -0.75 * A.T @ B1, rtol=0, atol=tol * 3)
+    np.testing.assert_allclose(C2.cpu().numpy(), -0.75 * A.T @ B2, rtol=0, atol=tol * 3)
+    C1, C2 = mfmv.block_gram2(T(A), T(B1), T(B2), T(C10), T(C20), alpha=0.5, beta=2.0)
+    np.testing.assert_allclose(C1.cpu().numpy(), 0.5 * A.T @ B1 + 2.0 * C10, rtol=0, atol=tol * 3)
+    np.testing.assert_allclose(C2.cpu().numpy(), 0.5 * A.T @ B2 + 2.0 * C20, rtol=0, atol=tol * 3)
+    P = rng.standard_normal((n, kp))
+    M = rng.standard_normal((kp, k))
+    Y = rng.standard_normal((n, k))
+    if k > 128 or kp > 128:
+        with pytest.raises(mfmv.MfError) as e:
+            mfmv.block_update_norms(T(P), T(M), T(Y))
+        assert e.value.status == mfmv.MF_ERR_UNSUPPORTED
+        return
+    for alpha, beta in ((-1.0, 1.0), (2.5, 0.0)):
+        Yn = T(Y) if beta != 0.0 else torch.full((n, k), float("nan"), dtype=torch.float64,
+                                                 device=dev())
+        nrm = torch.full((k,), float("nan"), dtype=torch.float64, device=dev())
+        Yd, nrm = mfmv.block_update_norms(T(P), T(M), Yn, nrm, alpha=alpha, beta=beta)
+        Yd, nrm = Yd.cpu().numpy(), nrm.cpu().numpy()
+        ref = beta * Y + alpha * P @ M
+        np.testing.assert_allclose(Yd, ref, rtol=0, atol=1e-12 * kp * 10)
+        # the norms are those of the values stored, to the rounding of a sum of n squares
+        np.testing.assert_allclose(nrm, (Yd * Yd).sum(axis=0), rtol=1e-13 * max(1, n) ** 0.5,
+                                   atol=0)
+        np.testing.assert_allclose(nrm, (ref * ref).sum(axis=0), rtol=1e-12, atol=0)
+        # the same update as block_update, bit for bit
+        Yb = mfmv.block_update(T(P), T(M), T(Y), alpha=alpha, beta=beta).cpu().numpy()
+        np.testing.assert_array_equal(Yd, Yb)
+
+
+def test_paired_gram_and_update_norms_strided_and_repeatable():
+    """Column blocks of wider arrays (ld > k), results repeat bit for bit (fixed
+    summation order), and bad arguments are refused."""
+    rng = np.random.default_rng(21)
+    n, k = 123457, 80
+    Wh = rng.standard_normal((n, 3 * k + 5))
+    Wd = T(Wh)
+    A, B1, B2 = Wd[:, 0:k], Wd[:, k + 2:2 * k + 2], Wd[:, 2 * k + 5:3 * k + 5]
+    C1, C2 = mfmv.block_gram2(A, B1, B2)
+    D1, D2 = mfmv.block_gram2(A, B1, B2)
+    assert torch.equal(C1, D1) and torch.equal(C2, D2)
+    np.testing.assert_allclose(C1.cpu().numpy(), Wh[:, 0:k].T @ Wh[:, k + 2:2 * k + 2], rtol=0,
+                               atol=1e-11 * n ** 0.5)
+    np.testing.assert_allclose(C2.cpu().numpy(), Wh[:, 0:k].T @ Wh[:, 2 * k + 5:3 * k + 5],
+                               rtol=0, atol=1e-11 * n ** 0.5)
+    M = T(rng.standard_normal((k, k)))
+    Yw = torch.zeros((n, k + 7), dtype=torch.float64, device=dev())
+    Yv = Yw[:, 3:k + 3]
+    _, n1 = mfmv.block_update_norms(A, M, Yv, alpha=1.0, beta=0.0)
+    _, n2 = mfmv.block_update_norms(A, M, Yv, alpha=1.0, beta=0.0)
+    assert torch.equal(n1, n2)
+    ref = Wh[:, 0:k] @ M.cpu().numpy()
+    np.testing.assert_allclose(Yv.cpu().numpy(), ref, rtol=0, atol=1e-12 * k * 10)
+    np.testing.assert_allclose(n1.cpu().numpy(), (ref * ref).sum(axis=0), rtol=1e-12)
+    assert float(Yw[:, :3].abs().max()) == 0.0 and float(Yw[:, k + 3:].abs().max()) == 0.0
+    with pytest.raises(mfmv.MfError) as e:      # C1 overlapping B1
+        mfmv.block_gram2(A, B1, B2, C1=Wd[:k, k + 2:2 * k + 2])
+    assert e.value.status == mfmv.MF_ERR_ARG
+    with pytest.raises(mfmv.MfError) as e:      # work too short
+        mfmv.block_gram2(A, B1, B2, work=torch.empty(10, dtype=torch.float64, device=dev()))
+    assert e.value.status == mfmv.MF_ERR_ARG
+    with pytest.raises(mfmv.MfError) as e:      # Y overlapping P
+        mfmv.block_update_norms(A, M, Wd[:, 1:k + 1])
+    assert e.value.status == mfmv.MF_ERR_ARG
 
 
 def test_dense_blocks_strided_and_symmetric():
