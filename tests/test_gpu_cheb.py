@@ -36,9 +36,13 @@ def colrel(Y, R):
     return float((np.linalg.norm(Y - R, axis=0) / np.linalg.norm(R, axis=0)).max())
 
 
+# the periodic and free one-cell directions check that every face row has one
+# owner cell when Out is not Xp (a periodic cell meets itself; the last cell of
+# a free direction owns its far face)
 CASES = [(2, 3, (3, 2, 2), W.BC_DIRICHLET0, 5), (3, 4, (2, 2, 3), W.BC_PERIODIC, 8),
          (4, 5, (2, 2, 2), W.BC_NONE, 3), (6, 7, (2, 2, 2), W.BC_PERIODIC, 16),
-         (8, 9, (2, 1, 1), W.BC_DIRICHLET0, 9)]
+         (8, 9, (2, 1, 1), W.BC_DIRICHLET0, 9), (3, 4, (1, 2, 3), W.BC_PERIODIC, 7),
+         (5, 6, (3, 1, 2), W.BC_NONE, 11), (6, 7, (1, 1, 1), W.BC_PERIODIC, 8)]
 
 
 @pytest.mark.parametrize("p,q,n,bc,nvec", CASES)
@@ -99,7 +103,11 @@ def test_standard_form_is_symmetric():
     assert abs(uSv - vSu) <= 1e-12 * float(S.abs().max()) * op.ndofs ** 0.5
 
 
-def test_config2_cheb_step_sampled_rows_in_place():
+@pytest.mark.parametrize("in_place", [True, False])
+def test_config2_cheb_step_sampled_rows(in_place):
+    """Config 2 at full size, in place (face rows initialised to b Y + c Xp) and
+    into a separate array (face rows zeroed, b Y + c Xp added by the owner cell),
+    on sampled rows that include cell-face rows."""
     w = W.config2()
     op = mfmv.Operator.from_workload(w)
     orc = fo.Oracle(w.mesh, w.p, w.q, w.mu, w.V, w.sigma)
@@ -109,9 +117,13 @@ def test_config2_cheb_step_sampled_rows_in_place():
     Y = w.X()
     Xp = np.random.default_rng(7).uniform(-1, 1, Y.shape)
     a, b, c = 0.9, 0.25, -0.5
-    Out = T(Xp)
-    mfmv.cheb_step(op, D, T(Y), Out, Out, a, b, c)
-    rows = np.random.default_rng(11).choice(orc.ndofs, 12, replace=False)
+    Out = T(Xp) if in_place else torch.full((orc.ndofs, Y.shape[1]), float("nan"),
+                                            dtype=torch.float64, device=dev())
+    mfmv.cheb_step(op, D, T(Y), Out if in_place else T(Xp), Out, a, b, c)
+    N = 16 * w.p   # periodic 16^3 cells: a node on a cell face has a coordinate index divisible by p
+    face = [int(i + N * (j + N * k)) for i, j, k in ((0, 3, 5), (6, 12, 1), (6, 12, 90),
+                                                   (12, 18, 24), (95, 0, 7))]
+    rows = np.concatenate([np.random.default_rng(11).choice(orc.ndofs, 12, replace=False), face])
     Dr = 1.0 / np.sqrt(m_ref)
     ref = a * Dr[rows, None] * orc.apply_rows(Dr[:, None] * Y, rows) + b * Y[rows] + c * Xp[rows]
     got = Out[torch.from_numpy(rows).to(dev())].cpu().numpy()
