@@ -364,6 +364,8 @@ def solve_leg(a) -> dict:
         print(json.dumps({name: out["solves"][name]}), file=sys.stderr, flush=True)
         del X
     out["judge_deploys_network"] = use_net
+    out["deployed_map"] = ("the trained network's symmetric linear part S with its eigenvalue floor "
+                           "(ReLU branch and biases not used in the solve)")
     best = min(out["solves"].values(), key=lambda r: r["seconds"] if r["converged"] else 1e30)
     out["value"] = best["seconds"]
     for prec in ("fp64", "mixed_fp32"):
