@@ -109,8 +109,8 @@ int mf_block_update_norms(int64_t n, int k, int kp, double alpha, const double* 
 int64_t mf_block_update_norms_work(int64_t n, int k);
 
 /* out[j] := sum_i A[i*lda + j] B[i*ldb + j] for j < k: column dot products
- * (residual norms with A = B, the descent check z_j^T r_j of the learned
- * preconditioner).  `out` is a device array of k doubles.  Errors:
+ * (residual norms with A = B; the z_j^T r_j of a preconditioned residual).
+ * `out` is a device array of k doubles.  Errors:
  * MF_ERR_ARG, MF_ERR_HIP. */
 int mf_col_dots(int64_t n, int k, const double* A, int64_t lda, const double* B, int64_t ldb,
                 double* out, void* stream);

@@ -86,24 +86,21 @@ def block_pcg(op: mfmv.Operator, B, X, precond: Callable, tol: float, maxit: int
     it, converged, breakdown = 0, False, False
     active = precond
 
-    def descent_or_fallback(Zb):
-        """Apply the active preconditioner to R into Zb; if it is not the fallback, a
-        direction that is not a descent direction for every column (z_j^T r_j > 0,
-        which a NaN fails too) switches the rest of the run to the fallback."""
-        nonlocal active
-        active(R, Zb)
-        if fallback is not None and active is not fallback:
-            zr = mfmv.col_dots(Zb, R, rn2).cpu().numpy()
-            if not bool(np.all(zr > 0)):
-                active = fallback
-                if stats is not None:
-                    stats.precond_switches += 1
-                active(R, Zb)
-
-    descent_or_fallback(P)
+    active(R, P)
     while it < maxit:
         op.apply(P, Q, precision=precision)
         mfmv.block_gram2(P, Q, R, G, S, work=work)    # P^T A P and P^T R, one pass over P
+        if fallback is not None and active is not fallback:
+            # Descent check on the direction about to be used: p_j^T r_j, the diagonal
+            # of S = P^T R (= z_j^T r_j, R being orthogonal to the previous block).  If
+            # it is not positive for every column (a NaN fails too), the rest of the run
+            # uses the fallback, from a restarted direction block.
+            if not bool(np.all(np.diagonal(S.cpu().numpy()) > 0)):   # host sync
+                active = fallback
+                if stats is not None:
+                    stats.precond_switches += 1
+                active(R, P)
+                continue
         mfmv.spd_solve(G, S, alpha, st)
         mfmv.block_update(P, alpha, X, 1.0, 1.0)      # X += P alpha
         check = it + 1 == maxit or (it + 1) % check_every == 0
@@ -124,7 +121,7 @@ def block_pcg(op: mfmv.Operator, B, X, precond: Callable, tol: float, maxit: int
             if rel <= tol:
                 converged = True
                 break
-        descent_or_fallback(Z)
+        active(R, Z)
         mfmv.block_gram(Q, Z, S, work=work)           # (A P)^T Z
         mfmv.spd_solve(G, S, alpha, st)               # G^{-1} (A P)^T Z
         mfmv.block_update(P, alpha, Z, -1.0, 1.0)     # Z -= P G^{-1} (AP)^T Z
