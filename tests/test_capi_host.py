@@ -96,6 +96,14 @@ def test_argument_errors_without_device_work():
     bad = mfmv.mesh_c(BoxMesh(n=(2, 2, 2), bc=7))
     assert L.mf_num_cells(ctypes.byref(bad), ctypes.byref(ctypes.c_int64())) == mfmv.MF_ERR_UNSUPPORTED
     assert L.mf_num_dofs(None, 2, ctypes.byref(ctypes.c_int64())) == mfmv.MF_ERR_ARG
+    # the largest mesh: node numbers are int32, so 2^31 nodes or more are refused
+    # before anything is allocated (1291^3 = 2^31 + 4,201,523 nodes at p = 1)
+    big = mfmv.mesh_c(BoxMesh(n=(1290, 1290, 1290)))
+    nd = ctypes.c_int64()
+    assert L.mf_num_dofs(ctypes.byref(big), 1, ctypes.byref(nd)) == mfmv.MF_OK
+    assert nd.value == 1291 ** 3 and nd.value >= 2 ** 31
+    assert L.mf_create_operator(ctypes.byref(big), 1, 2, 0.5, None, 0.0, ctypes.byref(out)) == mfmv.MF_ERR_UNSUPPORTED
+    assert b"2^31" in L.mf_last_error()
     # NaN parameters and NULL outputs
     assert L.mf_create_operator(ctypes.byref(m), 2, 3, float("nan"), None, 0.0, ctypes.byref(out)) == mfmv.MF_ERR_ARG
     assert L.mf_create_operator(ctypes.byref(m), 2, 3, 0.5, None, 0.0, None) == mfmv.MF_ERR_ARG
