@@ -47,22 +47,29 @@ __global__ void __launch_bounds__(256) fma_probe_kernel(int64_t iters, double se
   out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
-// One workgroup per node line (gy, gz) of the Nx x Ny x Nz grid.  A line on a
-// cell-face plane (gy or gz a multiple of p) is zeroed whole; otherwise only the
-// rows gx = 0, p, 2p, ... are.  Each wavefront takes rows, lanes take columns,
-// so stores are contiguous and no per-element index arithmetic is needed.
-// Rows of cell-interior nodes are skipped: the box kernel writes them.
+// Node lines (gy, gz) of the Nx x Ny x Nz grid, each taken whole by one
+// workgroup (a grid-stride loop when the grid is smaller than the line count).
+// A line on a cell-face plane (gy or gz a multiple of p) is zeroed whole;
+// otherwise only the rows gx = 0, p, 2p, ... are.  Threads form (row, column)
+// pairs, the columns of a row on cw = 2^cw_log2 consecutive lanes (the next
+// power of two >= ncols, at most 64), so narrow multivectors keep every lane
+// busy and wide ones store 64 contiguous columns at a time.  Rows of
+// cell-interior nodes are skipped: the box kernel writes them.
 __global__ void zero_shared_rows_kernel(double* __restrict__ Y, int Nx, int Ny, int p, int ncols,
-                                        int64_t ld) {
-  const int line = blockIdx.x;
-  const int gy = line % Ny, gz = line / Ny;
-  const bool full = (gy % p == 0) || (gz % p == 0);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  double* base = Y + (int64_t)line * Nx * ld;
-  const int step = full ? 1 : p;
-  for (int gx = wave * step; gx < Nx; gx += nw * step) {
-    double* row = base + (int64_t)gx * ld;
-    for (int c = lane; c < ncols; c += 64) row[c] = 0.0;
+                                        int64_t ld, int64_t lines, int cw_log2) {
+  const int cw = 1 << cw_log2;
+  const int c0 = threadIdx.x & (cw - 1);
+  const int r0 = threadIdx.x >> cw_log2, rstep = blockDim.x >> cw_log2;
+  for (int64_t line = blockIdx.x; line < lines; line += gridDim.x) {
+    const int gy = (int)(line % Ny), gz = (int)(line / Ny);
+    const bool full = (gy % p == 0) || (gz % p == 0);
+    const int step = full ? 1 : p;
+    const int nrows = full ? Nx : (Nx + p - 1) / p;
+    double* base = Y + line * Nx * ld;
+    for (int r = r0; r < nrows; r += rstep) {
+      double* row = base + (int64_t)r * step * ld;
+      for (int c = c0; c < ncols; c += cw) row[c] = 0.0;
+    }
   }
 }
 
@@ -216,9 +223,16 @@ int batched_blocks_per_cu(int prec, int bcfg) {
 hipError_t launch_zero_shared_rows(double* Y, const int64_t nodes[3], int p, int ncols, int64_t ld,
                                    hipStream_t s) {
   const int64_t lines = nodes[1] * nodes[2];
-  if (lines < 1) return hipSuccess;
-  hipLaunchKernelGGL(zero_shared_rows_kernel, dim3((unsigned)lines), dim3(256), 0, s, Y,
-                     (int)nodes[0], (int)nodes[1], p, ncols, ld);
+  if (lines < 1 || ncols < 1) return hipSuccess;
+  int cw_log2 = 0;
+  while (cw_log2 < 6 && (1 << cw_log2) < ncols) ++cw_log2;
+  // about 2048 grid elements per workgroup (some 7 KB of face rows), at least
+  // one workgroup per CU, at most one per line
+  int64_t wgs = nodes[0] * lines * ncols / 2048;
+  if (wgs < 256) wgs = 256;
+  if (wgs > lines) wgs = lines;
+  hipLaunchKernelGGL(zero_shared_rows_kernel, dim3((unsigned)wgs), dim3(256), 0, s, Y,
+                     (int)nodes[0], (int)nodes[1], p, ncols, ld, lines, cw_log2);
   return hipGetLastError();
 }
 
