@@ -34,7 +34,7 @@ def bf(a):
     return torch.from_numpy(bits).to(dev()), mo.bf16_round(a)
 
 
-@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True)])
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
 @pytest.mark.parametrize("M,N,K", [(8, 8, 8), (72, 136, 40), (256, 344, 352), (344, 200, 256)])
 def test_gemm_forms(ta, tb, M, N, K):
     rng = np.random.default_rng(M * 7 + N + K)
