@@ -110,16 +110,22 @@ condense_kernel(const ConstraintSet* __restrict__ sets, const int32_t* __restric
 }
 
 // kZeroRows rows per workgroup (a quarter per wavefront), one column per lane.
+// The wavefront's row numbers are loaded together before any store, so their
+// latency is paid once rather than once per row.
 constexpr int kZeroRows = 32;
 __device__ __forceinline__ void zero_rows_item(double* __restrict__ Y,
                                                const int32_t* __restrict__ rows, int64_t n,
                                                int ncols, int64_t ld, int64_t block) {
+  constexpr int kPer = kZeroRows / 4;
   const int wave = threadIdx.x / kCT, lane = threadIdx.x % kCT;
-  const int64_t i0 = block * kZeroRows + wave * (kZeroRows / 4);
-  for (int k = 0; k < kZeroRows / 4; ++k) {
-    const int64_t i = i0 + k;
-    if (i >= n) return;
-    double* row = Y + (int64_t)rows[i] * ld;
+  const int64_t i0 = block * kZeroRows + wave * kPer;
+  int32_t r[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) r[k] = i0 + k < n ? rows[i0 + k] : -1;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (r[k] < 0) continue;
+    double* row = Y + (int64_t)r[k] * ld;
     for (int c = lane; c < ncols; c += kCT) row[c] = 0.0;
   }
 }
